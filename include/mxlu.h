@@ -1,0 +1,180 @@
+/*
+ * mxlu.h -- C ABI of the MI355X (gfx950) dense LU solver.
+ *
+ * The operations are those of the paper's benchmarks (Sec. III-A.1: solve
+ * A x = b, A an N x N FP64 matrix, by LU factorization with partial pivoting
+ * followed by triangular solves, computed by the right-looking blocked
+ * algorithm of panel width NB with the phases PFACT, SWAP, DTRSM, DGEMM;
+ * Sec. III-A.2: the mixed-precision variant, low-precision factorization and
+ * trailing updates without pivoting, accuracy restored by FP64 iterative
+ * refinement; Sec. II-B: refinement based on GMRES).
+ *
+ * Conventions for every entry point
+ *   - Matrices are column-major with a leading dimension >= max(1, rows).
+ *   - All array arguments are DEVICE pointers (memory of the current HIP
+ *     device), owned by the caller.  The library never frees caller memory;
+ *     internal scratch is allocated stream-ordered on `stream` and released
+ *     before the call returns.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  All work is
+ *     enqueued on it.
+ *   - Return value: 0 on success; -k when the k-th argument is invalid
+ *     (checked on the host before anything is enqueued); > 0 from a
+ *     factorization when a pivot is exactly zero (see lu_factor); <= -1000 for
+ *     runtime failures (MXLU_E_*), with details in mxlu_last_error().
+ *   - Pivots: LAPACK interchange sequence, int32, 0-based: at step j row j was
+ *     swapped with row ipiv[j] >= j.  P = P_{n-1} ... P_0 and P A = L U.
+ */
+#ifndef MXLU_H
+#define MXLU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    MXLU_OK = 0,
+    MXLU_E_NODEV = -1001,    /* no HIP device visible */
+    MXLU_E_HIP = -1002,      /* a HIP runtime call failed */
+    MXLU_E_NOMEM = -1003,    /* a size overflows or an allocation failed */
+    MXLU_E_NOTCONV = -1004,  /* refinement did not reach the threshold */
+    MXLU_E_TIMEOUT = -1005,  /* a kernel's bounded wait expired (results invalid) */
+    MXLU_E_WORKSPACE = -1006 /* caller workspace too small */
+};
+
+/*
+ * lu_factor -- blocked right-looking LU with partial pivoting (Sec. III-A.1).
+ *   n      order of A (>= 0)
+ *   nb     panel width NB (1 <= nb <= 1024)
+ *   A      n x n FP64, leading dimension lda; overwritten by L (unit lower,
+ *          multipliers below the diagonal) and U (upper), as LAPACK getrf
+ *   ipiv   n int32 (device): the interchange sequence
+ * Pivot choice: the first row of largest magnitude (ties go to the smaller
+ * row index).  An exactly zero pivot column is left unscaled and the call
+ * returns its 1-based index (the first one); the factorization still
+ * completes.  Synchronises `stream` once at the end (to read that status).
+ */
+int lu_factor(int64_t n, int64_t nb, double *A, int64_t lda, int32_t *ipiv,
+              void *stream);
+
+/*
+ * lu_solve -- triangular solves with the factors of lu_factor (Sec. III-A.1).
+ *   trans = 0: solves A X = B  (apply P, L y = P b, U x = y)
+ *   trans = 1: solves A^T X = B (U^T y = b, L^T z = y, x = P^T z)
+ *   B      n x nrhs FP64, leading dimension ldb; overwritten by X
+ * Fully asynchronous on `stream`.
+ */
+int lu_solve(int64_t n, int64_t nrhs, const double *LU, int64_t lda,
+             const int32_t *ipiv, double *B, int64_t ldb, int trans,
+             void *stream);
+
+/*
+ * mxlu_schur_update_f64 -- the DGEMM phase on its own (Sec. III-A.1: update
+ * of the trailing submatrix): C (M x N) <- C - A (M x K) * B (K x N), FP64,
+ * column-major, on the FP64 matrix cores.  Asynchronous on `stream`.
+ */
+int mxlu_schur_update_f64(int64_t M, int64_t N, int64_t K, const double *A,
+                          int64_t lda, const double *B, int64_t ldb, double *C,
+                          int64_t ldc, void *stream);
+
+/* Precision of the mixed-precision factorization. */
+enum {
+    MXLU_PREC_BF16 = 0,  /* bf16 storage, BF16 MFMA trailing update, FP32 accumulation */
+    MXLU_PREC_FP16 = 1,  /* fp16 storage, FP16 MFMA trailing update, FP32 accumulation */
+    MXLU_PREC_FP8 = 2    /* fp16 storage, e4m3fn operands with per-tile power-of-two
+                            FP32 scales in the trailing update, FP32 accumulation */
+};
+enum { MXLU_IR_CLASSICAL = 0, MXLU_IR_GMRES = 1 };
+
+typedef struct {
+    int32_t prec;            /* MXLU_PREC_* */
+    int32_t pivot;           /* 0: no pivoting (Sec. III-A.2); 1: partial pivoting on FP32 values */
+    int64_t nb;              /* panel width */
+    int32_t refine;          /* MXLU_IR_CLASSICAL or MXLU_IR_GMRES */
+    int32_t restart;         /* GMRES cycle length m */
+    int32_t max_outer;       /* refinement steps */
+    int32_t max_inner_total; /* GMRES Arnoldi steps over all cycles */
+    double inner_tol;        /* GMRES: stop a cycle when the estimate <= inner_tol * beta */
+    double resid_threshold;  /* stop when the HPL scaled residual < this (16) */
+    int32_t scale_tile;      /* FP8: rows (cols) per scale tile of L21 (U12) */
+    int32_t reuse_factors;   /* 1: the factors in `work` come from an earlier call
+                                with the same A, n, opts: skip conversion and LU */
+    int32_t trans;           /* 0: solve A X = B; 1: solve A^T X = B */
+    int32_t x_init;          /* 0: x0 = M b; 1: X holds the initial guess */
+} mxp_opts;
+
+typedef struct {
+    int32_t converged;       /* 1 when every column reached resid_threshold */
+    int32_t outer_iters;     /* refinement steps, summed over the columns */
+    int32_t inner_iters;     /* GMRES Arnoldi steps, summed over the columns */
+    int32_t info;            /* > 0: first exactly-zero pivot column (1-based) */
+    double scaled_residual;  /* largest final HPL scaled residual over the columns */
+    double t_convert_ms, t_factor_ms, t_refine_ms;  /* event-timed phases */
+} mxp_report;
+
+/* Fill *opts with the defaults: BF16, no pivoting, nb 512, GMRES, restart 30,
+ * max_outer 20, max_inner_total 300, inner_tol 1e-6, threshold 16, tile 128. */
+void mxp_default_opts(mxp_opts *opts);
+
+/* Bytes of caller workspace mxp_solve needs for order n (factor storage,
+ * pivots-free), or 0 when the size overflows. */
+size_t mxp_workspace_bytes(int64_t n, const mxp_opts *opts);
+
+/*
+ * mxp_solve -- mixed-precision solve (Sec. III-A.2, Sec. II-B).
+ *   A      n x n FP64 (unmodified; used for the FP64 residuals)
+ *   B      n x nrhs FP64 right-hand sides (unmodified)
+ *   X      n x nrhs FP64 solution (in: initial guess when opts->x_init = 1)
+ *   work   caller workspace of >= mxp_workspace_bytes(n, opts) bytes; holds
+ *          the low-precision factors on return (reusable, see reuse_factors)
+ *   ipiv   n int32 when opts->pivot = 1 (written unless reuse_factors), else NULL
+ *   report filled on return (host struct), may be NULL
+ * Steps: convert A to the storage precision (round to nearest even from
+ * FP64); blocked LU in low precision; x0 = M b with M = U^-1 L^-1 P applied in
+ * FP32; then refinement with FP64 residuals r = b - A x until the HPL scaled
+ * residual ||r||_inf / (eps (||A||_inf ||x||_inf + ||b||_inf) n), eps = 2^-53,
+ * drops below opts->resid_threshold: classical (x += M r) or GMRES-IR.
+ * Returns MXLU_E_NOTCONV when a column does not converge (X holds the last
+ * iterate, report is filled).  Synchronises `stream` once per refinement step.
+ */
+int mxp_solve(int64_t n, int64_t nrhs, const double *A, int64_t lda,
+              const double *B, int64_t ldb, double *X, int64_t ldx,
+              void *work, size_t work_bytes, int32_t *ipiv,
+              const mxp_opts *opts, mxp_report *report, void *stream);
+
+/*
+ * Seeded synthetic inputs (not part of the method).  Element (i, j) of a
+ * rows x cols matrix is u(j*rows + i) with the counter-based generator
+ *   mix(z) = SplitMix64 finaliser, key = mix(seed + G (stream_id + 1)),
+ *   u(idx) = (mix(key + G (idx + 1)) >> 32) * 2^-32 - 0.5,  G = 0x9E3779B97F4A7C15.
+ * mxlu_make_diag_dominant replaces each diagonal entry of A by the sum of
+ * the absolute values of the other entries of its row (exact in FP64 for
+ * generator values).
+ */
+int mxlu_fill_uniform(int64_t rows, int64_t cols, double *A, int64_t lda,
+                      uint64_t seed, uint64_t stream_id, void *stream);
+int mxlu_make_diag_dominant(int64_t n, double *A, int64_t lda, void *stream);
+
+/*
+ * mxlu_scaled_residual -- verification in FP64 on the device (not timed):
+ * for each column c of X, R(:,c) = B(:,c) - op(A) X(:,c) and
+ * out[c] = ||R(:,c)||_inf / (eps (||op(A)||_inf ||X(:,c)||_inf + ||B(:,c)||_inf) n)
+ * with eps = 2^-53; op(A) = A (trans 0) or A^T (trans 1).  out is a HOST
+ * array of nrhs doubles; synchronises `stream`.
+ */
+int mxlu_scaled_residual(int64_t n, int64_t nrhs, const double *A, int64_t lda,
+                         const double *X, int64_t ldx, const double *B,
+                         int64_t ldb, int trans, double *out, void *stream);
+
+/* Static description of a status code. */
+const char *mxlu_status_string(int status);
+/* Detail of the last runtime failure on the calling thread ("" if none). */
+const char *mxlu_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MXLU_H */

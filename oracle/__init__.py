@@ -79,6 +79,8 @@ def _bind(L):
     i64, i32, dp = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p
     L.oracle_getrf_steps.argtypes = [i64, i64, dp, i64, dp, i64]
     L.oracle_getrf_steps.restype = i32
+    L.oracle_panel_getf2.argtypes = [i64, i64, dp, i64, dp]
+    L.oracle_panel_getf2.restype = i32
     L.oracle_getrs.argtypes = [i64, i64, dp, i64, dp, dp, i64, i32]
     L.oracle_getrs.restype = i32
     L.oracle_round.argtypes = [ctypes.c_double, i32]
@@ -112,6 +114,17 @@ def getrf(A, nb, max_steps=-1):
                                     int(max_steps))
     if info < 0:
         raise ValueError(f"oracle_getrf: bad argument ({info})")
+    return LU, ipiv, info
+
+
+def panel_getrf(P):
+    """GEPP of an m x kb panel (the first PFACT step).  Returns (LU, ipiv, info)."""
+    LU = _fortran(P)
+    m, kb = LU.shape
+    ipiv = np.arange(kb, dtype=np.int32)
+    info = lib().oracle_panel_getf2(m, kb, _ptr(LU), max(m, 1), _ptr(ipiv))
+    if info < 0:
+        raise ValueError("oracle_panel_getf2: bad argument")
     return LU, ipiv, info
 
 

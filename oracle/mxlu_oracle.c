@@ -160,6 +160,19 @@ int oracle_getrf(int64_t n, int64_t nb, double *A, int64_t lda, int32_t *ipiv)
 }
 
 /*
+ * PFACT of the leading panel alone: unblocked GEPP of an m x kb panel (the
+ * first step of the blocked algorithm only reads these columns, so its pivots
+ * and L\U panel are those of the full factorization's first step).
+ */
+int oracle_panel_getf2(int64_t m, int64_t kb, double *A, int64_t lda, int32_t *ipiv)
+{
+    if (m < 0 || kb < 0 || kb > m || lda < (m > 1 ? m : 1)) return -1;
+    int info = 0;
+    panel_getf2(m, 0, kb, A, lda, ipiv, &info);
+    return info;
+}
+
+/*
  * Solve with the factors of oracle_getrf.  trans = 0: A X = B, i.e. apply the
  * interchanges to B in order, forward substitution with unit-lower L, back
  * substitution with U (true division).  trans = 1: A^T X = B, i.e. U^T y = b

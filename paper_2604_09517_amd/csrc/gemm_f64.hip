@@ -1,0 +1,228 @@
+// Trailing-matrix update C -= A * B in FP64 on the matrix cores (gfx950).
+//
+// This is the DGEMM phase of the right-looking blocked LU (Sec. III-A.1: the
+// update of the trailing submatrix, which carries almost all of the 2/3 N^3
+// flops): A22 -= L21 * U12 with A = L21 (M x K), B = U12 (K x N), C = A22.
+//
+// Design (CDNA4):
+//   * 256 threads = 4 waves in a 2 x 2 arrangement; a workgroup owns a
+//     128 x 128 tile of C, each wave a 64 x 64 sub-tile held as 4 x 4
+//     accumulators of v_mfma_f64_16x16x4_f64 (64 doubles per lane).
+//   * The accumulators start from C and the MFMA consumes -A, so the tile is
+//     read once and written once: C - sum_k a_ik b_kj in one pass.
+//   * K is walked in chunks of 16; A and B chunks are staged in LDS, double
+//     buffered, with the next chunk's global loads in flight during the MFMAs
+//     of the current one (one workgroup barrier per chunk).
+//   * Tile order: consecutive workgroup ids are dealt round-robin over the 8
+//     XCDs, so ids are remapped to give every XCD a contiguous run of tiles,
+//     and tiles are ordered in groups of 8 tile-rows so that tiles that share
+//     A rows run on the same XCD (shared L2).
+//
+// MFMA operand layout (16x16x4 f64, wave64; lane l, i = l % 16, q = l / 16),
+// measured on gfx950: A operand A[i][q]; B operand B[q][i]; accumulator
+// register r holds D[q + 4r][i].
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 128, BN = 128, BK = 16;
+constexpr int APAD = 4, BPAD = 4;   // LDS row padding (doubles)
+constexpr int AST = BM + APAD;      // LDS stride of one k-row of the A chunk
+constexpr int BST = BN + BPAD;
+constexpr int GROUP_M = 8;
+
+__device__ inline void tile_of(int g, int tiles_m, int tiles_n, int &tm, int &tn) {
+    const int G = tiles_m * tiles_n;
+    // XCD-contiguous remap: id g runs on XCD g % 8.
+    const int per = G / 8, rem = G % 8;
+    const int xcd = g % 8, local = g / 8;
+    const int t = (xcd < rem) ? xcd * (per + 1) + local
+                              : rem * (per + 1) + (xcd - rem) * per + local;
+    // grouped order: GROUP_M tile-rows at a time, column-major inside a group
+    const int in_group = GROUP_M * tiles_n;
+    const int group = t / in_group;
+    const int first_m = group * GROUP_M;
+    const int gsize = min(tiles_m - first_m, GROUP_M);
+    const int r = t - group * in_group;
+    tm = first_m + r % gsize;
+    tn = r / gsize;
+}
+
+template <bool FULL>
+__global__ __launch_bounds__(256, 2) void gemm_f64_sub_kernel(
+    int64_t M, int64_t N, int64_t K, const double *__restrict__ A, int64_t lda,
+    const double *__restrict__ B, int64_t ldb, double *__restrict__ C, int64_t ldc,
+    int tiles_m, int tiles_n) {
+    __shared__ double As[2][BK * AST];
+    __shared__ double Bs[2][BK * BST];
+
+    int tm, tn;
+    tile_of(blockIdx.x, tiles_m, tiles_n, tm, tn);
+    const int64_t row0 = (int64_t)tm * BM;
+    const int64_t col0 = (int64_t)tn * BN;
+
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int li = lane & 15, lq = lane >> 4;
+
+    // ---- accumulators <- C -------------------------------------------------
+    v4d acc[4][4];
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj) {
+            const int64_t r = row0 + wm * 64 + bi * 16 + lq;
+            const int64_t c = col0 + wn * 64 + bj * 16 + li;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                double v = 0.0;
+                if (FULL || (r + 4 * e < M && c < N)) v = MXLU_AT(C, r + 4 * e, c, ldc);
+                acc[bi][bj][e] = v;
+            }
+        }
+
+    // ---- global -> register staging of one K chunk --------------------------
+    // A chunk (BM x BK): thread -> row i = tid % 128, k = (tid / 128) * 8 + q
+    // B chunk (BK x BN): thread -> col j = tid / 2,  k = (tid % 2) * 8 + q
+    const int a_i = tid & 127, a_k0 = (tid >> 7) * 8;
+    const int b_j = tid >> 1, b_k0 = (tid & 1) * 8;
+    double ra[8], rb[8];
+
+    auto load_chunk = [&](int64_t k0) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t k = k0 + a_k0 + q;
+            const int64_t r = row0 + a_i;
+            ra[q] = (FULL || (r < M && k < K)) ? MXLU_AT(A, r, k, lda) : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t k = k0 + b_k0 + q;
+            const int64_t c = col0 + b_j;
+            rb[q] = (FULL || (k < K && c < N)) ? MXLU_AT(B, k, c, ldb) : 0.0;
+        }
+    };
+    auto store_chunk = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) As[buf][(a_k0 + q) * AST + a_i] = -ra[q];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) Bs[buf][(b_k0 + q) * BST + b_j] = rb[q];
+    };
+
+    const int nk = (int)((K + BK - 1) / BK);
+    load_chunk(0);
+    store_chunk(0);
+    __syncthreads();
+
+    for (int kt = 0; kt < nk; ++kt) {
+        const int buf = kt & 1;
+        if (kt + 1 < nk) load_chunk((int64_t)(kt + 1) * BK);
+        const double *as = As[buf];
+        const double *bs = Bs[buf];
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            double a[4], b[4];
+#pragma unroll
+            for (int bi = 0; bi < 4; ++bi) a[bi] = as[(kk + lq) * AST + wm * 64 + bi * 16 + li];
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj) b[bj] = bs[(kk + lq) * BST + wn * 64 + bj * 16 + li];
+#pragma unroll
+            for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 4; ++bj)
+                    acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], acc[bi][bj],
+                                                                       0, 0, 0);
+        }
+        if (kt + 1 < nk) store_chunk(buf ^ 1);
+        __syncthreads();
+    }
+
+    // ---- C <- accumulators -------------------------------------------------
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj) {
+            const int64_t r = row0 + wm * 64 + bi * 16 + lq;
+            const int64_t c = col0 + wn * 64 + bj * 16 + li;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (FULL || (r + 4 * e < M && c < N))
+                    MXLU_AT(C, r + 4 * e, c, ldc) = acc[bi][bj][e];
+        }
+}
+
+// Tall-skinny update for few right-hand sides (N <= 16): C -= A * B with one
+// thread per row of C; B (K x N) is staged in LDS.  Memory-bound on A.
+template <int NMAX>
+__global__ __launch_bounds__(256) void gemm_f64_sub_skinny_kernel(
+    int64_t M, int N, int64_t K, const double *__restrict__ A, int64_t lda,
+    const double *__restrict__ B, int64_t ldb, double *__restrict__ C, int64_t ldc) {
+    __shared__ double Bs[256 * NMAX];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double acc[NMAX];
+#pragma unroll
+    for (int c = 0; c < NMAX; ++c) acc[c] = (i < M && c < N) ? MXLU_AT(C, i, c, ldc) : 0.0;
+    for (int64_t k0 = 0; k0 < K; k0 += 256) {
+        const int kc = (int)((K - k0 < 256) ? K - k0 : 256);
+        __syncthreads();
+        for (int t = threadIdx.x; t < kc * NMAX; t += 256) {
+            const int k = t % kc, c = t / kc;
+            Bs[k * NMAX + c] = (c < N) ? MXLU_AT(B, k0 + k, c, ldb) : 0.0;
+        }
+        __syncthreads();
+        if (i < M) {
+            for (int k = 0; k < kc; ++k) {
+                const double a = MXLU_AT(A, i, k0 + k, lda);
+#pragma unroll
+                for (int c = 0; c < NMAX; ++c) acc[c] = fma(-a, Bs[k * NMAX + c], acc[c]);
+            }
+        }
+    }
+    if (i < M)
+#pragma unroll
+        for (int c = 0; c < NMAX; ++c)
+            if (c < N) MXLU_AT(C, i, c, ldc) = acc[c];
+}
+
+}  // namespace
+
+namespace mxlu {
+
+int gemm_f64_sub(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
+                 const double *B, int64_t ldb, double *C, int64_t ldc, hipStream_t s) {
+    if (M <= 0 || N <= 0 || K <= 0) return 0;
+    if (N <= 16) {
+        const unsigned grid = (unsigned)((M + 255) / 256);
+        if (N == 1)
+            hipLaunchKernelGGL(gemm_f64_sub_skinny_kernel<1>, dim3(grid), dim3(256), 0, s, M,
+                               (int)N, K, A, lda, B, ldb, C, ldc);
+        else
+            hipLaunchKernelGGL(gemm_f64_sub_skinny_kernel<16>, dim3(grid), dim3(256), 0, s, M,
+                               (int)N, K, A, lda, B, ldb, C, ldc);
+        MXLU_LAUNCH_CHECK();
+        return 0;
+    }
+    const int64_t tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
+    if (tiles_m * tiles_n > 0x7fffffff) {
+        set_error_msg("gemm_f64_sub: grid too large");
+        return MXLU_E_NOMEM;
+    }
+    const bool full = (M % BM == 0) && (N % BN == 0) && (K % BK == 0);
+    const dim3 grid((unsigned)(tiles_m * tiles_n));
+    if (full)
+        hipLaunchKernelGGL(gemm_f64_sub_kernel<true>, grid, dim3(256), 0, s, M, N, K, A, lda, B,
+                           ldb, C, ldc, (int)tiles_m, (int)tiles_n);
+    else
+        hipLaunchKernelGGL(gemm_f64_sub_kernel<false>, grid, dim3(256), 0, s, M, N, K, A, lda, B,
+                           ldb, C, ldc, (int)tiles_m, (int)tiles_n);
+    MXLU_LAUNCH_CHECK();
+    return 0;
+}
+
+}  // namespace mxlu

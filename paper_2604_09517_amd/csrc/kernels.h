@@ -1,0 +1,63 @@
+// Host-side launchers of the library's kernels (internal interface).
+// Every launcher enqueues on stream `s` and returns 0 or an MXLU_E_* code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mxlu {
+
+// C(M x N) -= A(M x K) * B(K x N), FP64, column-major.
+int gemm_f64_sub(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
+                 const double *B, int64_t ldb, double *C, int64_t ldc, hipStream_t s);
+
+// Exchange area of the multi-workgroup panel kernel.
+struct PanelExchange {
+    double *cand;     // [2][kMaxGroups][kLeafW + 2]
+    double *rowj;     // [2][kLeafW]
+    int *counters;    // one zeroed counter per matrix column
+    int *flags;       // [0]: first zero pivot (1-based), [1]: wait expired
+};
+constexpr int kLeafW = 32;        // columns factored by one leaf kernel
+constexpr int kMaxGroups = 256;   // workgroups of one leaf kernel (<= CUs)
+
+// Factor the m x w (w <= kLeafW) leaf A[r0:r0+m, r0:r0+w] with partial
+// pivoting; ipiv[r0 .. r0+w) receives absolute row indices.
+int panel_leaf_f64(int64_t m, int w, double *A, int64_t lda, int64_t r0, int32_t *ipiv,
+                   const PanelExchange &ex, hipStream_t s);
+
+// Apply the interchanges ipiv[j0 .. j0+cnt) (absolute rows, cnt <= 1024) to
+// the columns c_begin + q (q < ncols, skipping [skip_begin, skip_begin +
+// skip_len)).  `moves` is a device buffer of kSwapMovesInts ints.
+constexpr int kSwapMovesInts = 1 + 4 * 1024;
+int laswp_f64(double *A, int64_t lda, const int32_t *ipiv, int64_t j0, int cnt,
+              int64_t c_begin, int64_t ncols, int64_t skip_begin, int64_t skip_len,
+              int *moves, hipStream_t s);
+
+// B(kb x ncols) = L^-1 B with L unit lower (kb x kb), kb <= 256.
+int trsm_llnu_f64(int kb, int64_t ncols, const double *L, int64_t ldl, double *B,
+                  int64_t ldb, hipStream_t s);
+// B(kb x ncols) = U^-1 B with U upper, non-unit (kb <= 256).
+int trsm_lunn_f64(int kb, int64_t ncols, const double *U, int64_t ldu, double *B,
+                  int64_t ldb, hipStream_t s);
+// B(kb x ncols) = U^-T B (U upper non-unit) and B = L^-T B (L unit lower).
+int trsm_lutn_f64(int kb, int64_t ncols, const double *U, int64_t ldu, double *B,
+                  int64_t ldb, hipStream_t s);
+int trsm_lltu_f64(int kb, int64_t ncols, const double *L, int64_t ldl, double *B,
+                  int64_t ldb, hipStream_t s);
+
+// C(M x N) -= A(K x M)^T * B(K x N), N <= 16 (transposed solves' updates).
+int gemm_f64_sub_tn_skinny(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
+                           const double *B, int64_t ldb, double *C, int64_t ldc,
+                           hipStream_t s);
+
+// perm[i] = original row at position i after the interchanges ipiv[0..n).
+int perm_from_ipiv(int64_t n, const int32_t *ipiv, int32_t *perm, hipStream_t s);
+// Y(i, c) = B(perm[i], c)  (gather)   /   B(perm[i], c) = Y(i, c)  (scatter)
+int gather_rows_f64(int64_t n, int64_t nrhs, const int32_t *perm, const double *B,
+                    int64_t ldb, double *Y, int64_t ldy, hipStream_t s);
+int scatter_rows_f64(int64_t n, int64_t nrhs, const int32_t *perm, const double *Y,
+                     int64_t ldy, double *B, int64_t ldb, hipStream_t s);
+
+}  // namespace mxlu

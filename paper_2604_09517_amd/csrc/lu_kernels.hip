@@ -1,0 +1,630 @@
+// FP64 kernels of the right-looking LU other than the trailing GEMM:
+//   PFACT  multi-workgroup panel factorization with partial pivoting,
+//   SWAP   row interchanges (composed, then applied column-strip-wise),
+//   DTRSM  triangular solves with a diagonal block (row per thread),
+// plus the permutation helpers of the solve (Sec. III-A.1).
+#include <hip/hip_runtime.h>
+
+#include <climits>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace {
+
+// Barrier that orders LDS only, so that global loads issued before it stay in
+// flight across it.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// (value, index) argmax: larger value wins, equal values go to the smaller
+// index (the first maximum, as in BLAS idamax).  NaN never wins.
+__device__ __forceinline__ void argmax_merge(double &v, int &idx, double ov, int oidx) {
+    if (ov > v || (ov == v && oidx < idx)) {
+        v = ov;
+        idx = oidx;
+    }
+}
+
+__device__ __forceinline__ void wave_argmax(double &v, int &idx) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(v, off);
+        const int oi = __shfl_xor(idx, off);
+        argmax_merge(v, idx, ov, oi);
+    }
+}
+
+// 256-thread argmax; every thread returns the result.
+__device__ __forceinline__ void block_argmax(double &v, int &idx, double *sv, int *si) {
+    wave_argmax(v, idx);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sv[w] = v;
+        si[w] = idx;
+    }
+    __syncthreads();
+    v = sv[0];
+    idx = si[0];
+#pragma unroll
+    for (int k = 1; k < 4; ++k) argmax_merge(v, idx, sv[k], si[k]);
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// PFACT leaf: columns [r0, r0 + w) of rows [r0, r0 + m), w <= kLeafW.
+// Workgroup g keeps rows [g R, g R + R) of the leaf in LDS (column-major,
+// stride R) for the whole kernel.  Per column j:
+//   1. local candidate: first row >= j of largest |a_ij| in the group;
+//   2. publish (|a|, row, full leaf row) and, by the owner, row j itself;
+//   3. grid barrier (one agent-scope atomic counter per matrix column);
+//   4. every group reduces the G candidates to the same winner p;
+//   5. owners of rows j and p swap them (whole leaf rows);
+//   6. rows > j: divide column j by the pivot, rank-1 update of columns > j.
+// An exactly zero pivot column is left unscaled; flags[0] records the first
+// such column (1-based).  The wait in step 3 is bounded: on expiry flags[1]
+// is set and the kernel runs to completion with invalid results.
+// Candidate slots are double-buffered by the parity of j: a group writes the
+// slots of column j only after barrier j-1, which every group reaches after
+// it has read the slots of column j-2.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void panel_leaf_f64_kernel(
+    int m, int w, double *__restrict__ P, int64_t lda, int R, int G, int64_t r0,
+    int32_t *__restrict__ ipiv, double *cand, double *rowj, int *counters, int *flags) {
+    extern __shared__ double sp[];   // [kLeafW][R]
+    __shared__ double s_prow[mxlu::kLeafW], s_rowj[mxlu::kLeafW];
+    __shared__ double s_v[4];
+    __shared__ int s_i[4];
+    constexpr int SLOT = mxlu::kLeafW + 2;
+
+    const int g = blockIdx.x, tid = threadIdx.x;
+    const int rb = g * R;
+    const int rows = min(R, m - rb);
+
+    for (int c = 0; c < w; ++c)
+        for (int i = tid; i < rows; i += 256) sp[c * R + i] = MXLU_AT(P, rb + i, c, lda);
+    __syncthreads();
+
+    for (int j = 0; j < w; ++j) {
+        const int par = j & 1;
+        double v = -1.0;
+        int idx = INT_MAX;
+        for (int i = tid; i < rows; i += 256) {
+            if (rb + i >= j) {
+                const double a = fabs(sp[j * R + i]);
+                if (a > v) {
+                    v = a;
+                    idx = rb + i;
+                }
+            }
+        }
+        block_argmax(v, idx, s_v, s_i);
+
+        double *mine = cand + ((size_t)par * mxlu::kMaxGroups + g) * SLOT;
+        if (tid == 0) {
+            mine[0] = v;
+            mine[1] = (double)idx;
+        }
+        if (tid < w && idx != INT_MAX) mine[2 + tid] = sp[tid * R + (idx - rb)];
+        if (tid < w && j >= rb && j < rb + rows)
+            rowj[par * mxlu::kLeafW + tid] = sp[tid * R + (j - rb)];
+        __syncthreads();
+
+        if (G > 1) {
+            // every wave releases its own slot writes at agent scope, one
+            // thread arrives and waits, every wave acquires
+            __threadfence();
+            __syncthreads();
+            if (tid == 0) {
+                atomicAdd(&counters[j], 1);
+                long spins = 0;
+                while (__hip_atomic_load(&counters[j], __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT) < G) {
+                    __builtin_amdgcn_s_sleep(1);
+                    if (++spins > (1L << 26)) {
+                        atomicExch(&flags[1], 1);
+                        break;
+                    }
+                }
+            }
+            __syncthreads();
+            __threadfence();
+        }
+
+        double gv = -1.0;
+        int gi = INT_MAX;
+        if (tid < G) {
+            const double *c = cand + ((size_t)par * mxlu::kMaxGroups + tid) * SLOT;
+            gv = c[0];
+            const double di = c[1];
+            gi = (di >= (double)INT_MAX) ? INT_MAX : (int)di;
+        }
+        block_argmax(gv, gi, s_v, s_i);
+        // gi is a valid row >= j: group 0's own candidate at least exists
+        // whenever some row >= j is left, which always holds for j < m.
+        const int p = gi;
+        const int gw = p / R;
+        if (tid < w) {
+            s_prow[tid] = cand[((size_t)par * mxlu::kMaxGroups + gw) * SLOT + 2 + tid];
+            s_rowj[tid] = rowj[par * mxlu::kLeafW + tid];
+        }
+        __syncthreads();
+
+        const bool nonzero = (gv != 0.0);
+        if (nonzero && p != j && tid < w) {
+            if (j >= rb && j < rb + rows) sp[tid * R + (j - rb)] = s_prow[tid];
+            if (p >= rb && p < rb + rows) sp[tid * R + (p - rb)] = s_rowj[tid];
+        }
+        if (g == 0 && tid == 0) {
+            ipiv[j] = (int32_t)(r0 + (nonzero ? p : j));
+            if (!nonzero && flags[0] == 0) flags[0] = (int)(r0 + j + 1);
+        }
+        __syncthreads();
+
+        const double piv = s_prow[j];
+        for (int i = tid; i < rows; i += 256) {
+            if (rb + i > j) {
+                double l = sp[j * R + i];
+                if (nonzero) {
+                    l = l / piv;
+                    sp[j * R + i] = l;
+                }
+                for (int c = j + 1; c < w; ++c)
+                    sp[c * R + i] = fma(-l, s_prow[c], sp[c * R + i]);
+            }
+        }
+        __syncthreads();
+    }
+
+    for (int c = 0; c < w; ++c)
+        for (int i = tid; i < rows; i += 256) MXLU_AT(P, rb + i, c, lda) = sp[c * R + i];
+}
+
+// ---------------------------------------------------------------------------
+// SWAP.  compose: one workgroup turns the interchange sequence
+// ipiv[j0 .. j0+cnt) (rows >= j0) into a list of moves (dst row <- src row):
+// slots 0..cnt-1 stand for rows j0..j0+cnt-1, further slots for the distinct
+// rows beyond them, numbered in order of first appearance; the interchanges
+// are replayed on slot contents, and every slot whose content changed is one
+// move.  apply: each workgroup copies the moves for a strip of columns,
+// staging the gathered values in LDS so that all reads of a column precede
+// all of its writes.
+// ---------------------------------------------------------------------------
+constexpr int kMaxSwaps = 1024;
+
+__global__ __launch_bounds__(256) void swap_compose_kernel(const int32_t *__restrict__ ipiv,
+                                                           int64_t j0, int cnt,
+                                                           int *__restrict__ moves) {
+    __shared__ int s_piv[kMaxSwaps];
+    __shared__ int s_first[kMaxSwaps];
+    __shared__ int s_slot[kMaxSwaps];
+    __shared__ int s_ext[kMaxSwaps];
+    __shared__ int s_content[2 * kMaxSwaps];
+    __shared__ int s_nslots;
+    __shared__ int s_wsum[4];
+    const int tid = threadIdx.x;
+    for (int t = tid; t < cnt; t += 256) s_piv[t] = (int)(ipiv[j0 + t] - j0);  // relative
+    __syncthreads();
+    for (int t = tid; t < cnt; t += 256) {
+        const int p = s_piv[t];
+        int first = t;
+        if (p >= cnt)
+            for (int u = 0; u < t; ++u)
+                if (s_piv[u] == p) {
+                    first = u;
+                    break;
+                }
+        s_first[t] = first;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int e = 0;
+        for (int t = 0; t < cnt; ++t) {
+            const int p = s_piv[t];
+            int sl;
+            if (p < cnt) sl = p;
+            else if (s_first[t] == t) {
+                s_ext[e] = p;
+                sl = cnt + e;
+                ++e;
+            } else sl = s_slot[s_first[t]];
+            s_slot[t] = sl;
+        }
+        s_nslots = cnt + e;
+    }
+    __syncthreads();
+    const int nslots = s_nslots;
+    for (int t = tid; t < nslots; t += 256) s_content[t] = t;
+    __syncthreads();
+    if (tid == 0) {
+        for (int t = 0; t < cnt; ++t) {
+            const int sl = s_slot[t];
+            const int a = s_content[t];
+            s_content[t] = s_content[sl];
+            s_content[sl] = a;
+        }
+    }
+    __syncthreads();
+    // compact the changed slots in slot order: moves = [count, dst..., src...]
+    int base = 0;
+    for (int t0 = 0; t0 < nslots; t0 += 256) {
+        const int t = t0 + tid;
+        const bool moved = (t < nslots) && (s_content[t] != t);
+        const unsigned long long mask = __ballot(moved);
+        const int lane = tid & 63, wv = tid >> 6;
+        const int before = __popcll(mask & ((1ull << lane) - 1ull));
+        if (lane == 0) s_wsum[wv] = __popcll(mask);
+        __syncthreads();
+        int off = base;
+        for (int k = 0; k < wv; ++k) off += s_wsum[k];
+        if (moved) {
+            const int pos = off + before;
+            const int src = s_content[t];
+            const int dst_row = (t < cnt) ? t : s_ext[t - cnt];
+            const int src_row = (src < cnt) ? src : s_ext[src - cnt];
+            moves[1 + pos] = dst_row;
+            moves[1 + 2 * kMaxSwaps + pos] = src_row;
+        }
+        const int total = s_wsum[0] + s_wsum[1] + s_wsum[2] + s_wsum[3];
+        __syncthreads();
+        base += total;
+    }
+    if (tid == 0) moves[0] = base;
+}
+
+constexpr int kSwapColsPerBlock = 32;
+constexpr int kSwapBatch = 4;   // columns staged per round
+
+__global__ __launch_bounds__(256) void swap_apply_kernel(double *__restrict__ A, int64_t lda,
+                                                         int64_t j0, const int *__restrict__ moves,
+                                                         int64_t c_begin, int64_t ncols,
+                                                         int64_t skip_begin, int64_t skip_len) {
+    __shared__ int s_dst[2 * kMaxSwaps];
+    __shared__ int s_src[2 * kMaxSwaps];
+    __shared__ double s_val[kSwapBatch * 2 * kMaxSwaps / 2];   // 4 x 1024
+    const int tid = threadIdx.x;
+    const int nm = moves[0];
+    for (int t = tid; t < nm; t += 256) {
+        s_dst[t] = moves[1 + t];
+        s_src[t] = moves[1 + 2 * kMaxSwaps + t];
+    }
+    __syncthreads();
+    if (nm == 0) return;
+    const int64_t q0 = (int64_t)blockIdx.x * kSwapColsPerBlock;
+    const int64_t q1 = (q0 + kSwapColsPerBlock < ncols) ? q0 + kSwapColsPerBlock : ncols;
+    const int per_round = (nm <= 1024) ? kSwapBatch : 2;   // s_val holds 4096 values
+    const int64_t skip_rel = skip_begin - c_begin;
+    for (int64_t qb = q0; qb < q1; qb += per_round) {
+        const int nb = (int)((q1 - qb < per_round) ? q1 - qb : per_round);
+        for (int t = tid; t < nb * nm; t += 256) {
+            const int b = t / nm, mv = t - b * nm;
+            const int64_t q = qb + b;
+            const int64_t c = c_begin + ((q < skip_rel) ? q : q + skip_len);
+            s_val[t] = MXLU_AT(A, j0 + s_src[mv], c, lda);
+        }
+        __syncthreads();
+        for (int t = tid; t < nb * nm; t += 256) {
+            const int b = t / nm, mv = t - b * nm;
+            const int64_t q = qb + b;
+            const int64_t c = c_begin + ((q < skip_rel) ? q : q + skip_len);
+            MXLU_AT(A, j0 + s_dst[mv], c, lda) = s_val[t];
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// DTRSM family, kb <= 256 rows: thread i owns row i of a strip of NC columns
+// of B in registers.  Step k broadcasts the finished row k through LDS (one
+// LDS barrier per k, double-buffered) and every row still to be solved takes
+// one fused multiply-add with its factor entry, so each entry accumulates its
+// terms in the same order as the textbook substitution.  The factor entries
+// are prefetched 8 steps ahead.
+// ---------------------------------------------------------------------------
+template <int NC, bool LOWER, bool UNIT, bool TRANS>
+__global__ __launch_bounds__(256) void trsm_kernel(int kb, int64_t ncols,
+                                                   const double *__restrict__ T, int64_t ldt,
+                                                   double *__restrict__ B, int64_t ldb) {
+    __shared__ double xs[2][NC];
+    const int i = threadIdx.x;
+    const int64_t c0 = (int64_t)blockIdx.x * NC;
+    const int nc = (int)((ncols - c0 < NC) ? ncols - c0 : NC);
+    double b[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) b[c] = (i < kb && c < nc) ? MXLU_AT(B, i, c0 + c, ldb) : 0.0;
+
+    // Effective factor F: column k of F is the k-th column used by the
+    // substitution.  LOWER && !TRANS: L (forward).  !LOWER && !TRANS: U
+    // (backward).  !LOWER && TRANS: U^T, lower (forward).  LOWER && TRANS: L^T,
+    // upper (backward).
+    constexpr bool FORWARD = (LOWER != TRANS);
+    auto fentry = [&](int row, int k) -> double {
+        // F[row][k]
+        return TRANS ? MXLU_AT(T, k, row, ldt) : MXLU_AT(T, row, k, ldt);
+    };
+    auto needs = [&](int row, int k) -> bool { return FORWARD ? (row > k) : (row < k); };
+
+    double lbuf[8], lnext[8];
+    auto prefetch = [&](int s0, double *dst) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int s = s0 + q;
+            const int k = FORWARD ? s : kb - 1 - s;
+            dst[q] = (s < kb && i < kb && (needs(i, k) || (!UNIT && i == k))) ? fentry(i, k) : 0.0;
+        }
+    };
+    prefetch(0, lbuf);
+    for (int s0 = 0; s0 < kb; s0 += 8) {
+        prefetch(s0 + 8, lnext);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int s = s0 + q;
+            if (s >= kb) break;
+            const int k = FORWARD ? s : kb - 1 - s;
+            if (i == k) {
+                if (!UNIT) {
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) b[c] = b[c] / lbuf[q];
+                }
+#pragma unroll
+                for (int c = 0; c < NC; ++c) xs[s & 1][c] = b[c];
+            }
+            lds_barrier();
+            if (i < kb && needs(i, k)) {
+                const double f = lbuf[q];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) b[c] = fma(-f, xs[s & 1][c], b[c]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) lbuf[q] = lnext[q];
+    }
+    if (i < kb)
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (c < nc) MXLU_AT(B, i, c0 + c, ldb) = b[c];
+}
+
+// C(M x N) -= A(K x M)^T B(K x N), N <= 16: one wave per output row i,
+// lanes stride over K (column i of A is contiguous).
+template <int NMAX>
+__global__ __launch_bounds__(256) void gemm_tn_skinny_kernel(int64_t M, int N, int64_t K,
+                                                             const double *__restrict__ A,
+                                                             int64_t lda,
+                                                             const double *__restrict__ B,
+                                                             int64_t ldb, double *__restrict__ C,
+                                                             int64_t ldc) {
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= M) return;
+    double acc[NMAX];
+#pragma unroll
+    for (int c = 0; c < NMAX; ++c) acc[c] = 0.0;
+    for (int64_t k = lane; k < K; k += 64) {
+        const double a = MXLU_AT(A, k, i, lda);
+#pragma unroll
+        for (int c = 0; c < NMAX; ++c)
+            if (c < N) acc[c] = fma(a, MXLU_AT(B, k, c, ldb), acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < NMAX; ++c) {
+        double v = acc[c];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        acc[c] = v;
+    }
+    if (lane < N) {
+        double v = 0.0;
+#pragma unroll
+        for (int c = 0; c < NMAX; ++c)
+            if (c == lane) v = acc[c];
+        MXLU_AT(C, i, lane, ldc) = MXLU_AT(C, i, lane, ldc) - v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Permutation of the solve: replay the n interchanges on an index array kept
+// in LDS when it fits, else in global memory.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void perm_from_ipiv_kernel(int64_t n,
+                                                             const int32_t *__restrict__ ipiv,
+                                                             int32_t *__restrict__ perm,
+                                                             int in_lds) {
+    extern __shared__ int sperm[];
+    int *p = in_lds ? sperm : perm;
+    for (int64_t t = threadIdx.x; t < n; t += 256) p[t] = (int)t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int64_t j = 0; j < n; ++j) {
+            const int q = ipiv[j];
+            if (q != j) {
+                const int a = p[j];
+                p[j] = p[q];
+                p[q] = a;
+            }
+        }
+    }
+    __syncthreads();
+    if (in_lds)
+        for (int64_t t = threadIdx.x; t < n; t += 256) perm[t] = sperm[t];
+}
+
+__global__ void gather_rows_kernel(int64_t n, int64_t nrhs, const int32_t *__restrict__ perm,
+                                   const double *__restrict__ B, int64_t ldb,
+                                   double *__restrict__ Y, int64_t ldy) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t src = perm[i];
+    for (int64_t c = 0; c < nrhs; ++c) MXLU_AT(Y, i, c, ldy) = MXLU_AT(B, src, c, ldb);
+}
+
+__global__ void scatter_rows_kernel(int64_t n, int64_t nrhs, const int32_t *__restrict__ perm,
+                                    const double *__restrict__ Y, int64_t ldy,
+                                    double *__restrict__ B, int64_t ldb) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t dst = perm[i];
+    for (int64_t c = 0; c < nrhs; ++c) MXLU_AT(B, dst, c, ldb) = MXLU_AT(Y, i, c, ldy);
+}
+
+}  // namespace
+
+namespace mxlu {
+
+static int max_dynamic_lds() {
+    static int cached = 0;
+    if (!cached) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+                hipSuccess)
+            v = 65536;
+        cached = v;
+    }
+    return cached;
+}
+
+int panel_leaf_f64(int64_t m, int w, double *A, int64_t lda, int64_t r0, int32_t *ipiv,
+                   const PanelExchange &ex, hipStream_t s) {
+    if (m <= 0 || w <= 0) return 0;
+    if (w > kLeafW || m > 0x7fffffff) {
+        set_error_msg("panel_leaf_f64: bad shape");
+        return MXLU_E_NOMEM;
+    }
+    // dynamic LDS budget: the device limit minus room for the static arrays
+    const int max_lds = max_dynamic_lds() - 1024;
+    const int rmax = max_lds / (kLeafW * (int)sizeof(double));
+    // about 64 groups; each group at least 256 rows, at most what LDS holds
+    int R = (int)((m + 63) / 64);
+    if (R < 256) R = 256;
+    if (R > rmax) R = rmax;
+    const int64_t G = (m + R - 1) / R;
+    if (G > kMaxGroups) {
+        set_error_msg("panel_leaf_f64: panel too tall for the LDS of the device");
+        return MXLU_E_NOMEM;
+    }
+    const size_t lds = (size_t)kLeafW * R * sizeof(double);
+    static bool attr_set = false;
+    if (!attr_set) {
+        MXLU_HIP_TRY(hipFuncSetAttribute((const void *)panel_leaf_f64_kernel,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, max_lds));
+        attr_set = true;
+    }
+    double *P = A + (size_t)r0 + (size_t)r0 * (size_t)lda;
+    hipLaunchKernelGGL(panel_leaf_f64_kernel, dim3((unsigned)G), dim3(256), lds, s, (int)m, w,
+                       P, lda, R, (int)G, r0, ipiv + r0, ex.cand, ex.rowj, ex.counters + r0,
+                       ex.flags);
+    MXLU_LAUNCH_CHECK();
+    return 0;
+}
+
+int laswp_f64(double *A, int64_t lda, const int32_t *ipiv, int64_t j0, int cnt,
+              int64_t c_begin, int64_t ncols, int64_t skip_begin, int64_t skip_len,
+              int *moves, hipStream_t s) {
+    if (cnt <= 0 || ncols <= 0) return 0;
+    if (cnt > kMaxSwaps || !moves) {
+        set_error_msg("laswp_f64: too many interchanges or no move buffer");
+        return MXLU_E_NOMEM;
+    }
+    hipLaunchKernelGGL(swap_compose_kernel, dim3(1), dim3(256), 0, s, ipiv, j0, cnt, moves);
+    MXLU_LAUNCH_CHECK();
+    const unsigned grid = (unsigned)((ncols + kSwapColsPerBlock - 1) / kSwapColsPerBlock);
+    hipLaunchKernelGGL(swap_apply_kernel, dim3(grid), dim3(256), 0, s, A, lda, j0,
+                       (const int *)moves, c_begin, ncols, skip_begin, skip_len);
+    MXLU_LAUNCH_CHECK();
+    return 0;
+}
+
+template <bool LOWER, bool UNIT, bool TRANS>
+static int trsm_launch(int kb, int64_t ncols, const double *T, int64_t ldt, double *B,
+                       int64_t ldb, hipStream_t s) {
+    if (kb <= 0 || ncols <= 0) return 0;
+    if (kb > 256) {
+        set_error_msg("trsm: diagonal block larger than 256");
+        return MXLU_E_NOMEM;
+    }
+    if (ncols <= 4) {
+        hipLaunchKernelGGL((trsm_kernel<1, LOWER, UNIT, TRANS>), dim3((unsigned)ncols), dim3(256),
+                           0, s, kb, ncols, T, ldt, B, ldb);
+    } else {
+        const unsigned grid = (unsigned)((ncols + 15) / 16);
+        hipLaunchKernelGGL((trsm_kernel<16, LOWER, UNIT, TRANS>), dim3(grid), dim3(256), 0, s, kb,
+                           ncols, T, ldt, B, ldb);
+    }
+    MXLU_LAUNCH_CHECK();
+    return 0;
+}
+
+int trsm_llnu_f64(int kb, int64_t ncols, const double *L, int64_t ldl, double *B, int64_t ldb,
+                  hipStream_t s) {
+    return trsm_launch<true, true, false>(kb, ncols, L, ldl, B, ldb, s);
+}
+int trsm_lunn_f64(int kb, int64_t ncols, const double *U, int64_t ldu, double *B, int64_t ldb,
+                  hipStream_t s) {
+    return trsm_launch<false, false, false>(kb, ncols, U, ldu, B, ldb, s);
+}
+int trsm_lutn_f64(int kb, int64_t ncols, const double *U, int64_t ldu, double *B, int64_t ldb,
+                  hipStream_t s) {
+    return trsm_launch<false, false, true>(kb, ncols, U, ldu, B, ldb, s);
+}
+int trsm_lltu_f64(int kb, int64_t ncols, const double *L, int64_t ldl, double *B, int64_t ldb,
+                  hipStream_t s) {
+    return trsm_launch<true, true, true>(kb, ncols, L, ldl, B, ldb, s);
+}
+
+int gemm_f64_sub_tn_skinny(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
+                           const double *B, int64_t ldb, double *C, int64_t ldc,
+                           hipStream_t s) {
+    if (M <= 0 || N <= 0 || K <= 0) return 0;
+    if (N > 16) {
+        set_error_msg("gemm_tn_skinny: more than 16 columns");
+        return MXLU_E_NOMEM;
+    }
+    const unsigned grid = (unsigned)((M + 3) / 4);
+    if (N == 1)
+        hipLaunchKernelGGL(gemm_tn_skinny_kernel<1>, dim3(grid), dim3(256), 0, s, M, (int)N, K, A,
+                           lda, B, ldb, C, ldc);
+    else
+        hipLaunchKernelGGL(gemm_tn_skinny_kernel<16>, dim3(grid), dim3(256), 0, s, M, (int)N, K,
+                           A, lda, B, ldb, C, ldc);
+    MXLU_LAUNCH_CHECK();
+    return 0;
+}
+
+int perm_from_ipiv(int64_t n, const int32_t *ipiv, int32_t *perm, hipStream_t s) {
+    if (n <= 0) return 0;
+    const int budget = max_dynamic_lds() - 1024;
+    const int in_lds = (int64_t)n * (int64_t)sizeof(int) <= budget;
+    const size_t lds = in_lds ? (size_t)n * sizeof(int) : 0;
+    static bool attr_set = false;
+    if (!attr_set) {
+        MXLU_HIP_TRY(hipFuncSetAttribute((const void *)perm_from_ipiv_kernel,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, budget));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(perm_from_ipiv_kernel, dim3(1), dim3(256), lds, s, n, ipiv, perm, in_lds);
+    MXLU_LAUNCH_CHECK();
+    return 0;
+}
+
+int gather_rows_f64(int64_t n, int64_t nrhs, const int32_t *perm, const double *B, int64_t ldb,
+                    double *Y, int64_t ldy, hipStream_t s) {
+    if (n <= 0 || nrhs <= 0) return 0;
+    hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
+                       nrhs, perm, B, ldb, Y, ldy);
+    MXLU_LAUNCH_CHECK();
+    return 0;
+}
+
+int scatter_rows_f64(int64_t n, int64_t nrhs, const int32_t *perm, const double *Y, int64_t ldy,
+                     double *B, int64_t ldb, hipStream_t s) {
+    if (n <= 0 || nrhs <= 0) return 0;
+    hipLaunchKernelGGL(scatter_rows_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       n, nrhs, perm, Y, ldy, B, ldb);
+    MXLU_LAUNCH_CHECK();
+    return 0;
+}
+
+}  // namespace mxlu

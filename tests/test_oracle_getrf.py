@@ -219,3 +219,12 @@ def test_perm_from_ipiv_roundtrip():
     for combo in itertools.product(range(3), repeat=3):
         ip = [max(j, c) for j, c in enumerate(combo)]
         assert sorted(checks.perm_from_ipiv(ip)) == [0, 1, 2]
+
+
+def test_panel_alone_equals_first_step(oracle_lib):
+    n, nb = 200, 48
+    A = inputs.uniform_matrix(12, 0, n, n)
+    LU, ipiv, _ = oracle.getrf(A, nb, max_steps=1)
+    P, pp, _ = oracle.panel_getrf(A[:, :nb])
+    assert np.array_equal(pp, ipiv[:nb])
+    assert np.array_equal(P, LU[:, :nb])
