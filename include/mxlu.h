@@ -79,6 +79,15 @@ int mxlu_schur_update_f64(int64_t M, int64_t N, int64_t K, const double *A,
                           int64_t lda, const double *B, int64_t ldb, double *C,
                           int64_t ldc, void *stream);
 
+/*
+ * mxlu_outer_update_f64 -- C (M x N) <- (accumulate ? C : 0) - A (M x K) B^T,
+ * B given as N x K (FP64 matrix cores).  Used for the gradient of a solve
+ * with respect to the matrix, dA = -Lambda X^T.  Asynchronous on `stream`.
+ */
+int mxlu_outer_update_f64(int64_t M, int64_t N, int64_t K, const double *A,
+                          int64_t lda, const double *B, int64_t ldb, double *C,
+                          int64_t ldc, int accumulate, void *stream);
+
 /* Precision of the mixed-precision factorization. */
 enum {
     MXLU_PREC_BF16 = 0,  /* bf16 storage, BF16 MFMA trailing update, FP32 accumulation */
@@ -118,9 +127,22 @@ typedef struct {
  * max_outer 20, max_inner_total 300, inner_tol 1e-6, threshold 16, tile 128. */
 void mxp_default_opts(mxp_opts *opts);
 
-/* Bytes of caller workspace mxp_solve needs for order n (factor storage,
- * pivots-free), or 0 when the size overflows. */
+/* Bytes of caller workspace mxp_solve needs for order n, or 0 when the size
+ * overflows.  The workspace starts with the low-precision factors: an n x n
+ * column-major array of 16-bit words (bf16 for MXLU_PREC_BF16, fp16 for the
+ * other two precisions) with leading dimension mxp_factor_ld(n), holding L
+ * (unit lower, below the diagonal) and U (upper), as lu_factor does in FP64. */
 size_t mxp_workspace_bytes(int64_t n, const mxp_opts *opts);
+int64_t mxp_factor_ld(int64_t n);
+
+/*
+ * mxp_convert -- the down-conversion step alone (Sec. III-A.2: the matrix is
+ * stored in reduced precision): F (rows x cols, 16-bit words, leading
+ * dimension ldf) <- A (FP64) rounded to nearest, ties to even, directly from
+ * FP64.  prec: MXLU_PREC_BF16 -> bf16, otherwise fp16.  Asynchronous.
+ */
+int mxp_convert(int32_t prec, int64_t rows, int64_t cols, const double *A, int64_t lda,
+                uint16_t *F, int64_t ldf, void *stream);
 
 /*
  * mxp_solve -- mixed-precision solve (Sec. III-A.2, Sec. II-B).
@@ -167,6 +189,19 @@ int mxlu_make_diag_dominant(int64_t n, double *A, int64_t lda, void *stream);
 int mxlu_scaled_residual(int64_t n, int64_t nrhs, const double *A, int64_t lda,
                          const double *X, int64_t ldx, const double *B,
                          int64_t ldb, int trans, double *out, void *stream);
+
+/*
+ * Instrumentation (not part of the method): per-phase GPU time measured with
+ * HIP events on the caller's stream.  Phases: 0 PFACT, 1 SWAP, 2 DTRSM,
+ * 3 DGEMM trailing update, 4 solve, 5 conversion, 6 low-precision LU,
+ * 7 refinement.  mxlu_profile_read synchronises on the recorded events and
+ * returns, per phase, the summed milliseconds, the summed nominal work (flops
+ * for DGEMM: 2 M N K per launch) and the number of intervals; arrays are HOST
+ * arrays of `nphase` entries (any may be NULL).
+ */
+int mxlu_profile_enable(int on);
+int mxlu_profile_reset(void);
+int mxlu_profile_read(double *ms, double *work, int64_t *count, int nphase);
 
 /* Static description of a status code. */
 const char *mxlu_status_string(int status);

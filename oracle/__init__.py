@@ -79,6 +79,8 @@ def _bind(L):
     i64, i32, dp = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p
     L.oracle_getrf_steps.argtypes = [i64, i64, dp, i64, dp, i64]
     L.oracle_getrf_steps.restype = i32
+    L.oracle_threads.argtypes = []
+    L.oracle_threads.restype = i32
     L.oracle_panel_getf2.argtypes = [i64, i64, dp, i64, dp]
     L.oracle_panel_getf2.restype = i32
     L.oracle_getrs.argtypes = [i64, i64, dp, i64, dp, dp, i64, i32]
@@ -94,6 +96,24 @@ def _bind(L):
     L.oracle_lp_precond.argtypes = [i64, dp, i64, dp, dp, dp, i32]
     L.oracle_lp_precond.restype = i32
     return L
+
+
+def threads():
+    """Number of OpenMP threads the oracle's parallel loops use."""
+    return int(lib().oracle_threads())
+
+
+def getrf_inplace(A, nb, max_steps=-1):
+    """getrf on a Fortran-ordered FP64 array in place (no copy; for timing
+    large samples).  Returns (ipiv, info)."""
+    assert A.dtype == np.float64 and A.flags["F_CONTIGUOUS"]
+    n = A.shape[0]
+    ipiv = np.arange(n, dtype=np.int32)
+    info = lib().oracle_getrf_steps(n, int(nb), _ptr(A), max(n, 1), _ptr(ipiv),
+                                    int(max_steps))
+    if info < 0:
+        raise ValueError(f"oracle_getrf: bad argument ({info})")
+    return ipiv, info
 
 
 def _fortran(a, dtype=np.float64):

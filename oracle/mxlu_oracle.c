@@ -30,6 +30,7 @@
  * index of the first column whose pivot is exactly zero.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -153,6 +154,9 @@ int oracle_getrf_steps(int64_t n, int64_t nb, double *A, int64_t lda,
     }
     return info;
 }
+
+/* Threads the OpenMP loops of this file use. */
+int oracle_threads(void) { return omp_get_max_threads(); }
 
 int oracle_getrf(int64_t n, int64_t nb, double *A, int64_t lda, int32_t *ipiv)
 {

@@ -42,14 +42,22 @@ SIGNATURES = {
     "lu_factor": (_int, [_i64, _i64, _vp, _i64, _vp, _vp]),
     "lu_solve": (_int, [_i64, _i64, _vp, _i64, _vp, _vp, _i64, _int, _vp]),
     "mxlu_schur_update_f64": (_int, [_i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp]),
+    "mxlu_outer_update_f64": (_int, [_i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _int,
+                                     _vp]),
     "mxp_default_opts": (None, [ctypes.POINTER(MxpOpts)]),
     "mxp_workspace_bytes": (_sz, [_i64, ctypes.POINTER(MxpOpts)]),
+    "mxp_factor_ld": (_i64, [_i64]),
+    "mxp_convert": (_int, [_i32, _i64, _i64, _vp, _i64, _vp, _i64, _vp]),
     "mxp_solve": (_int, [_i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _sz, _vp,
                          ctypes.POINTER(MxpOpts), ctypes.POINTER(MxpReport), _vp]),
     "mxlu_fill_uniform": (_int, [_i64, _i64, _vp, _i64, _u64, _u64, _vp]),
     "mxlu_make_diag_dominant": (_int, [_i64, _vp, _i64, _vp]),
     "mxlu_scaled_residual": (_int, [_i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _int,
                                     ctypes.POINTER(_dbl), _vp]),
+    "mxlu_profile_enable": (_int, [_int]),
+    "mxlu_profile_reset": (_int, []),
+    "mxlu_profile_read": (_int, [ctypes.POINTER(_dbl), ctypes.POINTER(_dbl),
+                                 ctypes.POINTER(_i64), _int]),
     "mxlu_status_string": (ctypes.c_char_p, [_int]),
     "mxlu_last_error": (ctypes.c_char_p, []),
 }

@@ -91,6 +91,19 @@ def schur_update(C, A, B):
     return C
 
 
+def outer_update(C, A, B, accumulate=False):
+    """C <- (accumulate ? C : 0) - A B^T (FP64 matrix cores); B is N x K."""
+    pc, m, n, ldc = _mat(C, "C")
+    pa, m2, k, lda = _mat(A, "A")
+    pb, n2, k2, ldb = _mat(B, "B")
+    if m2 != m or n2 != n or k2 != k:
+        raise ValueError("shape mismatch")
+    rc = lib().mxlu_outer_update_f64(m, n, k, pa, lda, pb, ldb, pc, ldc, 1 if accumulate else 0,
+                                     _stream())
+    check("mxlu_outer_update_f64", rc)
+    return C
+
+
 def fill_uniform(A, seed, stream_id):
     """Seeded i.i.d. values in [-0.5, 0.5) (the shared counter-based generator)."""
     pa, r, c, lda = _mat(A, "A")
@@ -147,6 +160,32 @@ def mxp_workspace_bytes(n, opts):
     return int(lib().mxp_workspace_bytes(int(n), ctypes.byref(opts)))
 
 
+def mxp_factor_ld(n):
+    return int(lib().mxp_factor_ld(int(n)))
+
+
+def mxp_factors(work, n, prec="bf16"):
+    """View of the low-precision factors held at the start of `work`
+    (n x n, column-major, as torch.bfloat16 or torch.float16)."""
+    ldf = mxp_factor_ld(n)
+    dt = torch.bfloat16 if prec in ("bf16", 0) else torch.float16
+    words = work[: 2 * ldf * n].view(dt)
+    return words.view(n, ldf).t()[:n, :]
+
+
+def mxp_convert(A, prec="bf16", out=None):
+    """A (FP64) rounded to bf16 / fp16 on the GPU (column-major result)."""
+    pa, r, c, lda = _mat(A, "A")
+    dt = torch.bfloat16 if prec in ("bf16", 0) else torch.float16
+    if out is None:
+        out = fortran_empty(r, c, dtype=dt, device=A.device)
+    po, _, _, ldo = _mat(out, "out", dt)
+    code = PREC[prec] if isinstance(prec, str) else int(prec)
+    rc = lib().mxp_convert(code, r, c, pa, lda, po, ldo, _stream())
+    check("mxp_convert", rc)
+    return out
+
+
 def mxp_solve(A, B, X=None, work=None, ipiv=None, opts=None, allow_notconv=False, **kw):
     """Mixed-precision solve.  Returns (X, report dict, work, ipiv)."""
     opts = opts if opts is not None else mxp_options(**kw)
@@ -175,3 +214,24 @@ def mxp_solve(A, B, X=None, work=None, ipiv=None, opts=None, allow_notconv=False
 def exported_symbols():
     """Names the binding expects the library to export."""
     return list(_lib.SIGNATURES)
+
+
+PHASES = ["pfact", "swap", "trsm", "gemm", "solve", "convert", "lp_factor", "refine"]
+
+
+def profile_enable(on=True):
+    check("mxlu_profile_enable", lib().mxlu_profile_enable(1 if on else 0))
+
+
+def profile_reset():
+    check("mxlu_profile_reset", lib().mxlu_profile_reset())
+
+
+def profile_read():
+    """{phase: (ms, work, count)} accumulated since the last reset."""
+    n = len(PHASES)
+    ms = (ctypes.c_double * n)()
+    work = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int64 * n)()
+    check("mxlu_profile_read", lib().mxlu_profile_read(ms, work, cnt, n))
+    return {p: (ms[i], work[i], cnt[i]) for i, p in enumerate(PHASES)}

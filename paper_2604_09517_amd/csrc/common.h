@@ -48,5 +48,11 @@ class Scratch {
 
 #define MXLU_LAUNCH_CHECK() MXLU_HIP_TRY(hipGetLastError())
 
+#define MXLU_TRY(x)              \
+    do {                         \
+        int rc_ = (x);           \
+        if (rc_) return rc_;     \
+    } while (0)
+
 // Offsets are 64-bit everywhere: n^2 exceeds 2^31 for the larger workloads.
 #define MXLU_AT(ptr, i, j, ld) ((ptr)[(size_t)(i) + (size_t)(j) * (size_t)(ld)])

@@ -53,7 +53,9 @@ __device__ inline void tile_of(int g, int tiles_m, int tiles_n, int &tm, int &tn
     tn = r / gsize;
 }
 
-template <bool FULL>
+// TRANSB: B is given as its transpose (element (k, j) at B[j + k ldb]);
+// ZEROC: C starts from zero instead of being read.
+template <bool FULL, bool TRANSB, bool ZEROC>
 __global__ __launch_bounds__(256, 2) void gemm_f64_sub_kernel(
     int64_t M, int64_t N, int64_t K, const double *__restrict__ A, int64_t lda,
     const double *__restrict__ B, int64_t ldb, double *__restrict__ C, int64_t ldc,
@@ -82,7 +84,7 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_sub_kernel(
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 double v = 0.0;
-                if (FULL || (r + 4 * e < M && c < N)) v = MXLU_AT(C, r + 4 * e, c, ldc);
+                if (!ZEROC && (FULL || (r + 4 * e < M && c < N))) v = MXLU_AT(C, r + 4 * e, c, ldc);
                 acc[bi][bj][e] = v;
             }
         }
@@ -91,7 +93,8 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_sub_kernel(
     // A chunk (BM x BK): thread -> row i = tid % 128, k = (tid / 128) * 8 + q
     // B chunk (BK x BN): thread -> col j = tid / 2,  k = (tid % 2) * 8 + q
     const int a_i = tid & 127, a_k0 = (tid >> 7) * 8;
-    const int b_j = tid >> 1, b_k0 = (tid & 1) * 8;
+    const int b_j = TRANSB ? (tid & 127) : (tid >> 1);
+    const int b_k0 = TRANSB ? (tid >> 7) * 8 : (tid & 1) * 8;
     double ra[8], rb[8];
 
     auto load_chunk = [&](int64_t k0) {
@@ -105,7 +108,9 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_sub_kernel(
         for (int q = 0; q < 8; ++q) {
             const int64_t k = k0 + b_k0 + q;
             const int64_t c = col0 + b_j;
-            rb[q] = (FULL || (k < K && c < N)) ? MXLU_AT(B, k, c, ldb) : 0.0;
+            rb[q] = (FULL || (k < K && c < N))
+                        ? (TRANSB ? MXLU_AT(B, c, k, ldb) : MXLU_AT(B, k, c, ldb))
+                        : 0.0;
         }
     };
     auto store_chunk = [&](int buf) {
@@ -216,11 +221,31 @@ int gemm_f64_sub(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
     const bool full = (M % BM == 0) && (N % BN == 0) && (K % BK == 0);
     const dim3 grid((unsigned)(tiles_m * tiles_n));
     if (full)
-        hipLaunchKernelGGL(gemm_f64_sub_kernel<true>, grid, dim3(256), 0, s, M, N, K, A, lda, B,
-                           ldb, C, ldc, (int)tiles_m, (int)tiles_n);
+        hipLaunchKernelGGL((gemm_f64_sub_kernel<true, false, false>), grid, dim3(256), 0, s, M, N,
+                           K, A, lda, B, ldb, C, ldc, (int)tiles_m, (int)tiles_n);
     else
-        hipLaunchKernelGGL(gemm_f64_sub_kernel<false>, grid, dim3(256), 0, s, M, N, K, A, lda, B,
-                           ldb, C, ldc, (int)tiles_m, (int)tiles_n);
+        hipLaunchKernelGGL((gemm_f64_sub_kernel<false, false, false>), grid, dim3(256), 0, s, M, N,
+                           K, A, lda, B, ldb, C, ldc, (int)tiles_m, (int)tiles_n);
+    MXLU_LAUNCH_CHECK();
+    return 0;
+}
+
+int gemm_f64_nt_sub(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
+                    const double *B, int64_t ldb, double *C, int64_t ldc, bool accumulate,
+                    hipStream_t s) {
+    if (M <= 0 || N <= 0) return 0;
+    const int64_t tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
+    if (tiles_m * tiles_n > 0x7fffffff) {
+        set_error_msg("gemm_f64_nt_sub: grid too large");
+        return MXLU_E_NOMEM;
+    }
+    const dim3 grid((unsigned)(tiles_m * tiles_n));
+    if (accumulate)
+        hipLaunchKernelGGL((gemm_f64_sub_kernel<false, true, false>), grid, dim3(256), 0, s, M, N,
+                           K, A, lda, B, ldb, C, ldc, (int)tiles_m, (int)tiles_n);
+    else
+        hipLaunchKernelGGL((gemm_f64_sub_kernel<false, true, true>), grid, dim3(256), 0, s, M, N,
+                           K, A, lda, B, ldb, C, ldc, (int)tiles_m, (int)tiles_n);
     MXLU_LAUNCH_CHECK();
     return 0;
 }

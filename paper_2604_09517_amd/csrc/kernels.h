@@ -11,6 +11,10 @@ namespace mxlu {
 // C(M x N) -= A(M x K) * B(K x N), FP64, column-major.
 int gemm_f64_sub(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
                  const double *B, int64_t ldb, double *C, int64_t ldc, hipStream_t s);
+// C(M x N) = (accumulate ? C : 0) - A(M x K) * B(N x K)^T.
+int gemm_f64_nt_sub(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
+                    const double *B, int64_t ldb, double *C, int64_t ldc, bool accumulate,
+                    hipStream_t s);
 
 // Exchange area of the multi-workgroup panel kernel.
 struct PanelExchange {
@@ -22,10 +26,21 @@ struct PanelExchange {
 constexpr int kLeafW = 32;        // columns factored by one leaf kernel
 constexpr int kMaxGroups = 256;   // workgroups of one leaf kernel (<= CUs)
 
-// Factor the m x w (w <= kLeafW) leaf A[r0:r0+m, r0:r0+w] with partial
-// pivoting; ipiv[r0 .. r0+w) receives absolute row indices.
-int panel_leaf_f64(int64_t m, int w, double *A, int64_t lda, int64_t r0, int32_t *ipiv,
-                   const PanelExchange &ex, hipStream_t s);
+// Factor the m x w (w <= kLeafW) leaf whose top-left element is P (leading
+// dimension ldp) with partial pivoting.  r0 is the leaf's first row/column
+// index within the caller's numbering: ipiv[r0 .. r0+w) receives r0 + the
+// pivot row within the leaf, and ex.counters[r0 ..] are its barrier counters.
+template <typename T>
+int panel_leaf(int64_t m, int w, T *P, int64_t ldp, int64_t r0, int32_t *ipiv,
+               const PanelExchange &ex, hipStream_t s);
+
+// Interchanges ipiv[j0 .. j0+cnt) (rows >= j0, cnt <= 1024) composed into a
+// list of row moves, then applied to the columns c_begin + q (q < ncols,
+// skipping [skip_begin, skip_begin + skip_len)) of a matrix of T.
+int swap_compose(const int32_t *ipiv, int64_t j0, int cnt, int *moves, hipStream_t s);
+template <typename T>
+int swap_apply(T *A, int64_t lda, int64_t j0, const int *moves, int64_t c_begin, int64_t ncols,
+               int64_t skip_begin, int64_t skip_len, hipStream_t s);
 
 // Apply the interchanges ipiv[j0 .. j0+cnt) (absolute rows, cnt <= 1024) to
 // the columns c_begin + q (q < ncols, skipping [skip_begin, skip_begin +
@@ -46,6 +61,17 @@ int trsm_lutn_f64(int kb, int64_t ncols, const double *U, int64_t ldu, double *B
                   int64_t ldb, hipStream_t s);
 int trsm_lltu_f64(int kb, int64_t ncols, const double *L, int64_t ldl, double *B,
                   int64_t ldb, hipStream_t s);
+
+class Scratch;
+// Zeroed exchange area of the panel kernels for a matrix of order n.
+int alloc_panel_exchange(Scratch &scratch, int64_t n, PanelExchange *ex, hipStream_t s);
+// GEPP of the m x kb panel P (recursive; leaves are panel_leaf<T>); element
+// (0, 0) is row/column ibase of the caller's matrix, ipiv[ibase ..] receives
+// caller-numbered rows; the interchanges are applied inside the panel only.
+// moves: kSwapMovesInts device ints.
+template <typename T>
+int panel_factor(T *P, int64_t ldp, int64_t m, int64_t kb, int64_t ibase, int32_t *ipiv,
+                 const PanelExchange &ex, int *moves, hipStream_t s);
 
 // C(M x N) -= A(K x M)^T * B(K x N), N <= 16 (transposed solves' updates).
 int gemm_f64_sub_tn_skinny(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,

@@ -1,0 +1,309 @@
+// Trailing update of the low-precision LU on the matrix cores (gfx950).
+//
+// Sec. III-A.2: the trailing matrix updates run in reduced precision; the
+// paper's runs store the matrix in BF16 and accumulate products in FP32.
+//   16-bit form:  A22 <- round( fp32(A22) - L21 U12 ), bf16 or fp16 operands,
+//                 v_mfma_f32_16x16x32_{bf16,f16}, accumulators start at A22.
+//   FP8 form:     A22 <- round_fp16( fp32(A22) - (Lq Uq) sL sU ), e4m3fn
+//                 operands with one power-of-two scale per 128-row tile of L21
+//                 and per 128-column tile of U12, v_mfma_scale_f32_16x16x128
+//                 _f8f6f4 with unit block scales, accumulators start at 0.
+//
+// Operands are read with k contiguous: L21 comes transposed (LT, K x M) and
+// U12 is the column-major block of the stored matrix.  A workgroup of 4
+// waves owns a 256 x 128 tile of A22 (each wave 128 x 64 = 8 x 4 MFMA
+// blocks); K is staged through LDS in chunks, double-buffered for the 16-bit
+// form, single-buffered with register prefetch for FP8.
+//
+// MFMA lane layouts (measured on gfx950; lane l, i = l % 16, g = l / 16):
+//   16x16x32 16-bit: A lane holds A[i][8g .. 8g+7], B lane B[8g .. 8g+7][i],
+//   16x16x128 fp8:   A lane holds A[i][32g .. 32g+31], B likewise,
+//   both: accumulator register r holds D[4g + r][i].
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+#include "lp_common.h"
+#include "lp_kernels.h"
+
+namespace {
+
+using namespace mxlu;
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef int v8i __attribute__((ext_vector_type(8)));
+
+constexpr int TM = 256, TN = 128;
+constexpr int GROUP_M = 8;
+
+__device__ inline void tile_of(int g, int tiles_m, int tiles_n, int &tm, int &tn) {
+    const int G = tiles_m * tiles_n;
+    const int per = G / 8, rem = G % 8;
+    const int xcd = g % 8, local = g / 8;
+    const int t = (xcd < rem) ? xcd * (per + 1) + local
+                              : rem * (per + 1) + (xcd - rem) * per + local;
+    const int in_group = GROUP_M * tiles_n;
+    const int group = t / in_group;
+    const int first_m = group * GROUP_M;
+    const int gsize = min(tiles_m - first_m, GROUP_M);
+    const int r = t - group * in_group;
+    tm = first_m + r % gsize;
+    tn = r / gsize;
+}
+
+template <int FMT>
+__device__ __forceinline__ v4f mfma16(uint4 a, uint4 b, v4f c) {
+    if constexpr (FMT == kFmtBf16)
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a),
+                                                       __builtin_bit_cast(v8bf, b), c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(v8h, a),
+                                                      __builtin_bit_cast(v8h, b), c, 0, 0, 0);
+}
+
+// ------------------------------------------------------------ 16-bit form
+constexpr int BK16 = 32;
+constexpr int ST16 = BK16 + 8;   // LDS row stride (elements) of a staged row
+
+template <int FMT>
+__global__ __launch_bounds__(256, 2) void lp_schur16_kernel(
+    int64_t M, int64_t N, int K, const uint16_t *__restrict__ LT, int64_t ldlt,
+    const uint16_t *__restrict__ U, int64_t ldu, uint16_t *__restrict__ C, int64_t ldc,
+    int tiles_m, int tiles_n) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[2][TM * ST16];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][TN * ST16];
+
+    int tm, tn;
+    tile_of(blockIdx.x, tiles_m, tiles_n, tm, tn);
+    const int64_t row0 = (int64_t)tm * TM, col0 = (int64_t)tn * TN;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int li = lane & 15, lg = lane >> 4;
+
+    v4f acc[8][4];
+#pragma unroll
+    for (int bi = 0; bi < 8; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj) {
+            const int64_t r = row0 + wm * 128 + bi * 16 + 4 * lg;
+            const int64_t c = col0 + wn * 64 + bj * 16 + li;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                acc[bi][bj][e] =
+                    (r + e < M && c < N) ? lp_to_f32<FMT>(C[(size_t)(r + e) + (size_t)c * ldc]) : 0.0f;
+        }
+
+    // staging: A row t of the tile (4 x 16 B), B column t/2, half t%2 (2 x 16 B)
+    const int64_t a_row = row0 + tid;
+    const bool a_ok = a_row < M;
+    const int64_t b_col = col0 + (tid >> 1);
+    const bool b_ok = b_col < N;
+    const int b_k = (tid & 1) * 16;
+    uint4 ra[4], rb[2];
+    auto load = [&](int k0) {
+        const uint4 *pa = reinterpret_cast<const uint4 *>(LT + (size_t)a_row * ldlt + k0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ra[q] = a_ok ? pa[q] : make_uint4(0, 0, 0, 0);
+        const uint4 *pb = reinterpret_cast<const uint4 *>(U + (size_t)b_col * ldu + k0 + b_k);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) rb[q] = b_ok ? pb[q] : make_uint4(0, 0, 0, 0);
+    };
+    auto store = [&](int buf) {
+        uint4 *da = reinterpret_cast<uint4 *>(&As[buf][tid * ST16]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            uint4 v = ra[q];   // negate: flip the sign bit of every element
+            v.x ^= 0x80008000u;
+            v.y ^= 0x80008000u;
+            v.z ^= 0x80008000u;
+            v.w ^= 0x80008000u;
+            da[q] = v;
+        }
+        uint4 *db = reinterpret_cast<uint4 *>(&Bs[buf][(tid >> 1) * ST16 + b_k]);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) db[q] = rb[q];
+    };
+
+    const int nk = K / BK16;
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int buf = kt & 1;
+        if (kt + 1 < nk) load((kt + 1) * BK16);
+        uint4 a[8], b[4];
+#pragma unroll
+        for (int bi = 0; bi < 8; ++bi)
+            a[bi] = *reinterpret_cast<const uint4 *>(
+                &As[buf][(wm * 128 + bi * 16 + li) * ST16 + lg * 8]);
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj)
+            b[bj] = *reinterpret_cast<const uint4 *>(
+                &Bs[buf][(wn * 64 + bj * 16 + li) * ST16 + lg * 8]);
+#pragma unroll
+        for (int bi = 0; bi < 8; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = mfma16<FMT>(a[bi], b[bj], acc[bi][bj]);
+        if (kt + 1 < nk) store(buf ^ 1);
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int bi = 0; bi < 8; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj) {
+            const int64_t r = row0 + wm * 128 + bi * 16 + 4 * lg;
+            const int64_t c = col0 + wn * 64 + bj * 16 + li;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (r + e < M && c < N)
+                    C[(size_t)(r + e) + (size_t)c * ldc] = f32_to_lp<FMT>(acc[bi][bj][e]);
+        }
+}
+
+// ------------------------------------------------------------ FP8 form
+constexpr int BK8 = 128;
+constexpr int ST8 = BK8 + 16;   // bytes per staged row
+
+template <int FMT>
+__global__ __launch_bounds__(256, 2) void lp_schur8_kernel(
+    int64_t M, int64_t N, int K, const uint8_t *__restrict__ LTq, const float *__restrict__ sL,
+    const uint8_t *__restrict__ Uq, const float *__restrict__ sU, int tile,
+    uint16_t *__restrict__ C, int64_t ldc, int tiles_m, int tiles_n) {
+    __shared__ __attribute__((aligned(16))) uint8_t As[TM * ST8];
+    __shared__ __attribute__((aligned(16))) uint8_t Bs[TN * ST8];
+
+    int tm, tn;
+    tile_of(blockIdx.x, tiles_m, tiles_n, tm, tn);
+    const int64_t row0 = (int64_t)tm * TM, col0 = (int64_t)tn * TN;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int li = lane & 15, lg = lane >> 4;
+
+    v4f acc[8][4];
+#pragma unroll
+    for (int bi = 0; bi < 8; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+
+    // staging: A row t (8 x 16 B = 128 k), B column t/2, half t%2 (4 x 16 B)
+    const int64_t a_row = row0 + tid;
+    const bool a_ok = a_row < M;
+    const int64_t b_col = col0 + (tid >> 1);
+    const bool b_ok = b_col < N;
+    const int b_k = (tid & 1) * 64;
+    uint4 ra[8], rb[4];
+    auto load = [&](int k0) {
+        const uint4 *pa = reinterpret_cast<const uint4 *>(LTq + (size_t)a_row * K + k0);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) ra[q] = a_ok ? pa[q] : make_uint4(0, 0, 0, 0);
+        const uint4 *pb = reinterpret_cast<const uint4 *>(Uq + (size_t)b_col * K + k0 + b_k);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rb[q] = b_ok ? pb[q] : make_uint4(0, 0, 0, 0);
+    };
+    auto store = [&]() {
+        uint4 *da = reinterpret_cast<uint4 *>(&As[tid * ST8]);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) da[q] = ra[q];
+        uint4 *db = reinterpret_cast<uint4 *>(&Bs[(tid >> 1) * ST8 + b_k]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) db[q] = rb[q];
+    };
+
+    const int nk = K / BK8;
+    load(0);
+    for (int kt = 0; kt < nk; ++kt) {
+        store();
+        __syncthreads();
+        if (kt + 1 < nk) load((kt + 1) * BK8);
+        v8i a[8], b[4];
+#pragma unroll
+        for (int bi = 0; bi < 8; ++bi) {
+            const uint4 *p = reinterpret_cast<const uint4 *>(
+                &As[(wm * 128 + bi * 16 + li) * ST8 + lg * 32]);
+            const uint4 lo = p[0], hi = p[1];
+            a[bi] = v8i{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w,
+                        (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+        }
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj) {
+            const uint4 *p = reinterpret_cast<const uint4 *>(
+                &Bs[(wn * 64 + bj * 16 + li) * ST8 + lg * 32]);
+            const uint4 lo = p[0], hi = p[1];
+            b[bj] = v8i{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w,
+                        (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+        }
+#pragma unroll
+        for (int bi = 0; bi < 8; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj)
+                acc[bi][bj] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+                    a[bi], b[bj], acc[bi][bj], 0, 0, 0, 127, 0, 127);
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int bi = 0; bi < 8; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj) {
+            const int64_t r = row0 + wm * 128 + bi * 16 + 4 * lg;
+            const int64_t c = col0 + wn * 64 + bj * 16 + li;
+            if (c >= N) continue;
+            const float su = sU[c / tile];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                if (r + e >= M) continue;
+                const float sl = sL[(r + e) / tile];
+                float upd = acc[bi][bj][e] * sl;   // exact: power-of-two scales
+                upd = upd * su;
+                uint16_t *p = &C[(size_t)(r + e) + (size_t)c * ldc];
+                *p = f32_to_lp<FMT>(lp_to_f32<FMT>(*p) - upd);
+            }
+        }
+}
+
+}  // namespace
+
+namespace mxlu {
+
+int lp_schur_update(int fmt, int64_t M, int64_t N, int K, const uint16_t *LT, int64_t ldlt,
+                    const uint16_t *U, int64_t ldu, uint16_t *C, int64_t ldc, hipStream_t s) {
+    if (M <= 0 || N <= 0 || K <= 0) return 0;
+    if (K % BK16 || ldlt % 8 || ldu % 8 || ((uintptr_t)LT | (uintptr_t)U) % 16) {
+        set_error_msg("lp_schur_update: K, leading dimensions or alignment not multiples of 8/16");
+        return MXLU_E_NOMEM;
+    }
+    const int64_t tiles_m = (M + TM - 1) / TM, tiles_n = (N + TN - 1) / TN;
+    const dim3 grid((unsigned)(tiles_m * tiles_n));
+    if (fmt == kFmtBf16)
+        hipLaunchKernelGGL(lp_schur16_kernel<kFmtBf16>, grid, dim3(256), 0, s, M, N, K, LT, ldlt,
+                           U, ldu, C, ldc, (int)tiles_m, (int)tiles_n);
+    else
+        hipLaunchKernelGGL(lp_schur16_kernel<kFmtFp16>, grid, dim3(256), 0, s, M, N, K, LT, ldlt,
+                           U, ldu, C, ldc, (int)tiles_m, (int)tiles_n);
+    MXLU_LAUNCH_CHECK();
+    return 0;
+}
+
+int lp_schur_update_fp8(int fmt, int64_t M, int64_t N, int K, const uint8_t *LTq,
+                        const float *sL, const uint8_t *Uq, const float *sU, int tile,
+                        uint16_t *C, int64_t ldc, hipStream_t s) {
+    if (M <= 0 || N <= 0 || K <= 0) return 0;
+    if (K % BK8 || ((uintptr_t)LTq | (uintptr_t)Uq) % 16) {
+        set_error_msg("lp_schur_update_fp8: K must be a multiple of 128");
+        return MXLU_E_NOMEM;
+    }
+    const int64_t tiles_m = (M + TM - 1) / TM, tiles_n = (N + TN - 1) / TN;
+    const dim3 grid((unsigned)(tiles_m * tiles_n));
+    if (fmt == kFmtBf16)
+        hipLaunchKernelGGL(lp_schur8_kernel<kFmtBf16>, grid, dim3(256), 0, s, M, N, K, LTq, sL,
+                           Uq, sU, tile, C, ldc, (int)tiles_m, (int)tiles_n);
+    else
+        hipLaunchKernelGGL(lp_schur8_kernel<kFmtFp16>, grid, dim3(256), 0, s, M, N, K, LTq, sL,
+                           Uq, sU, tile, C, ldc, (int)tiles_m, (int)tiles_n);
+    MXLU_LAUNCH_CHECK();
+    return 0;
+}
+
+}  // namespace mxlu

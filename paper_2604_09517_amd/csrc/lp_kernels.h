@@ -1,0 +1,48 @@
+// Launchers of the low-precision LU kernels (internal interface).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mxlu {
+
+constexpr int kLpIb = 32;   // inner block width of the FP32 panel factorization
+
+// F (rows x cols, 16-bit) <- round-to-nearest-even of A (FP64).
+int lp_convert(int fmt, int64_t rows, int64_t cols, const double *A, int64_t lda, uint16_t *F,
+               int64_t ldf, hipStream_t s);
+// P (FP32) <- F (16-bit), exact; F <- round(P).
+int lp_load_f32(int fmt, int64_t rows, int64_t cols, const uint16_t *F, int64_t ldf, float *P,
+                int64_t ldp, hipStream_t s);
+int lp_store_f32(int fmt, int64_t rows, int64_t cols, const float *P, int64_t ldp, uint16_t *F,
+                 int64_t ldf, hipStream_t s);
+// C -= A B in FP32 with the elimination order of terms.
+int gemm_f32_sub(int64_t M, int64_t N, int64_t K, const float *A, int64_t lda, const float *B,
+                 int64_t ldb, float *C, int64_t ldc, hipStream_t s);
+// No-pivot FP32 factorization of the m x kb panel P in place; the first
+// exactly-zero pivot (col_base + column, 1-based) goes to *info if still 0.
+int lp_panel_factor_nopiv(int64_t m, int kb, float *P, int64_t ldp, int *info, int64_t col_base,
+                          hipStream_t s);
+// B (kb x ncols) <- L^-1 B, L unit lower (FP32), any kb.
+int trsm_f32_llnu(int64_t kb, int64_t ncols, const float *L, int64_t ldl, float *B, int64_t ldb,
+                  hipStream_t s);
+// F panel <- round(P); LT (kb x (m - kb)) <- the L21 rows transposed (optional).
+int lp_panel_store(int fmt, int64_t m, int kb, const float *P, int64_t ldp, uint16_t *F,
+                   int64_t ldf, uint16_t *LT, int64_t ldlt, hipStream_t s);
+// FP8 operands of the trailing update with power-of-two tile scales.
+int lp_quant_l21(int fmt, int64_t mt, int kb, int tile, const uint16_t *L21, int64_t ldf,
+                 uint8_t *LTq, float *sL, hipStream_t s);
+int lp_quant_u12(int fmt, int64_t nt, int kb, int tile, const uint16_t *U12, int64_t ldf,
+                 uint8_t *Uq, float *sU, hipStream_t s);
+
+// Trailing update on the matrix cores:
+//   16-bit: C <- round(fp32(C) - LT^T U) with LT (K x M), U (K x N) 16-bit
+//   FP8:    C <- round(fp32(C) - (LTq^T Uq) sL sU), operands e4m3fn
+int lp_schur_update(int fmt, int64_t M, int64_t N, int K, const uint16_t *LT, int64_t ldlt,
+                    const uint16_t *U, int64_t ldu, uint16_t *C, int64_t ldc, hipStream_t s);
+int lp_schur_update_fp8(int fmt, int64_t M, int64_t N, int K, const uint8_t *LTq,
+                        const float *sL, const uint8_t *Uq, const float *sU, int tile,
+                        uint16_t *C, int64_t ldc, hipStream_t s);
+
+}  // namespace mxlu

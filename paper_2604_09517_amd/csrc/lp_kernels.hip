@@ -1,0 +1,480 @@
+// Kernels of the low-precision LU (Sec. III-A.2: factorization and trailing
+// updates in reduced precision, no pivoting) other than the MFMA update.
+//
+// Storage F holds the matrix in bf16 or fp16 (raw 16-bit words).  Per panel
+// step at column k0 (width kb, m = n - k0 rows):
+//   * the m x kb panel is copied to an FP32 buffer P and factored there in
+//     FP32 (inner blocks of kLpIb columns: diagonal block + row TRSM + column
+//     TRSM in one kernel, then an FP32 update of the panel's remaining
+//     columns).  Every element accumulates its terms in ascending k with one
+//     fused multiply-add per term and the division last, i.e. exactly the
+//     operation sequence of unblocked elimination of the panel in FP32;
+//   * the panel is rounded back to F; the L21 part is also written
+//     transposed (k contiguous), the operand layout of the MFMA update;
+//   * U12 = L11^-1 A12 in FP32 with the unrounded L11 of P, rounded to F;
+//   * FP8 variant: L21 and U12 are quantised per tile to e4m3fn with
+//     power-of-two scales.
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+#include "lp_common.h"
+#include "lp_kernels.h"
+
+namespace {
+
+using namespace mxlu;
+
+// ---------------------------------------------------------------- convert
+template <int FMT>
+__global__ void convert_kernel(int64_t rows, int64_t cols, const double *__restrict__ A,
+                               int64_t lda, uint16_t *__restrict__ F, int64_t ldf) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows) return;
+    for (int64_t j = blockIdx.y; j < cols; j += gridDim.y)
+        F[(size_t)i + (size_t)j * (size_t)ldf] = f64_to_lp<FMT>(MXLU_AT(A, i, j, lda));
+}
+
+template <int FMT>
+__global__ void lp_to_f32_kernel(int64_t rows, int64_t cols, const uint16_t *__restrict__ F,
+                                 int64_t ldf, float *__restrict__ P, int64_t ldp) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows) return;
+    for (int64_t j = blockIdx.y; j < cols; j += gridDim.y)
+        P[(size_t)i + (size_t)j * (size_t)ldp] = lp_to_f32<FMT>(F[(size_t)i + (size_t)j * (size_t)ldf]);
+}
+
+template <int FMT>
+__global__ void f32_to_lp_kernel(int64_t rows, int64_t cols, const float *__restrict__ P,
+                                 int64_t ldp, uint16_t *__restrict__ F, int64_t ldf) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows) return;
+    for (int64_t j = blockIdx.y; j < cols; j += gridDim.y)
+        F[(size_t)i + (size_t)j * (size_t)ldf] = f32_to_lp<FMT>(P[(size_t)i + (size_t)j * (size_t)ldp]);
+}
+
+// ---------------------------------------------------------------- panel leaf
+// Inner block [c, c+ib) of the FP32 panel P (m x kb, leading dimension ldp).
+// Every workgroup factors the ib x ib diagonal block in LDS (no pivoting);
+// workgroups [0, nrow) then finish rows c+ib.. of the block columns (row
+// TRSM with U of the diagonal block), workgroups [nrow, nrow+ncol) finish
+// rows c..c+ib of the panel columns right of the block (unit-lower TRSM).
+__global__ __launch_bounds__(256) void lp_leaf_nopiv_kernel(int m, int kb, int c, int ib,
+                                                            float *__restrict__ P, int64_t ldp,
+                                                            int nrow, int *__restrict__ info,
+                                                            int64_t col_base) {
+    __shared__ float D[kLpIb][kLpIb + 1];
+    const int tid = threadIdx.x;
+    for (int t = tid; t < ib * ib; t += 256) {
+        const int i = t % ib, j = t / ib;
+        D[i][j] = P[(size_t)(c + i) + (size_t)(c + j) * ldp];
+    }
+    __syncthreads();
+    for (int j = 0; j < ib; ++j) {
+        const float piv = D[j][j];
+        // an exactly zero pivot leaves its column unscaled (it is reported)
+        if (tid > j && tid < ib && piv != 0.0f) D[tid][j] = D[tid][j] / piv;
+        __syncthreads();
+        const int w = ib - j - 1;
+        for (int t = tid; t < w * w; t += 256) {
+            const int i = j + 1 + t % w, col = j + 1 + t / w;
+            D[i][col] = fmaf(-D[i][j], D[j][col], D[i][col]);
+        }
+        __syncthreads();
+    }
+    if (blockIdx.x == 0) {
+        for (int t = tid; t < ib * ib; t += 256) {
+            const int i = t % ib, j = t / ib;
+            P[(size_t)(c + i) + (size_t)(c + j) * ldp] = D[i][j];
+        }
+        if (tid == 0 && info) {
+            for (int j = 0; j < ib; ++j)
+                if (D[j][j] == 0.0f) {
+                    atomicCAS(info, 0, (int)(col_base + c + j + 1));
+                    break;
+                }
+        }
+    }
+    if ((int)blockIdx.x < nrow) {
+        const int r = c + ib + blockIdx.x * 256 + tid;
+        if (r >= m) return;
+        float x[kLpIb];
+#pragma unroll
+        for (int k = 0; k < kLpIb; ++k)
+            x[k] = (k < ib) ? P[(size_t)r + (size_t)(c + k) * ldp] : 0.0f;
+#pragma unroll
+        for (int k = 0; k < kLpIb; ++k) {
+            if (k >= ib) break;
+            if (D[k][k] != 0.0f) x[k] = x[k] / D[k][k];
+#pragma unroll
+            for (int col = k + 1; col < kLpIb; ++col)
+                if (col < ib) x[col] = fmaf(-x[k], D[k][col], x[col]);
+        }
+#pragma unroll
+        for (int k = 0; k < kLpIb; ++k)
+            if (k < ib) P[(size_t)r + (size_t)(c + k) * ldp] = x[k];
+    } else {
+        const int q = c + ib + ((int)blockIdx.x - nrow) * 256 + tid;
+        if (q >= kb) return;
+        float y[kLpIb];
+#pragma unroll
+        for (int k = 0; k < kLpIb; ++k)
+            y[k] = (k < ib) ? P[(size_t)(c + k) + (size_t)q * ldp] : 0.0f;
+#pragma unroll
+        for (int k = 0; k < kLpIb; ++k) {
+            if (k >= ib) break;
+#pragma unroll
+            for (int i = k + 1; i < kLpIb; ++i)
+                if (i < ib) y[i] = fmaf(-D[i][k], y[k], y[i]);
+        }
+#pragma unroll
+        for (int k = 0; k < kLpIb; ++k)
+            if (k < ib) P[(size_t)(c + k) + (size_t)q * ldp] = y[k];
+    }
+}
+
+// ---------------------------------------------------------------- FP32 GEMM
+// C (M x N) -= A (M x K) B (K x N), FP32, one fused multiply-add per term in
+// ascending k starting from C (the elimination order).  64 x 64 tiles,
+// 256 threads, 4 x 4 outputs per thread, K staged in chunks of 16.
+__global__ __launch_bounds__(256) void gemm_f32_sub_kernel(int64_t M, int64_t N, int64_t K,
+                                                           const float *__restrict__ A,
+                                                           int64_t lda,
+                                                           const float *__restrict__ B,
+                                                           int64_t ldb, float *__restrict__ C,
+                                                           int64_t ldc, int tiles_m) {
+    __shared__ float As[16][64 + 1];
+    __shared__ float Bs[16][64 + 1];
+    const int tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
+    const int64_t row0 = (int64_t)tm * 64, col0 = (int64_t)tn * 64;
+    const int tid = threadIdx.x;
+    const int tr = tid & 15, tc = tid >> 4;
+    float acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int64_t r = row0 + tr + 16 * a, cc = col0 + tc + 16 * b;
+            acc[a][b] = (r < M && cc < N) ? C[(size_t)r + (size_t)cc * ldc] : 0.0f;
+        }
+    for (int64_t k0 = 0; k0 < K; k0 += 16) {
+        for (int t = tid; t < 16 * 64; t += 256) {
+            const int i = t % 64, k = t / 64;
+            const int64_t r = row0 + i, kk = k0 + k;
+            As[k][i] = (r < M && kk < K) ? A[(size_t)r + (size_t)kk * lda] : 0.0f;
+        }
+        for (int t = tid; t < 16 * 64; t += 256) {
+            const int k = t % 16, j = t / 16;
+            const int64_t cc = col0 + j, kk = k0 + k;
+            Bs[k][j] = (cc < N && kk < K) ? B[(size_t)kk + (size_t)cc * ldb] : 0.0f;
+        }
+        __syncthreads();
+        const int kc = (int)((K - k0 < 16) ? K - k0 : 16);
+        for (int k = 0; k < kc; ++k) {
+            float av[4], bv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) av[a] = As[k][tr + 16 * a];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) bv[b] = Bs[k][tc + 16 * b];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] = fmaf(-av[a], bv[b], acc[a][b]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int64_t r = row0 + tr + 16 * a, cc = col0 + tc + 16 * b;
+            if (r < M && cc < N) C[(size_t)r + (size_t)cc * ldc] = acc[a][b];
+        }
+}
+
+// ---------------------------------------------------------------- FP32 TRSM
+// B (kb x ncols) <- L^-1 B, L unit lower kb x kb (kb <= 256), thread per row,
+// 16 columns per workgroup, one LDS barrier per step.
+__global__ __launch_bounds__(256) void trsm_f32_llnu_kernel(int kb, int64_t ncols,
+                                                            const float *__restrict__ L,
+                                                            int64_t ldl, float *__restrict__ B,
+                                                            int64_t ldb) {
+    __shared__ float xs[2][16];
+    const int i = threadIdx.x;
+    const int64_t c0 = (int64_t)blockIdx.x * 16;
+    const int nc = (int)((ncols - c0 < 16) ? ncols - c0 : 16);
+    float b[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+        b[c] = (i < kb && c < nc) ? B[(size_t)i + (size_t)(c0 + c) * ldb] : 0.0f;
+    float lnext = (i < kb && i > 0) ? L[(size_t)i] : 0.0f;
+    for (int k = 0; k < kb; ++k) {
+        const float l = lnext;
+        lnext = (k + 1 < kb && i < kb && i > k + 1) ? L[(size_t)i + (size_t)(k + 1) * ldl] : 0.0f;
+        if (i == k)
+#pragma unroll
+            for (int c = 0; c < 16; ++c) xs[k & 1][c] = b[c];
+        __syncthreads();
+        if (i > k && i < kb)
+#pragma unroll
+            for (int c = 0; c < 16; ++c) b[c] = fmaf(-l, xs[k & 1][c], b[c]);
+    }
+    if (i < kb)
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+            if (c < nc) B[(size_t)i + (size_t)(c0 + c) * ldb] = b[c];
+}
+
+// ---------------------------------------------------------------- store
+// F[i, c] <- round(P[i, c]) for the m x kb panel; for rows i >= kb also the
+// transposed copy LT[c, i - kb] (leading dimension ldlt) when LT is given.
+// 64 x 64 tiles through LDS so that both writes are coalesced.
+template <int FMT>
+__global__ __launch_bounds__(256) void panel_store_kernel(int64_t m, int kb,
+                                                          const float *__restrict__ P,
+                                                          int64_t ldp, uint16_t *__restrict__ F,
+                                                          int64_t ldf, uint16_t *__restrict__ LT,
+                                                          int64_t ldlt, int tiles_m) {
+    __shared__ uint16_t T[64][64 + 2];
+    const int tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
+    const int64_t r0 = (int64_t)tm * 64;
+    const int c0 = tn * 64;
+    const int tid = threadIdx.x;
+    for (int t = tid; t < 64 * 64; t += 256) {
+        const int i = t % 64, j = t / 64;
+        const int64_t r = r0 + i;
+        const int c = c0 + j;
+        uint16_t h = 0;
+        if (r < m && c < kb) {
+            h = f32_to_lp<FMT>(P[(size_t)r + (size_t)c * ldp]);
+            F[(size_t)r + (size_t)c * ldf] = h;
+        }
+        T[i][j] = h;
+    }
+    if (!LT) return;
+    __syncthreads();
+    for (int t = tid; t < 64 * 64; t += 256) {
+        const int j = t % 64, i = t / 64;
+        const int64_t r = r0 + i;
+        const int c = c0 + j;
+        if (r >= kb && r < m && c < kb) LT[(size_t)c + (size_t)(r - kb) * ldlt] = T[i][j];
+    }
+}
+
+// ---------------------------------------------------------------- FP8
+// L21 (rows [0, mt) of the stored panel below the diagonal block, kb columns)
+// -> LTq (kb x mt bytes, k contiguous) with one power-of-two scale per tile of
+// `tile` rows.  One workgroup per row tile: amax pass, then quantise through
+// LDS in chunks of 64 columns.
+template <int FMT>
+__global__ __launch_bounds__(256) void quant_l21_kernel(int64_t mt, int kb, int tile,
+                                                        const uint16_t *__restrict__ L21,
+                                                        int64_t ldf, uint8_t *__restrict__ LTq,
+                                                        float *__restrict__ sL) {
+    __shared__ float red[256];
+    __shared__ uint8_t T[64][256 + 4];
+    const int64_t r0 = (int64_t)blockIdx.x * tile;
+    const int rows = (int)((mt - r0 < tile) ? mt - r0 : tile);
+    const int tid = threadIdx.x;
+    float amax = 0.0f;
+    for (int c = 0; c < kb; ++c)
+        for (int i = tid; i < rows; i += 256)
+            amax = fmaxf(amax, fabsf(lp_to_f32<FMT>(L21[(size_t)(r0 + i) + (size_t)c * ldf])));
+    red[tid] = amax;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) red[tid] = fmaxf(red[tid], red[tid + s]);
+        __syncthreads();
+    }
+    const float sc = fp8_tile_scale(red[0]);
+    if (tid == 0) sL[blockIdx.x] = sc;
+    const float inv = 1.0f / sc;   // exact: power of two
+    for (int c0 = 0; c0 < kb; c0 += 64) {
+        const int cw = (kb - c0 < 64) ? kb - c0 : 64;
+        __syncthreads();
+        for (int t = tid; t < cw * rows; t += 256) {
+            const int i = t % rows, j = t / rows;
+            T[j][i] = f32_to_e4m3(lp_to_f32<FMT>(L21[(size_t)(r0 + i) + (size_t)(c0 + j) * ldf]) * inv);
+        }
+        __syncthreads();
+        for (int t = tid; t < cw * rows; t += 256) {
+            const int j = t % cw, i = t / cw;
+            LTq[(size_t)(c0 + j) + (size_t)(r0 + i) * kb] = T[j][i];
+        }
+    }
+}
+
+// U12 (kb x nt, stored) -> Uq (kb x nt bytes, leading dimension kb), one
+// scale per tile of `tile` columns.
+template <int FMT>
+__global__ __launch_bounds__(256) void quant_u12_kernel(int64_t nt, int kb, int tile,
+                                                        const uint16_t *__restrict__ U12,
+                                                        int64_t ldf, uint8_t *__restrict__ Uq,
+                                                        float *__restrict__ sU) {
+    __shared__ float red[256];
+    const int64_t q0 = (int64_t)blockIdx.x * tile;
+    const int cols = (int)((nt - q0 < tile) ? nt - q0 : tile);
+    const int tid = threadIdx.x;
+    float amax = 0.0f;
+    for (int j = 0; j < cols; ++j)
+        for (int k = tid; k < kb; k += 256)
+            amax = fmaxf(amax, fabsf(lp_to_f32<FMT>(U12[(size_t)k + (size_t)(q0 + j) * ldf])));
+    red[tid] = amax;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) red[tid] = fmaxf(red[tid], red[tid + s]);
+        __syncthreads();
+    }
+    const float sc = fp8_tile_scale(red[0]);
+    if (tid == 0) sU[blockIdx.x] = sc;
+    const float inv = 1.0f / sc;
+    for (int j = 0; j < cols; ++j)
+        for (int k = tid; k < kb; k += 256)
+            Uq[(size_t)k + (size_t)(q0 + j) * kb] =
+                f32_to_e4m3(lp_to_f32<FMT>(U12[(size_t)k + (size_t)(q0 + j) * ldf]) * inv);
+}
+
+dim3 grid2(int64_t rows, int64_t cols) {
+    return dim3((unsigned)((rows + 255) / 256), (unsigned)(cols < 4096 ? (cols > 0 ? cols : 1) : 4096));
+}
+
+}  // namespace
+
+namespace mxlu {
+
+int lp_convert(int fmt, int64_t rows, int64_t cols, const double *A, int64_t lda, uint16_t *F,
+               int64_t ldf, hipStream_t s) {
+    if (rows <= 0 || cols <= 0) return 0;
+    if (fmt == kFmtBf16)
+        hipLaunchKernelGGL(convert_kernel<kFmtBf16>, grid2(rows, cols), dim3(256), 0, s, rows, cols,
+                           A, lda, F, ldf);
+    else
+        hipLaunchKernelGGL(convert_kernel<kFmtFp16>, grid2(rows, cols), dim3(256), 0, s, rows, cols,
+                           A, lda, F, ldf);
+    MXLU_LAUNCH_CHECK();
+    return 0;
+}
+
+int lp_load_f32(int fmt, int64_t rows, int64_t cols, const uint16_t *F, int64_t ldf, float *P,
+                int64_t ldp, hipStream_t s) {
+    if (rows <= 0 || cols <= 0) return 0;
+    if (fmt == kFmtBf16)
+        hipLaunchKernelGGL(lp_to_f32_kernel<kFmtBf16>, grid2(rows, cols), dim3(256), 0, s, rows,
+                           cols, F, ldf, P, ldp);
+    else
+        hipLaunchKernelGGL(lp_to_f32_kernel<kFmtFp16>, grid2(rows, cols), dim3(256), 0, s, rows,
+                           cols, F, ldf, P, ldp);
+    MXLU_LAUNCH_CHECK();
+    return 0;
+}
+
+int lp_store_f32(int fmt, int64_t rows, int64_t cols, const float *P, int64_t ldp, uint16_t *F,
+                 int64_t ldf, hipStream_t s) {
+    if (rows <= 0 || cols <= 0) return 0;
+    if (fmt == kFmtBf16)
+        hipLaunchKernelGGL(f32_to_lp_kernel<kFmtBf16>, grid2(rows, cols), dim3(256), 0, s, rows,
+                           cols, P, ldp, F, ldf);
+    else
+        hipLaunchKernelGGL(f32_to_lp_kernel<kFmtFp16>, grid2(rows, cols), dim3(256), 0, s, rows,
+                           cols, P, ldp, F, ldf);
+    MXLU_LAUNCH_CHECK();
+    return 0;
+}
+
+int gemm_f32_sub(int64_t M, int64_t N, int64_t K, const float *A, int64_t lda, const float *B,
+                 int64_t ldb, float *C, int64_t ldc, hipStream_t s) {
+    if (M <= 0 || N <= 0 || K <= 0) return 0;
+    const int64_t tm = (M + 63) / 64, tn = (N + 63) / 64;
+    if (tm * tn > 0x7fffffff) {
+        set_error_msg("gemm_f32_sub: grid too large");
+        return MXLU_E_NOMEM;
+    }
+    hipLaunchKernelGGL(gemm_f32_sub_kernel, dim3((unsigned)(tm * tn)), dim3(256), 0, s, M, N, K,
+                       A, lda, B, ldb, C, ldc, (int)tm);
+    MXLU_LAUNCH_CHECK();
+    return 0;
+}
+
+int lp_panel_factor_nopiv(int64_t m, int kb, float *P, int64_t ldp, int *info, int64_t col_base,
+                          hipStream_t s) {
+    for (int c = 0; c < kb; c += kLpIb) {
+        const int ib = (kb - c < kLpIb) ? kb - c : kLpIb;
+        const int64_t rows_below = m - c - ib;
+        const int nrow = (int)((rows_below + 255) / 256);
+        const int ncol = (kb - c - ib + 255) / 256;
+        const int grid = (nrow + ncol > 0) ? nrow + ncol : 1;
+        hipLaunchKernelGGL(lp_leaf_nopiv_kernel, dim3(grid), dim3(256), 0, s, (int)m, kb, c, ib, P,
+                           ldp, nrow, info, col_base);
+        MXLU_LAUNCH_CHECK();
+        if (c + ib < kb && rows_below > 0) {
+            int rc = gemm_f32_sub(rows_below, kb - c - ib, ib, P + (size_t)(c + ib) + (size_t)c * ldp,
+                                  ldp, P + (size_t)c + (size_t)(c + ib) * ldp, ldp,
+                                  P + (size_t)(c + ib) + (size_t)(c + ib) * ldp, ldp, s);
+            if (rc) return rc;
+        }
+    }
+    return 0;
+}
+
+int trsm_f32_llnu(int64_t kb, int64_t ncols, const float *L, int64_t ldl, float *B, int64_t ldb,
+                  hipStream_t s) {
+    for (int64_t b0 = 0; b0 < kb; b0 += 256) {
+        const int bb = (int)((kb - b0 < 256) ? kb - b0 : 256);
+        hipLaunchKernelGGL(trsm_f32_llnu_kernel, dim3((unsigned)((ncols + 15) / 16)), dim3(256), 0,
+                           s, bb, ncols, L + (size_t)b0 + (size_t)b0 * ldl, ldl, B + b0, ldb);
+        MXLU_LAUNCH_CHECK();
+        if (b0 + bb < kb) {
+            int rc = gemm_f32_sub(kb - b0 - bb, ncols, bb, L + (size_t)(b0 + bb) + (size_t)b0 * ldl,
+                                  ldl, B + b0, ldb, B + b0 + bb, ldb, s);
+            if (rc) return rc;
+        }
+    }
+    return 0;
+}
+
+int lp_panel_store(int fmt, int64_t m, int kb, const float *P, int64_t ldp, uint16_t *F,
+                   int64_t ldf, uint16_t *LT, int64_t ldlt, hipStream_t s) {
+    if (m <= 0 || kb <= 0) return 0;
+    const int64_t tm = (m + 63) / 64, tn = (kb + 63) / 64;
+    if (fmt == kFmtBf16)
+        hipLaunchKernelGGL(panel_store_kernel<kFmtBf16>, dim3((unsigned)(tm * tn)), dim3(256), 0,
+                           s, m, kb, P, ldp, F, ldf, LT, ldlt, (int)tm);
+    else
+        hipLaunchKernelGGL(panel_store_kernel<kFmtFp16>, dim3((unsigned)(tm * tn)), dim3(256), 0,
+                           s, m, kb, P, ldp, F, ldf, LT, ldlt, (int)tm);
+    MXLU_LAUNCH_CHECK();
+    return 0;
+}
+
+int lp_quant_l21(int fmt, int64_t mt, int kb, int tile, const uint16_t *L21, int64_t ldf,
+                 uint8_t *LTq, float *sL, hipStream_t s) {
+    if (mt <= 0 || kb <= 0) return 0;
+    if (tile > 256) {
+        set_error_msg("lp_quant_l21: scale tile larger than 256 rows");
+        return MXLU_E_NOMEM;
+    }
+    const unsigned grid = (unsigned)((mt + tile - 1) / tile);
+    if (fmt == kFmtBf16)
+        hipLaunchKernelGGL(quant_l21_kernel<kFmtBf16>, dim3(grid), dim3(256), 0, s, mt, kb, tile,
+                           L21, ldf, LTq, sL);
+    else
+        hipLaunchKernelGGL(quant_l21_kernel<kFmtFp16>, dim3(grid), dim3(256), 0, s, mt, kb, tile,
+                           L21, ldf, LTq, sL);
+    MXLU_LAUNCH_CHECK();
+    return 0;
+}
+
+int lp_quant_u12(int fmt, int64_t nt, int kb, int tile, const uint16_t *U12, int64_t ldf,
+                 uint8_t *Uq, float *sU, hipStream_t s) {
+    if (nt <= 0 || kb <= 0) return 0;
+    const unsigned grid = (unsigned)((nt + tile - 1) / tile);
+    if (fmt == kFmtBf16)
+        hipLaunchKernelGGL(quant_u12_kernel<kFmtBf16>, dim3(grid), dim3(256), 0, s, nt, kb, tile,
+                           U12, ldf, Uq, sU);
+    else
+        hipLaunchKernelGGL(quant_u12_kernel<kFmtFp16>, dim3(grid), dim3(256), 0, s, nt, kb, tile,
+                           U12, ldf, Uq, sU);
+    MXLU_LAUNCH_CHECK();
+    return 0;
+}
+
+}  // namespace mxlu

@@ -12,111 +12,150 @@
 
 #include "common.h"
 #include "kernels.h"
+#include "lp_kernels.h"
+#include "profile.h"
 
 namespace {
 
 using namespace mxlu;
 
-struct FactorCtx {
-    int64_t n, lda;
-    double *A;
-    int32_t *ipiv;
+// Element-type specific TRSM / GEMM used by the panel recursion.
+template <typename T> struct PanelOps;
+template <> struct PanelOps<double> {
+    // B (kb x ncols) <- L^-1 B, L unit lower, any kb (diagonal blocks of 256)
+    static int trsm(int64_t kb, int64_t ncols, const double *L, int64_t ldl, double *B,
+                    int64_t ldb, hipStream_t s) {
+        for (int64_t b0 = 0; b0 < kb; b0 += 256) {
+            const int64_t bb = std::min<int64_t>(256, kb - b0);
+            MXLU_TRY(trsm_llnu_f64((int)bb, ncols, &MXLU_AT(L, b0, b0, ldl), ldl, B + b0, ldb, s));
+            if (b0 + bb < kb)
+                MXLU_TRY(gemm_f64_sub(kb - b0 - bb, ncols, bb, &MXLU_AT(L, b0 + bb, b0, ldl), ldl,
+                                 B + b0, ldb, B + b0 + bb, ldb, s));
+        }
+        return 0;
+    }
+    static int gemm(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
+                    const double *B, int64_t ldb, double *C, int64_t ldc, hipStream_t s) {
+        return gemm_f64_sub(M, N, K, A, lda, B, ldb, C, ldc, s);
+    }
+};
+template <> struct PanelOps<float> {
+    static int trsm(int64_t kb, int64_t ncols, const float *L, int64_t ldl, float *B,
+                    int64_t ldb, hipStream_t s) {
+        return trsm_f32_llnu(kb, ncols, L, ldl, B, ldb, s);
+    }
+    static int gemm(int64_t M, int64_t N, int64_t K, const float *A, int64_t lda, const float *B,
+                    int64_t ldb, float *C, int64_t ldc, hipStream_t s) {
+        return gemm_f32_sub(M, N, K, A, lda, B, ldb, C, ldc, s);
+    }
+};
+
+template <typename T>
+struct PanelCtx {
+    T *P;            // panel top-left element
+    int64_t ldp, m, kb, ibase;
+    int32_t *ipiv;   // indexed in the caller's numbering (ibase + local)
     PanelExchange ex;
     int *moves;
     hipStream_t s;
 };
 
-#define TRY(x)                 \
-    do {                       \
-        int rc_ = (x);         \
-        if (rc_) return rc_;   \
-    } while (0)
-
-// Recursive factorization of the panel columns [c, c + w) (absolute), rows
-// [c, n).  The panel spans columns [k0, k0 + kb); interchanges found inside
-// it are applied to its other columns as soon as they are known.
-int panel_rec(const FactorCtx &f, int64_t k0, int64_t kb, int64_t c, int64_t w) {
-    const int64_t n = f.n, lda = f.lda;
-    double *A = f.A;
+// Recursive factorization of the panel columns [c, c + w) (panel-local),
+// rows [c, m).  Interchanges found in a leaf are applied at once to the
+// panel's other columns; the halves are joined by a TRSM and a GEMM update,
+// so every element still takes its terms in ascending k (the order of
+// unblocked elimination).
+template <typename T>
+int panel_rec(const PanelCtx<T> &f, int64_t c, int64_t w) {
+    T *P = f.P;
+    const int64_t ldp = f.ldp;
     if (w <= kLeafW) {
-        TRY(panel_leaf_f64(n - c, (int)w, A, lda, c, f.ipiv, f.ex, f.s));
-        // the leaf's interchanges on the panel's other columns
-        TRY(laswp_f64(A, lda, f.ipiv, c, (int)w, k0, kb - w, c, w, f.moves, f.s));
+        MXLU_TRY(panel_leaf<T>(f.m - c, (int)w, P + (size_t)c + (size_t)c * ldp, ldp, f.ibase + c,
+                          f.ipiv, f.ex, f.s));
+        if (f.kb > w) {
+            MXLU_TRY(swap_compose(f.ipiv, f.ibase + c, (int)w, f.moves, f.s));
+            MXLU_TRY(swap_apply<T>(P, ldp, c, f.moves, 0, f.kb - w, c, w, f.s));
+        }
         return 0;
     }
     int64_t n1 = w / 2;
     n1 = std::max<int64_t>(kLeafW, (n1 / kLeafW) * kLeafW);
     const int64_t n2 = w - n1;
-    TRY(panel_rec(f, k0, kb, c, n1));
-    // A12 <- L11^-1 A12 ; A22 <- A22 - A21 A12   (inside the panel)
-    double *L11 = &MXLU_AT(A, c, c, lda);
-    double *A12 = &MXLU_AT(A, c, c + n1, lda);
-    for (int64_t b0 = 0; b0 < n1; b0 += 256) {
-        const int64_t bb = std::min<int64_t>(256, n1 - b0);
-        TRY(trsm_llnu_f64((int)bb, n2, &MXLU_AT(L11, b0, b0, lda), lda, &MXLU_AT(A12, b0, 0, lda),
-                          lda, f.s));
-        if (b0 + bb < n1)
-            TRY(gemm_f64_sub(n1 - b0 - bb, n2, bb, &MXLU_AT(L11, b0 + bb, b0, lda), lda,
-                             &MXLU_AT(A12, b0, 0, lda), lda, &MXLU_AT(A12, b0 + bb, 0, lda), lda,
-                             f.s));
-    }
-    TRY(gemm_f64_sub(n - c - n1, n2, n1, &MXLU_AT(A, c + n1, c, lda), lda, A12, lda,
-                     &MXLU_AT(A, c + n1, c + n1, lda), lda, f.s));
-    TRY(panel_rec(f, k0, kb, c + n1, n2));
+    MXLU_TRY(panel_rec(f, c, n1));
+    T *A12 = P + (size_t)c + (size_t)(c + n1) * ldp;
+    MXLU_TRY(PanelOps<T>::trsm(n1, n2, P + (size_t)c + (size_t)c * ldp, ldp, A12, ldp, f.s));
+    MXLU_TRY(PanelOps<T>::gemm(f.m - c - n1, n2, n1, P + (size_t)(c + n1) + (size_t)c * ldp, ldp, A12,
+                          ldp, P + (size_t)(c + n1) + (size_t)(c + n1) * ldp, ldp, f.s));
+    MXLU_TRY(panel_rec(f, c + n1, n2));
     return 0;
 }
 
-// Blocked U12 = L11^-1 A12 for any kb (diagonal blocks of 256 + GEMM).
-int trsm_block_row(double *A, int64_t lda, int64_t k0, int64_t kb, int64_t ncols,
-                   int64_t col0, hipStream_t s) {
-    for (int64_t b0 = 0; b0 < kb; b0 += 256) {
-        const int64_t bb = std::min<int64_t>(256, kb - b0);
-        TRY(trsm_llnu_f64((int)bb, ncols, &MXLU_AT(A, k0 + b0, k0 + b0, lda), lda,
-                          &MXLU_AT(A, k0 + b0, col0, lda), lda, s));
-        if (b0 + bb < kb)
-            TRY(gemm_f64_sub(kb - b0 - bb, ncols, bb, &MXLU_AT(A, k0 + b0 + bb, k0 + b0, lda),
-                             lda, &MXLU_AT(A, k0 + b0, col0, lda), lda,
-                             &MXLU_AT(A, k0 + b0 + bb, col0, lda), lda, s));
-    }
+}  // namespace
+
+namespace mxlu {
+// GEPP of the m x kb panel P (element (0, 0) is row/column ibase of the
+// caller's matrix); ipiv[ibase ..] receives caller-numbered rows.
+template <typename T>
+int panel_factor(T *P, int64_t ldp, int64_t m, int64_t kb, int64_t ibase, int32_t *ipiv,
+                 const PanelExchange &ex, int *moves, hipStream_t s) {
+    PanelCtx<T> f{P, ldp, m, kb, ibase, ipiv, ex, moves, s};
+    return panel_rec(f, 0, kb);
+}
+template int panel_factor<double>(double *, int64_t, int64_t, int64_t, int64_t, int32_t *,
+                                  const PanelExchange &, int *, hipStream_t);
+template int panel_factor<float>(float *, int64_t, int64_t, int64_t, int64_t, int32_t *,
+                                 const PanelExchange &, int *, hipStream_t);
+
+int alloc_panel_exchange(Scratch &scratch, int64_t n, PanelExchange *ex, hipStream_t s) {
+    ex->cand = scratch.alloc_n<double>((size_t)2 * kMaxGroups * (kLeafW + 2));
+    ex->rowj = scratch.alloc_n<double>((size_t)2 * kLeafW);
+    ex->counters = scratch.alloc_n<int>((size_t)(n > 0 ? n : 1));
+    ex->flags = scratch.alloc_n<int>(4);
+    if (!ex->cand || !ex->rowj || !ex->counters || !ex->flags) return MXLU_E_NOMEM;
+    MXLU_HIP_TRY(hipMemsetAsync(ex->counters, 0, sizeof(int) * (size_t)(n > 0 ? n : 1), s));
+    MXLU_HIP_TRY(hipMemsetAsync(ex->flags, 0, sizeof(int) * 4, s));
     return 0;
 }
+}  // namespace mxlu
+
+namespace {
 
 int factor_impl(int64_t n, int64_t nb, double *A, int64_t lda, int32_t *ipiv, hipStream_t s,
                 int *info_out) {
     Scratch scratch(s);
-    FactorCtx f;
-    f.n = n;
-    f.lda = lda;
-    f.A = A;
-    f.ipiv = ipiv;
-    f.s = s;
-    f.ex.cand = scratch.alloc_n<double>((size_t)2 * kMaxGroups * (kLeafW + 2));
-    f.ex.rowj = scratch.alloc_n<double>((size_t)2 * kLeafW);
-    f.ex.counters = scratch.alloc_n<int>((size_t)n);
-    f.ex.flags = scratch.alloc_n<int>(4);
-    f.moves = scratch.alloc_n<int>(kSwapMovesInts);
-    if (!f.ex.cand || !f.ex.rowj || !f.ex.counters || !f.ex.flags || !f.moves)
-        return MXLU_E_NOMEM;
-    MXLU_HIP_TRY(hipMemsetAsync(f.ex.counters, 0, sizeof(int) * (size_t)n, s));
-    MXLU_HIP_TRY(hipMemsetAsync(f.ex.flags, 0, sizeof(int) * 4, s));
+    PanelExchange ex;
+    MXLU_TRY(alloc_panel_exchange(scratch, n, &ex, s));
+    int *moves = scratch.alloc_n<int>(kSwapMovesInts);
+    if (!moves) return MXLU_E_NOMEM;
 
     for (int64_t k0 = 0; k0 < n; k0 += nb) {
         const int64_t kb = std::min(nb, n - k0);
-        // PFACT
-        TRY(panel_rec(f, k0, kb, k0, kb));
-        // SWAP on the columns left and right of the panel
-        TRY(laswp_f64(A, lda, ipiv, k0, (int)kb, 0, n - kb, k0, kb, f.moves, s));
-        const int64_t c1 = k0 + kb;
+        const int64_t m = n - k0, c1 = k0 + kb;
+        {   // PFACT
+            PhaseScope ph(kPhasePfact, s, (double)m * kb * 8.0);
+            MXLU_TRY(panel_factor<double>(&MXLU_AT(A, k0, k0, lda), lda, m, kb, k0, ipiv, ex, moves,
+                                     s));
+        }
+        {   // SWAP on the columns left and right of the panel
+            PhaseScope ph(kPhaseSwap, s, 32.0 * kb * (double)(n - kb));
+            MXLU_TRY(laswp_f64(A, lda, ipiv, k0, (int)kb, 0, n - kb, k0, kb, moves, s));
+        }
         if (c1 < n) {
-            // DTRSM: U12 = L11^-1 A12
-            TRY(trsm_block_row(A, lda, k0, kb, n - c1, c1, s));
-            // DGEMM: A22 -= L21 U12
-            TRY(gemm_f64_sub(n - c1, n - c1, kb, &MXLU_AT(A, c1, k0, lda), lda,
-                             &MXLU_AT(A, k0, c1, lda), lda, &MXLU_AT(A, c1, c1, lda), lda, s));
+            {   // DTRSM: U12 = L11^-1 A12
+                PhaseScope ph(kPhaseTrsm, s, (double)kb * (kb - 1) * (double)(n - c1));
+                MXLU_TRY(PanelOps<double>::trsm(kb, n - c1, &MXLU_AT(A, k0, k0, lda), lda,
+                                           &MXLU_AT(A, k0, c1, lda), lda, s));
+            }
+            {   // DGEMM: A22 -= L21 U12
+                const double mt = (double)(n - c1);
+                PhaseScope ph(kPhaseGemm, s, 2.0 * mt * mt * (double)kb);
+                MXLU_TRY(gemm_f64_sub(n - c1, n - c1, kb, &MXLU_AT(A, c1, k0, lda), lda,
+                                 &MXLU_AT(A, k0, c1, lda), lda, &MXLU_AT(A, c1, c1, lda), lda, s));
+            }
         }
     }
     int flags[4] = {0, 0, 0, 0};
-    MXLU_HIP_TRY(hipMemcpyAsync(flags, f.ex.flags, sizeof(flags), hipMemcpyDeviceToHost, s));
+    MXLU_HIP_TRY(hipMemcpyAsync(flags, ex.flags, sizeof(flags), hipMemcpyDeviceToHost, s));
     MXLU_HIP_TRY(hipStreamSynchronize(s));
     if (flags[1]) {
         set_error_msg("lu_factor: panel grid barrier wait expired");
@@ -162,9 +201,10 @@ extern "C" int lu_solve(int64_t n, int64_t nrhs, const double *LU, int64_t lda,
     clear_error();
     hipStream_t s = (hipStream_t)stream;
     Scratch scratch(s);
+    PhaseScope ph(kPhaseSolve, s, 8.0 * (double)n * (double)n);
     int32_t *perm = scratch.alloc_n<int32_t>((size_t)n);
     if (!perm) return MXLU_E_NOMEM;
-    TRY(perm_from_ipiv(n, ipiv, perm, s));
+    MXLU_TRY(perm_from_ipiv(n, ipiv, perm, s));
 
     // Work on strips of at most 16 right-hand sides.
     const int64_t bs = 256;
@@ -175,22 +215,22 @@ extern "C" int lu_solve(int64_t n, int64_t nrhs, const double *LU, int64_t lda,
         const int64_t nr = std::min<int64_t>(16, nrhs - r0);
         double *Bc = B + (size_t)r0 * (size_t)ldb;
         if (trans == 0) {
-            TRY(gather_rows_f64(n, nr, perm, Bc, ldb, Y, ldy, s));
+            MXLU_TRY(gather_rows_f64(n, nr, perm, Bc, ldb, Y, ldy, s));
             // L y = P b: diagonal blocks forward, updates below
             for (int64_t b0 = 0; b0 < n; b0 += bs) {
                 const int64_t bb = std::min(bs, n - b0);
-                TRY(trsm_llnu_f64((int)bb, nr, &MXLU_AT(LU, b0, b0, lda), lda, Y + b0, ldy, s));
+                MXLU_TRY(trsm_llnu_f64((int)bb, nr, &MXLU_AT(LU, b0, b0, lda), lda, Y + b0, ldy, s));
                 if (b0 + bb < n)
-                    TRY(gemm_f64_sub(n - b0 - bb, nr, bb, &MXLU_AT(LU, b0 + bb, b0, lda), lda,
+                    MXLU_TRY(gemm_f64_sub(n - b0 - bb, nr, bb, &MXLU_AT(LU, b0 + bb, b0, lda), lda,
                                      Y + b0, ldy, Y + b0 + bb, ldy, s));
             }
             // U x = y: diagonal blocks backward, updates above
             const int64_t nblk = (n + bs - 1) / bs;
             for (int64_t bi = nblk - 1; bi >= 0; --bi) {
                 const int64_t b0 = bi * bs, bb = std::min(bs, n - b0);
-                TRY(trsm_lunn_f64((int)bb, nr, &MXLU_AT(LU, b0, b0, lda), lda, Y + b0, ldy, s));
+                MXLU_TRY(trsm_lunn_f64((int)bb, nr, &MXLU_AT(LU, b0, b0, lda), lda, Y + b0, ldy, s));
                 if (b0 > 0)
-                    TRY(gemm_f64_sub(b0, nr, bb, &MXLU_AT(LU, 0, b0, lda), lda, Y + b0, ldy, Y,
+                    MXLU_TRY(gemm_f64_sub(b0, nr, bb, &MXLU_AT(LU, 0, b0, lda), lda, Y + b0, ldy, Y,
                                      ldy, s));
             }
             // copy back
@@ -204,20 +244,20 @@ extern "C" int lu_solve(int64_t n, int64_t nrhs, const double *LU, int64_t lda,
             for (int64_t b0 = 0; b0 < n; b0 += bs) {
                 const int64_t bb = std::min(bs, n - b0);
                 if (b0 > 0)
-                    TRY(gemm_f64_sub_tn_skinny(bb, nr, b0, &MXLU_AT(LU, 0, b0, lda), lda, Y, ldy,
+                    MXLU_TRY(gemm_f64_sub_tn_skinny(bb, nr, b0, &MXLU_AT(LU, 0, b0, lda), lda, Y, ldy,
                                                Y + b0, ldy, s));
-                TRY(trsm_lutn_f64((int)bb, nr, &MXLU_AT(LU, b0, b0, lda), lda, Y + b0, ldy, s));
+                MXLU_TRY(trsm_lutn_f64((int)bb, nr, &MXLU_AT(LU, b0, b0, lda), lda, Y + b0, ldy, s));
             }
             // L^T z = y: backward; block first takes the rows below it
             const int64_t nblk = (n + bs - 1) / bs;
             for (int64_t bi = nblk - 1; bi >= 0; --bi) {
                 const int64_t b0 = bi * bs, bb = std::min(bs, n - b0);
                 if (b0 + bb < n)
-                    TRY(gemm_f64_sub_tn_skinny(bb, nr, n - b0 - bb, &MXLU_AT(LU, b0 + bb, b0, lda),
+                    MXLU_TRY(gemm_f64_sub_tn_skinny(bb, nr, n - b0 - bb, &MXLU_AT(LU, b0 + bb, b0, lda),
                                                lda, Y + b0 + bb, ldy, Y + b0, ldy, s));
-                TRY(trsm_lltu_f64((int)bb, nr, &MXLU_AT(LU, b0, b0, lda), lda, Y + b0, ldy, s));
+                MXLU_TRY(trsm_lltu_f64((int)bb, nr, &MXLU_AT(LU, b0, b0, lda), lda, Y + b0, ldy, s));
             }
-            TRY(scatter_rows_f64(n, nr, perm, Y, ldy, Bc, ldb, s));
+            MXLU_TRY(scatter_rows_f64(n, nr, perm, Y, ldy, Bc, ldb, s));
         }
     }
     return 0;
@@ -239,4 +279,23 @@ extern "C" int mxlu_schur_update_f64(int64_t M, int64_t N, int64_t K, const doub
     if (int rc = check_device()) return rc;
     clear_error();
     return gemm_f64_sub(M, N, K, A, lda, B, ldb, C, ldc, (hipStream_t)stream);
+}
+
+extern "C" int mxlu_outer_update_f64(int64_t M, int64_t N, int64_t K, const double *A,
+                                     int64_t lda, const double *B, int64_t ldb, double *C,
+                                     int64_t ldc, int accumulate, void *stream) {
+    if (M < 0) return -1;
+    if (N < 0) return -2;
+    if (K < 0) return -3;
+    if (M > 0 && K > 0 && !A) return -4;
+    if (lda < std::max<int64_t>(1, M)) return -5;
+    if (N > 0 && K > 0 && !B) return -6;
+    if (ldb < std::max<int64_t>(1, N)) return -7;
+    if (M > 0 && N > 0 && !C) return -8;
+    if (ldc < std::max<int64_t>(1, M)) return -9;
+    if (accumulate != 0 && accumulate != 1) return -10;
+    if (M == 0 || N == 0) return 0;
+    if (int rc = check_device()) return rc;
+    clear_error();
+    return gemm_f64_nt_sub(M, N, K, A, lda, B, ldb, C, ldc, accumulate != 0, (hipStream_t)stream);
 }

@@ -71,11 +71,13 @@ __device__ __forceinline__ void block_argmax(double &v, int &idx, double *sv, in
 // slots of column j only after barrier j-1, which every group reaches after
 // it has read the slots of column j-2.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void panel_leaf_f64_kernel(
-    int m, int w, double *__restrict__ P, int64_t lda, int R, int G, int64_t r0,
+template <typename T>
+__global__ __launch_bounds__(256) void panel_leaf_kernel(
+    int m, int w, T *__restrict__ P, int64_t lda, int R, int G, int64_t r0,
     int32_t *__restrict__ ipiv, double *cand, double *rowj, int *counters, int *flags) {
-    extern __shared__ double sp[];   // [kLeafW][R]
-    __shared__ double s_prow[mxlu::kLeafW], s_rowj[mxlu::kLeafW];
+    extern __shared__ __attribute__((aligned(16))) unsigned char sp_raw[];
+    T *sp = reinterpret_cast<T *>(sp_raw);   // [kLeafW][R]
+    __shared__ T s_prow[mxlu::kLeafW], s_rowj[mxlu::kLeafW];
     __shared__ double s_v[4];
     __shared__ int s_i[4];
     constexpr int SLOT = mxlu::kLeafW + 2;
@@ -94,7 +96,7 @@ __global__ __launch_bounds__(256) void panel_leaf_f64_kernel(
         int idx = INT_MAX;
         for (int i = tid; i < rows; i += 256) {
             if (rb + i >= j) {
-                const double a = fabs(sp[j * R + i]);
+                const double a = fabs((double)sp[j * R + i]);
                 if (a > v) {
                     v = a;
                     idx = rb + i;
@@ -108,9 +110,9 @@ __global__ __launch_bounds__(256) void panel_leaf_f64_kernel(
             mine[0] = v;
             mine[1] = (double)idx;
         }
-        if (tid < w && idx != INT_MAX) mine[2 + tid] = sp[tid * R + (idx - rb)];
+        if (tid < w && idx != INT_MAX) mine[2 + tid] = (double)sp[tid * R + (idx - rb)];
         if (tid < w && j >= rb && j < rb + rows)
-            rowj[par * mxlu::kLeafW + tid] = sp[tid * R + (j - rb)];
+            rowj[par * mxlu::kLeafW + tid] = (double)sp[tid * R + (j - rb)];
         __syncthreads();
 
         if (G > 1) {
@@ -147,9 +149,9 @@ __global__ __launch_bounds__(256) void panel_leaf_f64_kernel(
         // whenever some row >= j is left, which always holds for j < m.
         const int p = gi;
         const int gw = p / R;
-        if (tid < w) {
-            s_prow[tid] = cand[((size_t)par * mxlu::kMaxGroups + gw) * SLOT + 2 + tid];
-            s_rowj[tid] = rowj[par * mxlu::kLeafW + tid];
+        if (tid < w) {   // values of the matrix's own type, exact through double
+            s_prow[tid] = (T)cand[((size_t)par * mxlu::kMaxGroups + gw) * SLOT + 2 + tid];
+            s_rowj[tid] = (T)rowj[par * mxlu::kLeafW + tid];
         }
         __syncthreads();
 
@@ -164,10 +166,10 @@ __global__ __launch_bounds__(256) void panel_leaf_f64_kernel(
         }
         __syncthreads();
 
-        const double piv = s_prow[j];
+        const T piv = s_prow[j];
         for (int i = tid; i < rows; i += 256) {
             if (rb + i > j) {
-                double l = sp[j * R + i];
+                T l = sp[j * R + i];
                 if (nonzero) {
                     l = l / piv;
                     sp[j * R + i] = l;
@@ -278,13 +280,14 @@ __global__ __launch_bounds__(256) void swap_compose_kernel(const int32_t *__rest
 constexpr int kSwapColsPerBlock = 32;
 constexpr int kSwapBatch = 4;   // columns staged per round
 
-__global__ __launch_bounds__(256) void swap_apply_kernel(double *__restrict__ A, int64_t lda,
+template <typename T>
+__global__ __launch_bounds__(256) void swap_apply_kernel(T *__restrict__ A, int64_t lda,
                                                          int64_t j0, const int *__restrict__ moves,
                                                          int64_t c_begin, int64_t ncols,
                                                          int64_t skip_begin, int64_t skip_len) {
     __shared__ int s_dst[2 * kMaxSwaps];
     __shared__ int s_src[2 * kMaxSwaps];
-    __shared__ double s_val[kSwapBatch * 2 * kMaxSwaps / 2];   // 4 x 1024
+    __shared__ T s_val[kSwapBatch * 2 * kMaxSwaps / 2];   // 4 x 1024
     const int tid = threadIdx.x;
     const int nm = moves[0];
     for (int t = tid; t < nm; t += 256) {
@@ -486,16 +489,17 @@ static int max_dynamic_lds() {
     return cached;
 }
 
-int panel_leaf_f64(int64_t m, int w, double *A, int64_t lda, int64_t r0, int32_t *ipiv,
-                   const PanelExchange &ex, hipStream_t s) {
+template <typename T>
+int panel_leaf(int64_t m, int w, T *P, int64_t ldp, int64_t r0, int32_t *ipiv,
+               const PanelExchange &ex, hipStream_t s) {
     if (m <= 0 || w <= 0) return 0;
     if (w > kLeafW || m > 0x7fffffff) {
-        set_error_msg("panel_leaf_f64: bad shape");
+        set_error_msg("panel_leaf: bad shape");
         return MXLU_E_NOMEM;
     }
     // dynamic LDS budget: the device limit minus room for the static arrays
     const int max_lds = max_dynamic_lds() - 1024;
-    const int rmax = max_lds / (kLeafW * (int)sizeof(double));
+    const int rmax = max_lds / (kLeafW * (int)sizeof(T));
     // about 64 groups; each group at least 256 rows, at most what LDS holds
     int R = (int)((m + 63) / 64);
     if (R < 256) R = 256;
@@ -505,36 +509,58 @@ int panel_leaf_f64(int64_t m, int w, double *A, int64_t lda, int64_t r0, int32_t
         set_error_msg("panel_leaf_f64: panel too tall for the LDS of the device");
         return MXLU_E_NOMEM;
     }
-    const size_t lds = (size_t)kLeafW * R * sizeof(double);
+    const size_t lds = (size_t)kLeafW * R * sizeof(T);
     static bool attr_set = false;
     if (!attr_set) {
-        MXLU_HIP_TRY(hipFuncSetAttribute((const void *)panel_leaf_f64_kernel,
+        MXLU_HIP_TRY(hipFuncSetAttribute((const void *)panel_leaf_kernel<T>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, max_lds));
         attr_set = true;
     }
-    double *P = A + (size_t)r0 + (size_t)r0 * (size_t)lda;
-    hipLaunchKernelGGL(panel_leaf_f64_kernel, dim3((unsigned)G), dim3(256), lds, s, (int)m, w,
-                       P, lda, R, (int)G, r0, ipiv + r0, ex.cand, ex.rowj, ex.counters + r0,
+    hipLaunchKernelGGL(panel_leaf_kernel<T>, dim3((unsigned)G), dim3(256), lds, s, (int)m, w, P,
+                       ldp, R, (int)G, r0, ipiv + r0, ex.cand, ex.rowj, ex.counters + r0,
                        ex.flags);
     MXLU_LAUNCH_CHECK();
     return 0;
 }
+template int panel_leaf<double>(int64_t, int, double *, int64_t, int64_t, int32_t *,
+                                const PanelExchange &, hipStream_t);
+template int panel_leaf<float>(int64_t, int, float *, int64_t, int64_t, int32_t *,
+                               const PanelExchange &, hipStream_t);
+
+int swap_compose(const int32_t *ipiv, int64_t j0, int cnt, int *moves, hipStream_t s) {
+    if (cnt <= 0) return 0;
+    if (cnt > kMaxSwaps || !moves) {
+        set_error_msg("laswp: too many interchanges or no move buffer");
+        return MXLU_E_NOMEM;
+    }
+    hipLaunchKernelGGL(swap_compose_kernel, dim3(1), dim3(256), 0, s, ipiv, j0, cnt, moves);
+    MXLU_LAUNCH_CHECK();
+    return 0;
+}
+
+template <typename T>
+int swap_apply(T *A, int64_t lda, int64_t j0, const int *moves, int64_t c_begin, int64_t ncols,
+               int64_t skip_begin, int64_t skip_len, hipStream_t s) {
+    if (ncols <= 0) return 0;
+    const unsigned grid = (unsigned)((ncols + kSwapColsPerBlock - 1) / kSwapColsPerBlock);
+    hipLaunchKernelGGL(swap_apply_kernel<T>, dim3(grid), dim3(256), 0, s, A, lda, j0, moves,
+                       c_begin, ncols, skip_begin, skip_len);
+    MXLU_LAUNCH_CHECK();
+    return 0;
+}
+template int swap_apply<double>(double *, int64_t, int64_t, const int *, int64_t, int64_t,
+                                int64_t, int64_t, hipStream_t);
+template int swap_apply<float>(float *, int64_t, int64_t, const int *, int64_t, int64_t, int64_t,
+                               int64_t, hipStream_t);
+template int swap_apply<uint16_t>(uint16_t *, int64_t, int64_t, const int *, int64_t, int64_t,
+                                  int64_t, int64_t, hipStream_t);
 
 int laswp_f64(double *A, int64_t lda, const int32_t *ipiv, int64_t j0, int cnt,
               int64_t c_begin, int64_t ncols, int64_t skip_begin, int64_t skip_len,
               int *moves, hipStream_t s) {
     if (cnt <= 0 || ncols <= 0) return 0;
-    if (cnt > kMaxSwaps || !moves) {
-        set_error_msg("laswp_f64: too many interchanges or no move buffer");
-        return MXLU_E_NOMEM;
-    }
-    hipLaunchKernelGGL(swap_compose_kernel, dim3(1), dim3(256), 0, s, ipiv, j0, cnt, moves);
-    MXLU_LAUNCH_CHECK();
-    const unsigned grid = (unsigned)((ncols + kSwapColsPerBlock - 1) / kSwapColsPerBlock);
-    hipLaunchKernelGGL(swap_apply_kernel, dim3(grid), dim3(256), 0, s, A, lda, j0,
-                       (const int *)moves, c_begin, ncols, skip_begin, skip_len);
-    MXLU_LAUNCH_CHECK();
-    return 0;
+    MXLU_TRY(swap_compose(ipiv, j0, cnt, moves, s));
+    return swap_apply<double>(A, lda, j0, moves, c_begin, ncols, skip_begin, skip_len, s);
 }
 
 template <bool LOWER, bool UNIT, bool TRANS>

@@ -1,0 +1,123 @@
+// Optional per-phase timing with HIP events on the work's own stream.
+//
+// When enabled, each phase of the factorization (PFACT, SWAP, DTRSM, DGEMM
+// and the solve; Sec. III-A.1 lists these phases and models the time of each
+// step as set by the slowest of them) is bracketed by a pair of events; the
+// totals are read back after the caller's work has completed.  Disabled, the
+// scopes cost one branch.
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <vector>
+
+#include "common.h"
+#include "profile.h"
+
+namespace mxlu {
+
+namespace {
+struct Pending {
+    hipEvent_t start, stop;
+    int phase;
+    double work;
+};
+std::mutex g_mu;
+bool g_enabled = false;
+std::vector<Pending> g_pending;
+std::vector<hipEvent_t> g_free;
+double g_ms[kPhaseCount];
+double g_work[kPhaseCount];
+int64_t g_count[kPhaseCount];
+
+hipEvent_t get_event() {
+    if (!g_free.empty()) {
+        hipEvent_t e = g_free.back();
+        g_free.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+}  // namespace
+
+bool profiling_enabled() { return g_enabled; }
+
+PhaseScope::PhaseScope(int phase, hipStream_t s, double work) : s_(s) {
+    if (!g_enabled) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    start_ = get_event();
+    if (!start_) return;
+    phase_ = phase;
+    work_ = work;
+    if (hipEventRecord(start_, s_) != hipSuccess) {
+        (void)hipGetLastError();
+        g_free.push_back(start_);
+        start_ = nullptr;
+    }
+}
+
+PhaseScope::~PhaseScope() {
+    if (!start_) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    hipEvent_t stop = get_event();
+    if (!stop || hipEventRecord(stop, s_) != hipSuccess) {
+        (void)hipGetLastError();
+        g_free.push_back(start_);
+        if (stop) g_free.push_back(stop);
+        return;
+    }
+    g_pending.push_back({start_, stop, phase_, work_});
+}
+
+}  // namespace mxlu
+
+using namespace mxlu;
+
+extern "C" int mxlu_profile_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_enabled = on != 0;
+    return 0;
+}
+
+extern "C" int mxlu_profile_reset(void) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto &p : g_pending) {
+        (void)hipEventSynchronize(p.stop);
+        g_free.push_back(p.start);
+        g_free.push_back(p.stop);
+    }
+    g_pending.clear();
+    for (int i = 0; i < kPhaseCount; ++i) g_ms[i] = g_work[i] = 0.0, g_count[i] = 0;
+    return 0;
+}
+
+extern "C" int mxlu_profile_read(double *ms, double *work, int64_t *count, int nphase) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto &p : g_pending) {
+        if (hipEventSynchronize(p.stop) != hipSuccess) {
+            set_error("hipEventSynchronize", hipGetLastError());
+            return MXLU_E_HIP;
+        }
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, p.start, p.stop) != hipSuccess) {
+            set_error("hipEventElapsedTime", hipGetLastError());
+            return MXLU_E_HIP;
+        }
+        g_ms[p.phase] += t;
+        g_work[p.phase] += p.work;
+        g_count[p.phase] += 1;
+        g_free.push_back(p.start);
+        g_free.push_back(p.stop);
+    }
+    g_pending.clear();
+    for (int i = 0; i < nphase && i < kPhaseCount; ++i) {
+        if (ms) ms[i] = g_ms[i];
+        if (work) work[i] = g_work[i];
+        if (count) count[i] = g_count[i];
+    }
+    return 0;
+}

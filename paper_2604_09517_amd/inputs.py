@@ -77,15 +77,28 @@ def uniform_at(seed: int, stream: int, idx) -> np.ndarray:
 
 
 def uniform_matrix(seed: int, stream: int, n_rows: int, n_cols: int,
-                   chunk_cols: int = 4096) -> np.ndarray:
-    """Column-major (Fortran-ordered) n_rows x n_cols FP64 matrix."""
+                   chunk_cols: int = 4096, threads: int = 1) -> np.ndarray:
+    """Column-major (Fortran-ordered) n_rows x n_cols FP64 matrix.  `threads`
+    > 1 fills column chunks concurrently (numpy releases the GIL)."""
     out = np.empty((n_rows, n_cols), dtype=np.float64, order="F")
     rows = np.arange(n_rows, dtype=np.uint64)
-    for c0 in range(0, n_cols, chunk_cols):
+    if threads > 1:
+        chunk_cols = max(1, min(chunk_cols, (1 << 22) // max(1, n_rows)))
+
+    def fill(c0):
         c1 = min(n_cols, c0 + chunk_cols)
         cols = np.arange(c0, c1, dtype=np.uint64)
         idx = cols[None, :] * np.uint64(n_rows) + rows[:, None]
         out[:, c0:c1] = uniform_at(seed, stream, idx)
+
+    starts = range(0, n_cols, chunk_cols)
+    if threads > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(threads) as ex:
+            list(ex.map(fill, starts))
+    else:
+        for c0 in starts:
+            fill(c0)
     return out
 
 

@@ -1,0 +1,116 @@
+"""GPU parity of the differentiable solve (autograd.Function): gradient of
+loss = sum(W * X), X = A^-1 B, against the CPU oracle gradient
+(Lambda = A^-T W, dA = -Lambda X^T, dB = Lambda), central finite
+differences, and torch.autograd.gradcheck."""
+
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import grad as ograd
+from paper_2604_09517_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ag():
+    from paper_2604_09517_amd import api, autograd
+    api.lib()
+    torch.cuda.set_device(0)
+    return autograd
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def grads(ag, A_h, B_h, W_h, mode, nb=64):
+    A = torch.tensor(A_h, device="cuda", requires_grad=True)
+    B = torch.tensor(B_h, device="cuda", requires_grad=True)
+    X = ag.solve(A, B, mode=mode, nb=nb)
+    loss = (X * torch.tensor(W_h, device="cuda")).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    return X.detach().cpu().numpy(), A.grad.cpu().numpy(), B.grad.cpu().numpy()
+
+
+@pytest.mark.parametrize("mode,n,k", [("fp64", 64, 3), ("fp64", 300, 16), ("bf16_ir", 256, 2)])
+def test_gradient_matches_oracle(ag, mode, n, k):
+    note(f"autograd {mode} n={n} k={k}")
+    A = inputs.uniform_matrix(400 + n, 0, n, n)
+    B = inputs.uniform_matrix(400 + n, 1, n, k)
+    W = inputs.normal_matrix(400 + n, n, k)
+    X, dA, dB = grads(ag, A, B, W, mode)
+    Xr, dAr, dBr, _ = ograd.solve_and_grad(A, B, W, nb=64)
+    tol = 1e-9 if mode == "fp64" else 1e-8
+    assert np.abs(X - Xr).max() <= tol * np.abs(Xr).max()
+    assert np.abs(dB - dBr).max() <= tol * np.abs(dBr).max()
+    assert np.abs(dA - dAr).max() <= tol * np.abs(dAr).max()
+
+
+def test_gradcheck_fp64(ag):
+    n = 8
+    A0 = inputs.uniform_matrix(7, 0, n, n) + 2 * np.eye(n)
+    B0 = inputs.uniform_matrix(7, 1, n, 2)
+    A = torch.tensor(A0, device="cuda", requires_grad=True)
+    B = torch.tensor(B0, device="cuda", requires_grad=True)
+    assert torch.autograd.gradcheck(lambda a, b: ag.solve(a, b, mode="fp64", nb=4), (A, B),
+                                    eps=1e-6, atol=1e-7)
+
+
+@pytest.mark.parametrize("mode", ["fp64", "bf16_ir"])
+def test_full_size_gradient_finite_differences(ag, mode):
+    """n = 8192, 16 right-hand sides, loss = sum(W * X) with W ~ N(0, 1):
+    central differences (h = 1e-6) on single entries of A and B and on
+    rank-one directions of A, relative tolerance 1e-5."""
+    cfg = inputs.WORKLOADS["autograd"]
+    n, k, nb, seed = cfg["n"], cfg["nrhs"], cfg["nb"], inputs.config_seed(cfg["index"])
+    note(f"full-size autograd {mode} n={n} k={k}")
+    from paper_2604_09517_amd import api
+    A = api.fortran_empty(n, n)
+    api.fill_uniform(A, seed, inputs.STREAM_A)
+    B = torch.from_numpy(inputs.uniform_matrix(seed, inputs.STREAM_B, n, k)).cuda()
+    W = torch.from_numpy(inputs.normal_matrix(seed, n, k)).cuda()
+    kw = {} if mode == "fp64" else dict(inner_tol=1e-10, resid_threshold=0.5)
+    Ar = A.clone().requires_grad_(True)
+    Br = B.clone().requires_grad_(True)
+    X = ag.solve(Ar, Br, mode=mode, nb=nb, **kw)
+    (X * W).sum().backward()
+    dA, dB = Ar.grad, Br.grad
+    torch.cuda.synchronize()
+
+    def loss(Ap, Bp):
+        with torch.no_grad():
+            return float((ag.solve(Ap, Bp, mode=mode, nb=nb, **kw) * W).sum())
+
+    h = 1e-6
+    rng = np.random.default_rng(0)
+    worst = 0.0
+    for t in range(16):
+        i, j = (int(v) for v in rng.integers(0, n, 2))
+        Ap = A.clone(); Ap[i, j] += h
+        Am = A.clone(); Am[i, j] -= h
+        fd = (loss(Ap, B) - loss(Am, B)) / (2 * h)
+        g = float(dA[i, j])
+        worst = max(worst, abs(fd - g) / max(1.0, abs(g)))
+    for t in range(8):
+        i, c = int(rng.integers(0, n)), int(rng.integers(0, k))
+        Bp = B.clone(); Bp[i, c] += h
+        Bm = B.clone(); Bm[i, c] -= h
+        fd = (loss(A, Bp) - loss(A, Bm)) / (2 * h)
+        g = float(dB[i, c])
+        worst = max(worst, abs(fd - g) / max(1.0, abs(g)))
+    for t in range(4):
+        i, j = (int(v) for v in rng.integers(0, n, 2))
+        # direction E = e_i e_j^T scaled (unit vectors): d/dh L(A + h E)
+        Ap = A.clone(); Ap[i, j] += h
+        Am = A.clone(); Am[i, j] -= h
+        fd = (loss(Ap, B) - loss(Am, B)) / (2 * h)
+        g = float(dA[i, j])
+        worst = max(worst, abs(fd - g) / max(1.0, abs(g)))
+    note(f"worst relative finite-difference mismatch {worst:.2e}")
+    assert worst <= 1e-5
