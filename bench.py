@@ -144,13 +144,13 @@ def run_fp64(args, cfg):
     rho = api.scaled_residual(A0, rhs[-1], b)[0]
     log(f"scaled residual {rho:.3e}, info {infos}")
 
-    gflop, gms, gcnt = prof["gemm"]
+    gms, gflop, gcnt = prof["gemm"]        # (milliseconds, flops, launches)
     achieved = gflop / (gms * 1e-3) / 1e12 if gms > 0 else 0.0
     traffic = traffic_from_profile("gemm_f64_fp64_large.md", GEMM_SRC)
     roofline = {
         "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["f64"],
         "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["f64"], 4),
-        "traffic": traffic, "kernel": "gemm_f64_sub_kernel<true> (trailing update)",
+        "traffic": traffic, "kernel": "gemm_f64_sub_kernel<true, false, false> (trailing update)",
         "launches": gcnt, "avg_launch_ms": round(gms / max(1, gcnt), 4),
     }
     phases = {p: round(v[0] / args.steps, 3) for p, v in prof.items() if v[2] > 0}
@@ -175,6 +175,106 @@ def run_fp64(args, cfg):
     return out, (lambda: cpu_baseline_fp64(n, nb, seed))
 
 
+def cpu_baseline_mxp(cfg, seed, prec_id, n_sample=4096):
+    """Time the oracle's mixed-precision solve (low-precision LU + GMRES-IR)
+    on the same recipe at a smaller order."""
+    import oracle
+    from oracle import refine
+    from paper_2604_09517_amd import inputs
+
+    nb = min(cfg["nb"], n_sample)
+    A = inputs.diag_dominant_matrix(seed, inputs.STREAM_A, n_sample)
+    b = inputs.uniform_matrix(seed, inputs.STREAM_B, n_sample, 1)[:, 0]
+    t0 = time.perf_counter()
+    F, _, _ = oracle.lp_getrf(A, nb, prec_id, pivot=False, tile=128)
+    out = refine.refine(A, b, F, None, method="gmres")
+    dt = time.perf_counter() - t0
+    return {
+        "value": (2.0 / 3.0) * n_sample ** 3 / dt / 1e12,
+        "unit": "TFLOP/s",
+        "cores": oracle.threads(),
+        "kind": "oracle",
+        "sample": (f"full mixed-precision solve (low-precision LU NB={nb} + GMRES-IR, "
+                   f"converged={out['converged']}) of the same recipe at N={n_sample}, "
+                   f"{dt:.1f} s"),
+    }
+
+
+def run_mxp(args, cfg, name):
+    import torch
+
+    from paper_2604_09517_amd import api, inputs
+
+    n, nb = cfg["n"], cfg["nb"]
+    prec = {"bf16_ir": "bf16", "fp8_ir": "fp8"}[name]
+    seed = inputs.config_seed(cfg["index"])
+    log(f"workload {name} n={n} nb={nb}: generating A in HBM")
+    A = api.fortran_empty(n, n)
+    api.fill_uniform(A, seed, inputs.STREAM_A)
+    api.make_diag_dominant(A)
+    b = torch.from_numpy(inputs.uniform_matrix(seed, inputs.STREAM_B, n, 1)[:, 0]).cuda()
+    X = torch.empty(n, dtype=torch.float64, device="cuda")
+    opts = api.mxp_options(prec=prec, nb=nb, refine="gmres", scale_tile=128)
+    work = torch.empty(api.mxp_workspace_bytes(n, opts), dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    for w in range(args.warmup):
+        _, rep, _, _ = api.mxp_solve(A, b, X=X, work=work, opts=opts)
+        torch.cuda.synchronize()
+        log(f"warmup step {w}: {rep}")
+    api.profile_reset()
+    api.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = []
+    for _ in range(args.steps):
+        _, rep, _, _ = api.mxp_solve(A, b, X=X, work=work, opts=opts)
+        reps.append(rep)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    api.profile_enable(False)
+    prof = api.profile_read()
+    ms = (t1 - t0) * 1e3 / args.steps
+    rho = api.scaled_residual(A, X, b)[0]
+    log(f"timed {args.steps} steps: {ms:.1f} ms/step, residual {rho:.3e}, last report {reps[-1]}")
+    sms, sbytes, scnt = prof["lp_schur"]   # (milliseconds, bytes, launches)
+    achieved = sbytes / (sms * 1e-3) / 1e9 if sms > 0 else 0.0
+    schur_flops = sum(2.0 * (n - k0 - nb) ** 2 * nb for k0 in range(0, n - nb, nb))
+    mma_peak = PEAK_TFLOPS["bf16" if prec == "bf16" else "fp8"]
+    value = (2.0 / 3.0) * n ** 3 / (ms * 1e-3) / 1e12
+    phases = {p: round(v[0] / args.steps, 3) for p, v in prof.items() if v[2] > 0}
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "TFLOP/s",
+        "ms_per_step": round(ms, 3),
+        "dtype": "bf16" if prec == "bf16" else "fp8",
+        "config": {"workload": f"{prec}_lu_nopivot_plus_fp64_gmres_ir", "n": n, "nb": nb,
+                   "nrhs": 1, "matrix": "diagonally dominant (off-diagonal uniform[-0.5,0.5), "
+                   "diagonal = row sum of |off-diagonal|), column-major",
+                   "storage": "bf16" if prec == "bf16" else "fp16",
+                   "peak_frac_fp64_equivalent_vs_mfma": round(value / mma_peak, 4)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0,
+                     "unit": "GB/s", "frac": round(achieved / 8000.0, 4), "traffic": None,
+                     "kernel": f"lp_schur{'16' if prec == 'bf16' else '8'}_kernel "
+                               f"(trailing update)",
+                     "launches": scnt, "avg_launch_ms": round(sms / max(1, scnt), 4),
+                     "mfma_tflops": round(schur_flops * args.steps / (sms * 1e-3) / 1e12, 1)
+                     if sms > 0 else None,
+                     "mfma_peak_tflops": mma_peak},
+        "scaled_residual": rho,
+        "refinement": {"outer": reps[-1]["outer_iters"], "inner": reps[-1]["inner_iters"],
+                       "converged": reps[-1]["converged"],
+                       "t_convert_ms": round(reps[-1]["t_convert_ms"], 3),
+                       "t_factor_ms": round(reps[-1]["t_factor_ms"], 3),
+                       "t_refine_ms": round(reps[-1]["t_refine_ms"], 3)},
+        "phases_ms_per_step": phases,
+    }
+    del A, work
+    torch.cuda.empty_cache()
+    prec_id = 0 if prec == "bf16" else 2
+    return out, (lambda: cpu_baseline_mxp(cfg, seed, prec_id))
+
+
 def copy_calibration(nbytes):
     """A plain device copy of known size (rocprofv3 counter calibration)."""
     import torch
@@ -195,7 +295,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="fp64_large",
-                    choices=["fp64_large", "fp64_small"])
+                    choices=["fp64_large", "fp64_small", "bf16_ir", "fp8_ir"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="run only a plain copy of this many bytes (counter calibration)")
@@ -220,7 +320,10 @@ def main():
     from paper_2604_09517_amd import api, inputs
     api.lib()
     cfg = inputs.WORKLOADS[args.workload]
-    out, cpu = run_fp64(args, cfg)
+    if args.workload.startswith("fp64"):
+        out, cpu = run_fp64(args, cfg)
+    else:
+        out, cpu = run_mxp(args, cfg, args.workload)
     line = {
         "metric": out.pop("metric"),
         "value": out.pop("value"),

@@ -194,10 +194,11 @@ int mxlu_scaled_residual(int64_t n, int64_t nrhs, const double *A, int64_t lda,
  * Instrumentation (not part of the method): per-phase GPU time measured with
  * HIP events on the caller's stream.  Phases: 0 PFACT, 1 SWAP, 2 DTRSM,
  * 3 DGEMM trailing update, 4 solve, 5 conversion, 6 low-precision LU,
- * 7 refinement.  mxlu_profile_read synchronises on the recorded events and
- * returns, per phase, the summed milliseconds, the summed nominal work (flops
- * for DGEMM: 2 M N K per launch) and the number of intervals; arrays are HOST
- * arrays of `nphase` entries (any may be NULL).
+ * 7 refinement, 8 low-precision trailing update.  mxlu_profile_read
+ * synchronises on the recorded events and returns, per phase, the summed
+ * milliseconds, the summed nominal work (flops for DGEMM: 2 M N K per launch;
+ * bytes for phase 8: 4 M N + operand bytes) and the number of intervals;
+ * arrays are HOST arrays of `nphase` entries (any may be NULL).
  */
 int mxlu_profile_enable(int on);
 int mxlu_profile_reset(void);

@@ -216,7 +216,8 @@ def exported_symbols():
     return list(_lib.SIGNATURES)
 
 
-PHASES = ["pfact", "swap", "trsm", "gemm", "solve", "convert", "lp_factor", "refine"]
+PHASES = ["pfact", "swap", "trsm", "gemm", "solve", "convert", "lp_factor", "refine",
+          "lp_schur"]
 
 
 def profile_enable(on=True):

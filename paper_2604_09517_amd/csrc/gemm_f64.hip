@@ -200,7 +200,8 @@ __global__ __launch_bounds__(256) void gemm_f64_sub_skinny_kernel(
 namespace mxlu {
 
 int gemm_f64_sub(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
-                 const double *B, int64_t ldb, double *C, int64_t ldc, hipStream_t s) {
+                 const double *B, int64_t ldb, double *C, int64_t ldc, hipStream_t s,
+                 bool trailing) {
     if (M <= 0 || N <= 0 || K <= 0) return 0;
     if (N <= 16) {
         const unsigned grid = (unsigned)((M + 255) / 256);
@@ -218,7 +219,9 @@ int gemm_f64_sub(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
         set_error_msg("gemm_f64_sub: grid too large");
         return MXLU_E_NOMEM;
     }
-    const bool full = (M % BM == 0) && (N % BN == 0) && (K % BK == 0);
+    // the bounds-check-free instance serves the trailing update only, so that
+    // its launches are exactly the DGEMM phase
+    const bool full = trailing && (M % BM == 0) && (N % BN == 0) && (K % BK == 0);
     const dim3 grid((unsigned)(tiles_m * tiles_n));
     if (full)
         hipLaunchKernelGGL((gemm_f64_sub_kernel<true, false, false>), grid, dim3(256), 0, s, M, N,

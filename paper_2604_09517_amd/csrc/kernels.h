@@ -9,18 +9,21 @@
 namespace mxlu {
 
 // C(M x N) -= A(M x K) * B(K x N), FP64, column-major.
+// `trailing` marks the DGEMM phase of the factorization (its own kernel
+// instance, so that profiles separate it from the updates inside the panel).
 int gemm_f64_sub(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
-                 const double *B, int64_t ldb, double *C, int64_t ldc, hipStream_t s);
+                 const double *B, int64_t ldb, double *C, int64_t ldc, hipStream_t s,
+                 bool trailing = false);
 // C(M x N) = (accumulate ? C : 0) - A(M x K) * B(N x K)^T.
 int gemm_f64_nt_sub(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
                     const double *B, int64_t ldb, double *C, int64_t ldc, bool accumulate,
                     hipStream_t s);
 
-// Exchange area of the multi-workgroup panel kernel.
+// Exchange area of the multi-workgroup panel kernel (64-bit words, each a
+// 32-bit payload tagged with a 32-bit column sequence number).
 struct PanelExchange {
-    double *cand;     // [2][kMaxGroups][kLeafW + 2]
-    double *rowj;     // [2][kLeafW]
-    int *counters;    // one zeroed counter per matrix column
+    uint64_t *slots;  // [2][kMaxGroups][kLeafW * 2 + 4] candidate slots
+    uint64_t *rowj;   // [2][kLeafW * 2] the current pivot row's old contents
     int *flags;       // [0]: first zero pivot (1-based), [1]: wait expired
 };
 constexpr int kLeafW = 32;        // columns factored by one leaf kernel
@@ -29,7 +32,8 @@ constexpr int kMaxGroups = 256;   // workgroups of one leaf kernel (<= CUs)
 // Factor the m x w (w <= kLeafW) leaf whose top-left element is P (leading
 // dimension ldp) with partial pivoting.  r0 is the leaf's first row/column
 // index within the caller's numbering: ipiv[r0 .. r0+w) receives r0 + the
-// pivot row within the leaf, and ex.counters[r0 ..] are its barrier counters.
+// pivot row within the leaf; the column numbers r0 + j + 1 are the values of
+// the workgroups' sequence flags, so they must grow from leaf to leaf.
 template <typename T>
 int panel_leaf(int64_t m, int w, T *P, int64_t ldp, int64_t r0, int32_t *ipiv,
                const PanelExchange &ex, hipStream_t s);

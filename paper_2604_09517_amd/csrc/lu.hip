@@ -107,12 +107,16 @@ template int panel_factor<float>(float *, int64_t, int64_t, int64_t, int64_t, in
                                  const PanelExchange &, int *, hipStream_t);
 
 int alloc_panel_exchange(Scratch &scratch, int64_t n, PanelExchange *ex, hipStream_t s) {
-    ex->cand = scratch.alloc_n<double>((size_t)2 * kMaxGroups * (kLeafW + 2));
-    ex->rowj = scratch.alloc_n<double>((size_t)2 * kLeafW);
-    ex->counters = scratch.alloc_n<int>((size_t)(n > 0 ? n : 1));
+    const size_t slot_words = (size_t)2 * kMaxGroups * (2 * kLeafW + 4);
+    const size_t rowj_words = (size_t)2 * 2 * kLeafW;
+    ex->slots = scratch.alloc_n<uint64_t>(slot_words);
+    ex->rowj = scratch.alloc_n<uint64_t>(rowj_words);
     ex->flags = scratch.alloc_n<int>(4);
-    if (!ex->cand || !ex->rowj || !ex->counters || !ex->flags) return MXLU_E_NOMEM;
-    MXLU_HIP_TRY(hipMemsetAsync(ex->counters, 0, sizeof(int) * (size_t)(n > 0 ? n : 1), s));
+    (void)n;
+    if (!ex->slots || !ex->rowj || !ex->flags) return MXLU_E_NOMEM;
+    // sequence number 0 is never current: zeroed words never match
+    MXLU_HIP_TRY(hipMemsetAsync(ex->slots, 0, sizeof(uint64_t) * slot_words, s));
+    MXLU_HIP_TRY(hipMemsetAsync(ex->rowj, 0, sizeof(uint64_t) * rowj_words, s));
     MXLU_HIP_TRY(hipMemsetAsync(ex->flags, 0, sizeof(int) * 4, s));
     return 0;
 }
@@ -150,7 +154,8 @@ int factor_impl(int64_t n, int64_t nb, double *A, int64_t lda, int32_t *ipiv, hi
                 const double mt = (double)(n - c1);
                 PhaseScope ph(kPhaseGemm, s, 2.0 * mt * mt * (double)kb);
                 MXLU_TRY(gemm_f64_sub(n - c1, n - c1, kb, &MXLU_AT(A, c1, k0, lda), lda,
-                                 &MXLU_AT(A, k0, c1, lda), lda, &MXLU_AT(A, c1, c1, lda), lda, s));
+                                      &MXLU_AT(A, k0, c1, lda), lda, &MXLU_AT(A, c1, c1, lda),
+                                      lda, s, true));
             }
         }
     }
@@ -278,7 +283,7 @@ extern "C" int mxlu_schur_update_f64(int64_t M, int64_t N, int64_t K, const doub
     if (M == 0 || N == 0 || K == 0) return 0;
     if (int rc = check_device()) return rc;
     clear_error();
-    return gemm_f64_sub(M, N, K, A, lda, B, ldb, C, ldc, (hipStream_t)stream);
+    return gemm_f64_sub(M, N, K, A, lda, B, ldb, C, ldc, (hipStream_t)stream, true);
 }
 
 extern "C" int mxlu_outer_update_f64(int64_t M, int64_t N, int64_t K, const double *A,

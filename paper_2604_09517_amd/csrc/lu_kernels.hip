@@ -5,6 +5,7 @@
 // plus the permutation helpers of the solve (Sec. III-A.1).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 
 #include "common.h"
@@ -38,53 +39,59 @@ __device__ __forceinline__ void wave_argmax(double &v, int &idx) {
     }
 }
 
-// 256-thread argmax; every thread returns the result.
-__device__ __forceinline__ void block_argmax(double &v, int &idx, double *sv, int *si) {
-    wave_argmax(v, idx);
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        sv[w] = v;
-        si[w] = idx;
-    }
-    __syncthreads();
-    v = sv[0];
-    idx = si[0];
-#pragma unroll
-    for (int k = 1; k < 4; ++k) argmax_merge(v, idx, sv[k], si[k]);
-    __syncthreads();
-}
-
 // ---------------------------------------------------------------------------
 // PFACT leaf: columns [r0, r0 + w) of rows [r0, r0 + m), w <= kLeafW.
 // Workgroup g keeps rows [g R, g R + R) of the leaf in LDS (column-major,
-// stride R) for the whole kernel.  Per column j:
+// stride R) for the whole kernel; thread t owns the rows t, t + 256, ...
+// of its group.  Per column j:
 //   1. local candidate: first row >= j of largest |a_ij| in the group;
 //   2. publish (|a|, row, full leaf row) and, by the owner, row j itself;
-//   3. grid barrier (one agent-scope atomic counter per matrix column);
-//   4. every group reduces the G candidates to the same winner p;
-//   5. owners of rows j and p swap them (whole leaf rows);
-//   6. rows > j: divide column j by the pivot, rank-1 update of columns > j.
+//   3. gather every group's slot into LDS; every wave reduces the G
+//      candidates to the same winner p;
+//   4. the owner threads of rows j and p swap those rows (whole leaf rows);
+//   5. every thread divides column j of its rows > j by the pivot and
+//      applies the rank-1 update to their columns > j.
+// Exchange protocol: every 64-bit word of a slot carries 32 bits of payload
+// and, in its upper half, the sequence number r0 + j + 1 of the column; it is
+// written and read with agent-scope relaxed atomics, and a reader polls each
+// word until it carries the current sequence number.  A word is atomic, so
+// its payload is the one written with that number: no fences and no separate
+// flag are needed.  Slots are double-buffered by the parity of j: a group
+// overwrites its slot of column j only after it has gathered every slot of
+// column j-1, which every group publishes only after it has gathered column
+// j-2.  Sequence numbers grow during one factorization, so words left by
+// earlier columns or leaves never match.  Steps 4-5 touch only a thread's
+// own rows, so a column costs two workgroup barriers and one round trip.
 // An exactly zero pivot column is left unscaled; flags[0] records the first
-// such column (1-based).  The wait in step 3 is bounded: on expiry flags[1]
-// is set and the kernel runs to completion with invalid results.
-// Candidate slots are double-buffered by the parity of j: a group writes the
-// slots of column j only after barrier j-1, which every group reaches after
-// it has read the slots of column j-2.
+// such column (1-based).  The polling is bounded: on expiry flags[1] is set
+// and the kernel runs to completion with invalid results.
 // ---------------------------------------------------------------------------
+constexpr int kSlotWords = 2 + 1 + 2 * mxlu::kLeafW + 1;   // |a|, row, leaf row, pad
+constexpr int kRowjWords = 2 * mxlu::kLeafW;
+
+__device__ __forceinline__ void ll_store(uint64_t *p, uint32_t seq, uint32_t payload) {
+    __hip_atomic_store(p, ((uint64_t)seq << 32) | payload, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void panel_leaf_kernel(
     int m, int w, T *__restrict__ P, int64_t lda, int R, int G, int64_t r0,
-    int32_t *__restrict__ ipiv, double *cand, double *rowj, int *counters, int *flags) {
-    extern __shared__ __attribute__((aligned(16))) unsigned char sp_raw[];
-    T *sp = reinterpret_cast<T *>(sp_raw);   // [kLeafW][R]
-    __shared__ T s_prow[mxlu::kLeafW], s_rowj[mxlu::kLeafW];
-    __shared__ double s_v[4];
-    __shared__ int s_i[4];
-    constexpr int SLOT = mxlu::kLeafW + 2;
+    int32_t *__restrict__ ipiv, uint64_t *slots, uint64_t *rowj, int *flags) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+    uint32_t *s_words = reinterpret_cast<uint32_t *>(lds_raw);          // [G][kSlotWords]
+    T *sp = reinterpret_cast<T *>(lds_raw + sizeof(uint32_t) * (size_t)G * kSlotWords);
+    __shared__ uint32_t s_rowj[kRowjWords];
+    __shared__ double s_wv[4];
+    __shared__ int s_wi[4];
 
     const int g = blockIdx.x, tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
     const int rb = g * R;
     const int rows = min(R, m - rb);
+    auto word_double = [](const uint32_t *q) {
+        return __longlong_as_double((long long)(((uint64_t)q[1] << 32) | q[0]));
+    };
 
     for (int c = 0; c < w; ++c)
         for (int i = tid; i < rows; i += 256) sp[c * R + i] = MXLU_AT(P, rb + i, c, lda);
@@ -92,6 +99,8 @@ __global__ __launch_bounds__(256) void panel_leaf_kernel(
 
     for (int j = 0; j < w; ++j) {
         const int par = j & 1;
+        const uint32_t seq = (uint32_t)(r0 + j + 1);
+        // 1. local candidate (own rows), then the group's
         double v = -1.0;
         int idx = INT_MAX;
         for (int i = tid; i < rows; i += 256) {
@@ -103,70 +112,89 @@ __global__ __launch_bounds__(256) void panel_leaf_kernel(
                 }
             }
         }
-        block_argmax(v, idx, s_v, s_i);
-
-        double *mine = cand + ((size_t)par * mxlu::kMaxGroups + g) * SLOT;
-        if (tid == 0) {
-            mine[0] = v;
-            mine[1] = (double)idx;
+        wave_argmax(v, idx);
+        if (lane == 0) {
+            s_wv[wave] = v;
+            s_wi[wave] = idx;
         }
-        if (tid < w && idx != INT_MAX) mine[2 + tid] = (double)sp[tid * R + (idx - rb)];
-        if (tid < w && j >= rb && j < rb + rows)
-            rowj[par * mxlu::kLeafW + tid] = (double)sp[tid * R + (j - rb)];
         __syncthreads();
+        v = s_wv[0];
+        idx = s_wi[0];
+#pragma unroll
+        for (int k = 1; k < 4; ++k) argmax_merge(v, idx, s_wv[k], s_wi[k]);
 
-        if (G > 1) {
-            // every wave releases its own slot writes at agent scope, one
-            // thread arrives and waits, every wave acquires
-            __threadfence();
-            __syncthreads();
-            if (tid == 0) {
-                atomicAdd(&counters[j], 1);
-                long spins = 0;
-                while (__hip_atomic_load(&counters[j], __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT) < G) {
-                    __builtin_amdgcn_s_sleep(1);
-                    if (++spins > (1L << 26)) {
-                        atomicExch(&flags[1], 1);
-                        break;
-                    }
-                }
-            }
-            __syncthreads();
-            __threadfence();
+        // 2. publish
+        uint64_t *mine = slots + ((size_t)par * mxlu::kMaxGroups + g) * kSlotWords;
+        if (tid == 0) {
+            const uint64_t vb = (uint64_t)__double_as_longlong(v);
+            ll_store(&mine[0], seq, (uint32_t)vb);
+            ll_store(&mine[1], seq, (uint32_t)(vb >> 32));
+            ll_store(&mine[2], seq, (uint32_t)idx);
         }
+        if (tid < w) {
+            const uint64_t xb = (idx != INT_MAX)
+                                    ? (uint64_t)__double_as_longlong((double)sp[tid * R + (idx - rb)])
+                                    : 0ull;
+            ll_store(&mine[3 + 2 * tid], seq, (uint32_t)xb);
+            ll_store(&mine[4 + 2 * tid], seq, (uint32_t)(xb >> 32));
+            if (j >= rb && j < rb + rows) {
+                const uint64_t yb = (uint64_t)__double_as_longlong((double)sp[tid * R + (j - rb)]);
+                ll_store(&rowj[par * kRowjWords + 2 * tid], seq, (uint32_t)yb);
+                ll_store(&rowj[par * kRowjWords + 2 * tid + 1], seq, (uint32_t)(yb >> 32));
+            }
+        }
+
+        // 3. gather all slots (and row j) into LDS, polling each word
+        const uint64_t *gslots = slots + (size_t)par * mxlu::kMaxGroups * kSlotWords;
+        const int nslot = G * kSlotWords;
+        for (int t = tid; t < nslot + kRowjWords; t += 256) {
+            const bool is_slot = t < nslot;
+            if (is_slot && (t % kSlotWords) == kSlotWords - 1) continue;   // pad word
+            if (is_slot && (t % kSlotWords) >= 3 + 2 * w && (t % kSlotWords) < kSlotWords - 1)
+                continue;                                                   // unused row words
+            if (!is_slot && (t - nslot) >= 2 * w) continue;
+            const uint64_t *src = is_slot ? &gslots[t] : &rowj[par * kRowjWords + (t - nslot)];
+            uint64_t x = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            long spins = 0;
+            while ((uint32_t)(x >> 32) != seq) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > (1L << 26)) {
+                    atomicExch(&flags[1], 1);
+                    break;
+                }
+                x = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (is_slot) s_words[t] = (uint32_t)x;
+            else s_rowj[t - nslot] = (uint32_t)x;
+        }
+        __syncthreads();
 
         double gv = -1.0;
         int gi = INT_MAX;
-        if (tid < G) {
-            const double *c = cand + ((size_t)par * mxlu::kMaxGroups + tid) * SLOT;
-            gv = c[0];
-            const double di = c[1];
-            gi = (di >= (double)INT_MAX) ? INT_MAX : (int)di;
+        for (int t = lane; t < G; t += 64) {
+            const double cv = word_double(&s_words[t * kSlotWords]);
+            const int ci = (int)s_words[t * kSlotWords + 2];
+            argmax_merge(gv, gi, cv, ci);
         }
-        block_argmax(gv, gi, s_v, s_i);
-        // gi is a valid row >= j: group 0's own candidate at least exists
-        // whenever some row >= j is left, which always holds for j < m.
+        wave_argmax(gv, gi);
+        // gi is a valid row >= j (the group holding row j has a candidate)
         const int p = gi;
-        const int gw = p / R;
-        if (tid < w) {   // values of the matrix's own type, exact through double
-            s_prow[tid] = (T)cand[((size_t)par * mxlu::kMaxGroups + gw) * SLOT + 2 + tid];
-            s_rowj[tid] = (T)rowj[par * mxlu::kLeafW + tid];
-        }
-        __syncthreads();
-
+        const uint32_t *prow = s_words + (size_t)(p / R) * kSlotWords + 3;
         const bool nonzero = (gv != 0.0);
-        if (nonzero && p != j && tid < w) {
-            if (j >= rb && j < rb + rows) sp[tid * R + (j - rb)] = s_prow[tid];
-            if (p >= rb && p < rb + rows) sp[tid * R + (p - rb)] = s_rowj[tid];
-        }
         if (g == 0 && tid == 0) {
             ipiv[j] = (int32_t)(r0 + (nonzero ? p : j));
             if (!nonzero && flags[0] == 0) flags[0] = (int)(r0 + j + 1);
         }
-        __syncthreads();
 
-        const T piv = s_prow[j];
+        // 4. swap (owner threads of rows j and p, whole leaf rows)
+        if (nonzero && p != j) {
+            if (j >= rb && j < rb + rows && ((j - rb) & 255) == tid)
+                for (int c = 0; c < w; ++c) sp[c * R + (j - rb)] = (T)word_double(&prow[2 * c]);
+            if (p >= rb && p < rb + rows && ((p - rb) & 255) == tid)
+                for (int c = 0; c < w; ++c) sp[c * R + (p - rb)] = (T)word_double(&s_rowj[2 * c]);
+        }
+        // 5. scale and rank-1 update of the own rows below the pivot
+        const T piv = (T)word_double(&prow[2 * j]);
         for (int i = tid; i < rows; i += 256) {
             if (rb + i > j) {
                 T l = sp[j * R + i];
@@ -175,12 +203,11 @@ __global__ __launch_bounds__(256) void panel_leaf_kernel(
                     sp[j * R + i] = l;
                 }
                 for (int c = j + 1; c < w; ++c)
-                    sp[c * R + i] = fma(-l, s_prow[c], sp[c * R + i]);
+                    sp[c * R + i] = fma(-l, (T)word_double(&prow[2 * c]), sp[c * R + i]);
             }
         }
-        __syncthreads();
     }
-
+    __syncthreads();
     for (int c = 0; c < w; ++c)
         for (int i = tid; i < rows; i += 256) MXLU_AT(P, rb + i, c, lda) = sp[c * R + i];
 }
@@ -497,28 +524,32 @@ int panel_leaf(int64_t m, int w, T *P, int64_t ldp, int64_t r0, int32_t *ipiv,
         set_error_msg("panel_leaf: bad shape");
         return MXLU_E_NOMEM;
     }
-    // dynamic LDS budget: the device limit minus room for the static arrays
-    const int max_lds = max_dynamic_lds() - 1024;
-    const int rmax = max_lds / (kLeafW * (int)sizeof(T));
-    // about 64 groups; each group at least 256 rows, at most what LDS holds
-    int R = (int)((m + 63) / 64);
-    if (R < 256) R = 256;
-    if (R > rmax) R = rmax;
-    const int64_t G = (m + R - 1) / R;
-    if (G > kMaxGroups) {
-        set_error_msg("panel_leaf_f64: panel too tall for the LDS of the device");
+    // dynamic LDS: the G candidate slots and the group's rows of the leaf;
+    // about 64 groups of at least 256 rows, more groups when LDS is short
+    const int64_t budget = max_dynamic_lds() - 1024;
+    int64_t R = std::max<int64_t>(256, (m + 63) / 64);
+    int64_t G = (m + R - 1) / R;
+    auto need = [&](int64_t r, int64_t g) {
+        return (int64_t)sizeof(uint32_t) * g * kSlotWords + (int64_t)sizeof(T) * kLeafW * r;
+    };
+    while (need(R, G) > budget && G < kMaxGroups) {
+        R = std::max<int64_t>(64, (R * 7) / 8);
+        G = (m + R - 1) / R;
+    }
+    if (G > kMaxGroups || need(R, G) > budget) {
+        set_error_msg("panel_leaf: panel too tall for the LDS of the device");
         return MXLU_E_NOMEM;
     }
-    const size_t lds = (size_t)kLeafW * R * sizeof(T);
+    const size_t lds = (size_t)need(R, G);
     static bool attr_set = false;
     if (!attr_set) {
         MXLU_HIP_TRY(hipFuncSetAttribute((const void *)panel_leaf_kernel<T>,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, max_lds));
+                                         hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)budget));
         attr_set = true;
     }
     hipLaunchKernelGGL(panel_leaf_kernel<T>, dim3((unsigned)G), dim3(256), lds, s, (int)m, w, P,
-                       ldp, R, (int)G, r0, ipiv + r0, ex.cand, ex.rowj, ex.counters + r0,
-                       ex.flags);
+                       ldp, (int)R, (int)G, r0, ipiv + r0, ex.slots, ex.rowj, ex.flags);
     MXLU_LAUNCH_CHECK();
     return 0;
 }

@@ -128,12 +128,18 @@ int lp_factorize(const mxp_opts &o, int64_t n, const double *A, int64_t lda, uin
             MXLU_TRY(trsm_f32_llnu(kb, nt, P32, m, T32, kb, s));
             MXLU_TRY(lp_store_f32(fmt, kb, nt, T32, kb, U12, ldf, s));
             uint16_t *A22 = F + (size_t)c1 + (size_t)c1 * ldf;
+            // algorithmic bytes: A22 read and written in 16 bits, L21 and U12 read once
+            const double ob = fp8 ? 1.0 : 2.0;
+            const double schur_bytes =
+                4.0 * (double)nt * (double)nt + 2.0 * ob * (double)nt * (double)kb;
             if (fp8) {
                 const uint16_t *L21 = F + (size_t)c1 + (size_t)k0 * ldf;
                 MXLU_TRY(lp_quant_l21(fmt, nt, (int)kb, tile, L21, ldf, LTq, sL, s));
                 MXLU_TRY(lp_quant_u12(fmt, nt, (int)kb, tile, U12, ldf, Uq, sU, s));
+                PhaseScope ph(kPhaseLpSchur, s, schur_bytes);
                 MXLU_TRY(lp_schur_update_fp8(fmt, nt, nt, (int)kb, LTq, sL, Uq, sU, tile, A22, ldf, s));
             } else {
+                PhaseScope ph(kPhaseLpSchur, s, schur_bytes);
                 MXLU_TRY(lp_schur_update(fmt, nt, nt, (int)kb, LT, kb, U12, ldf, A22, ldf, s));
             }
         }

@@ -15,7 +15,8 @@ enum {
     kPhaseConvert = 5,   // FP64 -> low precision
     kPhaseLpFactor = 6,  // low-precision LU
     kPhaseRefine = 7,    // refinement loop
-    kPhaseCount = 8
+    kPhaseLpSchur = 8,   // low-precision trailing update (work = algorithmic bytes)
+    kPhaseCount = 9
 };
 
 bool profiling_enabled();

@@ -232,7 +232,14 @@ def test_lp_pivoted_first_panel_matches_oracle(api):
     piv = ipiv.cpu().numpy()
     assert rep["info"] == info == 0
     assert np.array_equal(piv[:nb], piv_ref[:nb])
-    assert np.array_equal(F[:, :nb], F_ref[:, :nb])
+    # later panels may legitimately pick other pivots (their inputs passed
+    # through the MFMA update) and move the first panel's rows differently:
+    # compare the first panel row by row of the original matrix
+    by_orig = np.empty_like(F[:, :nb])
+    by_orig[checks.perm_from_ipiv(piv, n)] = F[:, :nb]
+    by_orig_ref = np.empty_like(F_ref[:, :nb])
+    by_orig_ref[checks.perm_from_ipiv(piv_ref, n)] = F_ref[:, :nb]
+    assert np.array_equal(by_orig, by_orig_ref)
     # whole factorization: a valid interchange sequence and a small backward error
     assert np.all(piv >= np.arange(n)) and np.all(piv < n)
     p = checks.perm_from_ipiv(piv, n)
