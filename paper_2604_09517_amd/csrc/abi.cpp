@@ -13,6 +13,9 @@ static thread_local char g_last_error[512] = "";
 void set_error(const char *what, hipError_t e) {
     std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s", what,
                   hipGetErrorString(e));
+    // the failure is reported through the return code: do not leave it as
+    // the runtime's pending error for the caller's next, unrelated HIP call
+    (void)hipGetLastError();
 }
 
 void set_error_msg(const char *msg) {

@@ -56,3 +56,10 @@ class Scratch {
 
 // Offsets are 64-bit everywhere: n^2 exceeds 2^31 for the larger workloads.
 #define MXLU_AT(ptr, i, j, ld) ((ptr)[(size_t)(i) + (size_t)(j) * (size_t)(ld)])
+
+// Wait until every vector-memory load of the wave has returned (vmcnt(0)).
+// Used before a software-pipelined main loop whose accumulators were loaded
+// in the prologue: without it, the compiler's wait for those loads lands
+// inside the loop on the first use of each accumulator, where the in-order
+// counter also makes it wait for the next chunk's prefetch every iteration.
+__device__ __forceinline__ void retire_vector_loads() { __builtin_amdgcn_s_waitcnt(0x0F70); }

@@ -124,6 +124,7 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_sub_kernel(
     load_chunk(0);
     store_chunk(0);
     __syncthreads();
+    retire_vector_loads();
 
     for (int kt = 0; kt < nk; ++kt) {
         const int buf = kt & 1;

@@ -22,7 +22,7 @@ int gemm_f64_nt_sub(int64_t M, int64_t N, int64_t K, const double *A, int64_t ld
 // Exchange area of the multi-workgroup panel kernel (64-bit words, each a
 // 32-bit payload tagged with a 32-bit column sequence number).
 struct PanelExchange {
-    uint64_t *slots;  // [2][kMaxGroups][kLeafW * 2 + 4] candidate slots
+    uint64_t *slots;  // [2][kMaxGroups][4] candidates, then [2][kMaxGroups][kLeafW * 2] rows
     uint64_t *rowj;   // [2][kLeafW * 2] the current pivot row's old contents
     int *flags;       // [0]: first zero pivot (1-based), [1]: wait expired
 };

@@ -129,6 +129,7 @@ __global__ __launch_bounds__(256, 2) void lp_schur16_kernel(
     load(0);
     store(0);
     __syncthreads();
+    retire_vector_loads();
     for (int kt = 0; kt < nk; ++kt) {
         const int buf = kt & 1;
         if (kt + 1 < nk) load((kt + 1) * BK16);

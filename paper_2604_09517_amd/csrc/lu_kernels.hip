@@ -45,33 +45,65 @@ __device__ __forceinline__ void wave_argmax(double &v, int &idx) {
 // stride R) for the whole kernel; thread t owns the rows t, t + 256, ...
 // of its group.  Per column j:
 //   1. local candidate: first row >= j of largest |a_ij| in the group;
-//   2. publish (|a|, row, full leaf row) and, by the owner, row j itself;
-//   3. gather every group's slot into LDS; every wave reduces the G
-//      candidates to the same winner p;
+//   2. publish the candidate (|a|, row) and its whole leaf row and, by the
+//      owner, row j itself;
+//   3. gather: with at most kOnePhaseGroups groups, every group reads all
+//      candidates and candidate rows in one batch of loads; otherwise it
+//      reads the candidates first and then only the winner's row.  Every
+//      wave reduces the G candidates to the same winner p;
 //   4. the owner threads of rows j and p swap those rows (whole leaf rows);
 //   5. every thread divides column j of its rows > j by the pivot and
 //      applies the rank-1 update to their columns > j.
-// Exchange protocol: every 64-bit word of a slot carries 32 bits of payload
-// and, in its upper half, the sequence number r0 + j + 1 of the column; it is
-// written and read with agent-scope relaxed atomics, and a reader polls each
-// word until it carries the current sequence number.  A word is atomic, so
-// its payload is the one written with that number: no fences and no separate
-// flag are needed.  Slots are double-buffered by the parity of j: a group
-// overwrites its slot of column j only after it has gathered every slot of
-// column j-1, which every group publishes only after it has gathered column
-// j-2.  Sequence numbers grow during one factorization, so words left by
-// earlier columns or leaves never match.  Steps 4-5 touch only a thread's
-// own rows, so a column costs two workgroup barriers and one round trip.
-// An exactly zero pivot column is left unscaled; flags[0] records the first
-// such column (1-based).  The polling is bounded: on expiry flags[1] is set
-// and the kernel runs to completion with invalid results.
+// Exchange protocol: every 64-bit word carries 32 bits of payload and, in its
+// upper half, the sequence number r0 + j + 1 of the column; it is written and
+// read with agent-scope relaxed atomics, and a reader polls each word until
+// it carries the current sequence number.  A word is atomic, so its payload
+// is the one written with that number: no fences and no separate flag are
+// needed.  Every load of a phase is issued before the first wait, so a
+// column costs one round trip (two for many groups).  Buffers are
+// double-buffered by the parity of j: a group overwrites its words of column
+// j only after it has gathered every candidate of column j-1, which every
+// group publishes only after it has finished reading column j-2.  Sequence
+// numbers grow during one factorization, so words left by earlier columns or
+// leaves never match.  Steps 4-5 touch only a thread's own rows.  An exactly
+// zero pivot column is left unscaled; flags[0] records the first such column
+// (1-based).  The polling is bounded: on expiry flags[1] is set and the
+// kernel runs to completion with invalid results.
+// Layout of `slots`: [2][kMaxGroups][kSlotWords], a slot holding |a| (low,
+// high), the row index, one unused word and the candidate's leaf row (two
+// words per value); `rowj` is [2][kRowWords].
 // ---------------------------------------------------------------------------
-constexpr int kSlotWords = 2 + 1 + 2 * mxlu::kLeafW + 1;   // |a|, row, leaf row, pad
-constexpr int kRowjWords = 2 * mxlu::kLeafW;
+constexpr int kRowWords = 2 * mxlu::kLeafW;      // a leaf row, two words per value
+constexpr int kSlotWords = 4 + kRowWords;
+constexpr int kOnePhaseGroups = 8;               // one-batch gather up to this many groups
+constexpr int kOneBatch = (kOnePhaseGroups * kSlotWords + 255) / 256;
+constexpr int kCandPerThread = (mxlu::kMaxGroups * 3 + 255) / 256;
+constexpr int kWordsLds = (kOnePhaseGroups * kSlotWords > mxlu::kMaxGroups * 3)
+                              ? kOnePhaseGroups * kSlotWords
+                              : mxlu::kMaxGroups * 3;
 
 __device__ __forceinline__ void ll_store(uint64_t *p, uint32_t seq, uint32_t payload) {
     __hip_atomic_store(p, ((uint64_t)seq << 32) | payload, __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t ll_load(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Payload of *p once it carries `seq`; x is a load of *p already issued.
+__device__ __forceinline__ uint32_t ll_wait(const uint64_t *p, uint64_t x, uint32_t seq,
+                                           int *flags) {
+    long spins = 0;
+    while ((uint32_t)(x >> 32) != seq) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > (1L << 26)) {
+            atomicExch(&flags[1], 1);
+            break;
+        }
+        x = ll_load(p);
+    }
+    return (uint32_t)x;
 }
 
 template <typename T>
@@ -79,9 +111,12 @@ __global__ __launch_bounds__(256) void panel_leaf_kernel(
     int m, int w, T *__restrict__ P, int64_t lda, int R, int G, int64_t r0,
     int32_t *__restrict__ ipiv, uint64_t *slots, uint64_t *rowj, int *flags) {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
-    uint32_t *s_words = reinterpret_cast<uint32_t *>(lds_raw);          // [G][kSlotWords]
-    T *sp = reinterpret_cast<T *>(lds_raw + sizeof(uint32_t) * (size_t)G * kSlotWords);
-    __shared__ uint32_t s_rowj[kRowjWords];
+    T *sp = reinterpret_cast<T *>(lds_raw);     // [w][R]
+    // one-batch form: slot words of every group (slot layout); two-phase
+    // form: the 3 candidate words of every group, then the winner's row
+    __shared__ uint32_t s_words[kWordsLds];
+    __shared__ uint32_t s_prow[kRowWords];
+    __shared__ uint32_t s_rowj[kRowWords];
     __shared__ double s_wv[4];
     __shared__ int s_wi[4];
 
@@ -89,6 +124,7 @@ __global__ __launch_bounds__(256) void panel_leaf_kernel(
     const int lane = tid & 63, wave = tid >> 6;
     const int rb = g * R;
     const int rows = min(R, m - rb);
+    const bool one_phase = G <= kOnePhaseGroups;
     auto word_double = [](const uint32_t *q) {
         return __longlong_as_double((long long)(((uint64_t)q[1] << 32) | q[0]));
     };
@@ -100,6 +136,8 @@ __global__ __launch_bounds__(256) void panel_leaf_kernel(
     for (int j = 0; j < w; ++j) {
         const int par = j & 1;
         const uint32_t seq = (uint32_t)(r0 + j + 1);
+        uint64_t *gs = slots + (size_t)par * mxlu::kMaxGroups * kSlotWords;
+        uint64_t *grj = rowj + par * kRowWords;
         // 1. local candidate (own rows), then the group's
         double v = -1.0;
         int idx = INT_MAX;
@@ -124,7 +162,7 @@ __global__ __launch_bounds__(256) void panel_leaf_kernel(
         for (int k = 1; k < 4; ++k) argmax_merge(v, idx, s_wv[k], s_wi[k]);
 
         // 2. publish
-        uint64_t *mine = slots + ((size_t)par * mxlu::kMaxGroups + g) * kSlotWords;
+        uint64_t *mine = gs + (size_t)g * kSlotWords;
         if (tid == 0) {
             const uint64_t vb = (uint64_t)__double_as_longlong(v);
             ll_store(&mine[0], seq, (uint32_t)vb);
@@ -135,51 +173,74 @@ __global__ __launch_bounds__(256) void panel_leaf_kernel(
             const uint64_t xb = (idx != INT_MAX)
                                     ? (uint64_t)__double_as_longlong((double)sp[tid * R + (idx - rb)])
                                     : 0ull;
-            ll_store(&mine[3 + 2 * tid], seq, (uint32_t)xb);
-            ll_store(&mine[4 + 2 * tid], seq, (uint32_t)(xb >> 32));
+            ll_store(&mine[4 + 2 * tid], seq, (uint32_t)xb);
+            ll_store(&mine[5 + 2 * tid], seq, (uint32_t)(xb >> 32));
             if (j >= rb && j < rb + rows) {
                 const uint64_t yb = (uint64_t)__double_as_longlong((double)sp[tid * R + (j - rb)]);
-                ll_store(&rowj[par * kRowjWords + 2 * tid], seq, (uint32_t)yb);
-                ll_store(&rowj[par * kRowjWords + 2 * tid + 1], seq, (uint32_t)(yb >> 32));
+                ll_store(&grj[2 * tid], seq, (uint32_t)yb);
+                ll_store(&grj[2 * tid + 1], seq, (uint32_t)(yb >> 32));
             }
         }
 
-        // 3. gather all slots (and row j) into LDS, polling each word
-        const uint64_t *gslots = slots + (size_t)par * mxlu::kMaxGroups * kSlotWords;
-        const int nslot = G * kSlotWords;
-        for (int t = tid; t < nslot + kRowjWords; t += 256) {
-            const bool is_slot = t < nslot;
-            if (is_slot && (t % kSlotWords) == kSlotWords - 1) continue;   // pad word
-            if (is_slot && (t % kSlotWords) >= 3 + 2 * w && (t % kSlotWords) < kSlotWords - 1)
-                continue;                                                   // unused row words
-            if (!is_slot && (t - nslot) >= 2 * w) continue;
-            const uint64_t *src = is_slot ? &gslots[t] : &rowj[par * kRowjWords + (t - nslot)];
-            uint64_t x = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            long spins = 0;
-            while ((uint32_t)(x >> 32) != seq) {
-                __builtin_amdgcn_s_sleep(1);
-                if (++spins > (1L << 26)) {
-                    atomicExch(&flags[1], 1);
-                    break;
-                }
-                x = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            if (is_slot) s_words[t] = (uint32_t)x;
-            else s_rowj[t - nslot] = (uint32_t)x;
-        }
-        __syncthreads();
-
+        // 3. gather
         double gv = -1.0;
         int gi = INT_MAX;
-        for (int t = lane; t < G; t += 64) {
-            const double cv = word_double(&s_words[t * kSlotWords]);
-            const int ci = (int)s_words[t * kSlotWords + 2];
-            argmax_merge(gv, gi, cv, ci);
+        const uint32_t *prow;
+        bool swap;
+        if (one_phase) {
+            // every slot word in use, and row j, in one batch
+            const int nw = G * kSlotWords;
+            uint64_t x[kOneBatch];
+#pragma unroll
+            for (int k = 0; k < kOneBatch; ++k) {
+                const int t = tid + 256 * k, u = t % kSlotWords;
+                x[k] = (t < nw && u != 3 && u < 4 + 2 * w) ? ll_load(&gs[t]) : 0ull;
+            }
+            const uint64_t y = (tid < 2 * w) ? ll_load(&grj[tid]) : 0ull;
+#pragma unroll
+            for (int k = 0; k < kOneBatch; ++k) {
+                const int t = tid + 256 * k, u = t % kSlotWords;
+                if (t < nw && u != 3 && u < 4 + 2 * w) s_words[t] = ll_wait(&gs[t], x[k], seq, flags);
+            }
+            if (tid < 2 * w) s_rowj[tid] = ll_wait(&grj[tid], y, seq, flags);
+            __syncthreads();
+            for (int t = lane; t < G; t += 64)
+                argmax_merge(gv, gi, word_double(&s_words[t * kSlotWords]),
+                             (int)s_words[t * kSlotWords + 2]);
+            wave_argmax(gv, gi);
+            prow = &s_words[(gi / R) * kSlotWords + 4];
+            swap = (gv != 0.0) && gi != j;
+        } else {
+            // the candidates first, then the winner's row (and row j when it moves)
+            const int nc = G * 3;
+            uint64_t x[kCandPerThread];
+#pragma unroll
+            for (int k = 0; k < kCandPerThread; ++k) {
+                const int t = tid + 256 * k;
+                x[k] = (t < nc) ? ll_load(&gs[(t / 3) * kSlotWords + t % 3]) : 0ull;
+            }
+#pragma unroll
+            for (int k = 0; k < kCandPerThread; ++k) {
+                const int t = tid + 256 * k;
+                if (t < nc) s_words[t] = ll_wait(&gs[(t / 3) * kSlotWords + t % 3], x[k], seq, flags);
+            }
+            __syncthreads();
+            for (int t = lane; t < G; t += 64)
+                argmax_merge(gv, gi, word_double(&s_words[3 * t]), (int)s_words[3 * t + 2]);
+            wave_argmax(gv, gi);
+            swap = (gv != 0.0) && gi != j;
+            if (tid < 2 * w) {
+                const uint64_t *src = gs + (size_t)(gi / R) * kSlotWords + 4 + tid;
+                s_prow[tid] = ll_wait(src, ll_load(src), seq, flags);
+            } else if (swap && tid >= 64 && tid < 64 + 2 * w) {
+                const uint64_t *src = &grj[tid - 64];
+                s_rowj[tid - 64] = ll_wait(src, ll_load(src), seq, flags);
+            }
+            __syncthreads();
+            prow = s_prow;
         }
-        wave_argmax(gv, gi);
         // gi is a valid row >= j (the group holding row j has a candidate)
         const int p = gi;
-        const uint32_t *prow = s_words + (size_t)(p / R) * kSlotWords + 3;
         const bool nonzero = (gv != 0.0);
         if (g == 0 && tid == 0) {
             ipiv[j] = (int32_t)(r0 + (nonzero ? p : j));
@@ -187,7 +248,7 @@ __global__ __launch_bounds__(256) void panel_leaf_kernel(
         }
 
         // 4. swap (owner threads of rows j and p, whole leaf rows)
-        if (nonzero && p != j) {
+        if (swap) {
             if (j >= rb && j < rb + rows && ((j - rb) & 255) == tid)
                 for (int c = 0; c < w; ++c) sp[c * R + (j - rb)] = (T)word_double(&prow[2 * c]);
             if (p >= rb && p < rb + rows && ((p - rb) & 255) == tid)
@@ -206,6 +267,9 @@ __global__ __launch_bounds__(256) void panel_leaf_kernel(
                     sp[c * R + i] = fma(-l, (T)word_double(&prow[2 * c]), sp[c * R + i]);
             }
         }
+        // the next column's step 1 reads s_wv/s_wi only after its own barrier,
+        // and s_words/s_prow/s_rowj are rewritten only after the next gather's
+        // waits, which follow that barrier
     }
     __syncthreads();
     for (int c = 0; c < w; ++c)
@@ -214,13 +278,15 @@ __global__ __launch_bounds__(256) void panel_leaf_kernel(
 
 // ---------------------------------------------------------------------------
 // SWAP.  compose: one workgroup turns the interchange sequence
-// ipiv[j0 .. j0+cnt) (rows >= j0) into a list of moves (dst row <- src row):
-// slots 0..cnt-1 stand for rows j0..j0+cnt-1, further slots for the distinct
-// rows beyond them, numbered in order of first appearance; the interchanges
-// are replayed on slot contents, and every slot whose content changed is one
-// move.  apply: each workgroup copies the moves for a strip of columns,
-// staging the gathered values in LDS so that all reads of a column precede
-// all of its writes.
+// ipiv[j0 .. j0+cnt) (rows >= j0) into a list of moves (dst row <- src row).
+// The rows that can change are rows j0 .. j0+cnt-1 and the distinct pivot
+// rows beyond them (taken in order of first appearance).  For each such row
+// d, the row whose contents end up in d is found by applying the
+// interchanges to d in reverse order (each thread follows its own rows; the
+// pivot list is read from LDS by all threads in step); every row whose
+// source differs is one move.  apply: each workgroup copies the moves for a
+// strip of columns, staging the gathered values in LDS so that all reads of
+// a column precede all of its writes.
 // ---------------------------------------------------------------------------
 constexpr int kMaxSwaps = 1024;
 
@@ -228,74 +294,47 @@ __global__ __launch_bounds__(256) void swap_compose_kernel(const int32_t *__rest
                                                            int64_t j0, int cnt,
                                                            int *__restrict__ moves) {
     __shared__ int s_piv[kMaxSwaps];
-    __shared__ int s_first[kMaxSwaps];
-    __shared__ int s_slot[kMaxSwaps];
-    __shared__ int s_ext[kMaxSwaps];
-    __shared__ int s_content[2 * kMaxSwaps];
-    __shared__ int s_nslots;
     __shared__ int s_wsum[4];
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
     for (int t = tid; t < cnt; t += 256) s_piv[t] = (int)(ipiv[j0 + t] - j0);  // relative
     __syncthreads();
-    for (int t = tid; t < cnt; t += 256) {
-        const int p = s_piv[t];
-        int first = t;
-        if (p >= cnt)
-            for (int u = 0; u < t; ++u)
-                if (s_piv[u] == p) {
-                    first = u;
-                    break;
-                }
-        s_first[t] = first;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        int e = 0;
-        for (int t = 0; t < cnt; ++t) {
-            const int p = s_piv[t];
-            int sl;
-            if (p < cnt) sl = p;
-            else if (s_first[t] == t) {
-                s_ext[e] = p;
-                sl = cnt + e;
-                ++e;
-            } else sl = s_slot[s_first[t]];
-            s_slot[t] = sl;
-        }
-        s_nslots = cnt + e;
-    }
-    __syncthreads();
-    const int nslots = s_nslots;
-    for (int t = tid; t < nslots; t += 256) s_content[t] = t;
-    __syncthreads();
-    if (tid == 0) {
-        for (int t = 0; t < cnt; ++t) {
-            const int sl = s_slot[t];
-            const int a = s_content[t];
-            s_content[t] = s_content[sl];
-            s_content[sl] = a;
-        }
-    }
-    __syncthreads();
-    // compact the changed slots in slot order: moves = [count, dst..., src...]
+    // candidate t < cnt is row t; candidate cnt + u is the pivot row of
+    // interchange u when it lies beyond the block and appears there first
     int base = 0;
-    for (int t0 = 0; t0 < nslots; t0 += 256) {
+    for (int t0 = 0; t0 < 2 * cnt; t0 += 256) {
         const int t = t0 + tid;
-        const bool moved = (t < nslots) && (s_content[t] != t);
+        int d = -1;
+        if (t < cnt) {
+            d = t;
+        } else if (t < 2 * cnt) {
+            const int u = t - cnt;
+            const int q = s_piv[u];
+            if (q >= cnt) {
+                d = q;
+                for (int v = 0; v < u; ++v)
+                    if (s_piv[v] == q) {
+                        d = -1;
+                        break;
+                    }
+            }
+        }
+        int src = d;
+        for (int u = cnt - 1; u >= 0; --u) {
+            const int q = s_piv[u];
+            src = (src == u) ? q : ((src == q) ? u : src);
+        }
+        const bool moved = (d >= 0) && (src != d);
+        // compact in candidate order: moves = [count, dst..., src...]
         const unsigned long long mask = __ballot(moved);
-        const int lane = tid & 63, wv = tid >> 6;
         const int before = __popcll(mask & ((1ull << lane) - 1ull));
         if (lane == 0) s_wsum[wv] = __popcll(mask);
         __syncthreads();
         int off = base;
         for (int k = 0; k < wv; ++k) off += s_wsum[k];
         if (moved) {
-            const int pos = off + before;
-            const int src = s_content[t];
-            const int dst_row = (t < cnt) ? t : s_ext[t - cnt];
-            const int src_row = (src < cnt) ? src : s_ext[src - cnt];
-            moves[1 + pos] = dst_row;
-            moves[1 + 2 * kMaxSwaps + pos] = src_row;
+            moves[1 + off + before] = d;
+            moves[1 + 2 * kMaxSwaps + off + before] = src;
         }
         const int total = s_wsum[0] + s_wsum[1] + s_wsum[2] + s_wsum[3];
         __syncthreads();
@@ -503,6 +542,20 @@ __global__ void scatter_rows_kernel(int64_t n, int64_t nrhs, const int32_t *__re
 
 namespace mxlu {
 
+// Compute units of the current device: the leaf kernel's workgroups wait on
+// each other, so all of them must be resident at once (one per CU).
+static int compute_units() {
+    static int cached = 0;
+    if (!cached) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            v = 1;
+        cached = v;
+    }
+    return cached;
+}
+
 static int max_dynamic_lds() {
     static int cached = 0;
     if (!cached) {
@@ -524,23 +577,28 @@ int panel_leaf(int64_t m, int w, T *P, int64_t ldp, int64_t r0, int32_t *ipiv,
         set_error_msg("panel_leaf: bad shape");
         return MXLU_E_NOMEM;
     }
-    // dynamic LDS: the G candidate slots and the group's rows of the leaf;
-    // about 64 groups of at least 256 rows, more groups when LDS is short
-    const int64_t budget = max_dynamic_lds() - 1024;
+    // dynamic LDS: the group's rows of the leaf (the static part holds the
+    // gathered words); about 64 groups of at least 256 rows, more groups when
+    // LDS is short
+    static int64_t static_lds = -1;
+    if (static_lds < 0) {
+        hipFuncAttributes fa;
+        MXLU_HIP_TRY(hipFuncGetAttributes(&fa, (const void *)panel_leaf_kernel<T>));
+        static_lds = (int64_t)fa.sharedSizeBytes;
+    }
+    const int64_t budget = max_dynamic_lds() - static_lds;
     int64_t R = std::max<int64_t>(256, (m + 63) / 64);
     int64_t G = (m + R - 1) / R;
-    auto need = [&](int64_t r, int64_t g) {
-        return (int64_t)sizeof(uint32_t) * g * kSlotWords + (int64_t)sizeof(T) * kLeafW * r;
-    };
-    while (need(R, G) > budget && G < kMaxGroups) {
+    auto need = [&](int64_t r) { return (int64_t)sizeof(T) * kLeafW * r; };
+    while (need(R) > budget && G < kMaxGroups) {
         R = std::max<int64_t>(64, (R * 7) / 8);
         G = (m + R - 1) / R;
     }
-    if (G > kMaxGroups || need(R, G) > budget) {
+    if (G > kMaxGroups || G > compute_units() || need(R) > budget) {
         set_error_msg("panel_leaf: panel too tall for the LDS of the device");
         return MXLU_E_NOMEM;
     }
-    const size_t lds = (size_t)need(R, G);
+    const size_t lds = (size_t)need(R);
     static bool attr_set = false;
     if (!attr_set) {
         MXLU_HIP_TRY(hipFuncSetAttribute((const void *)panel_leaf_kernel<T>,

@@ -172,12 +172,14 @@ struct RefineCtx {
     double *r, *z, *w, *V, *part, *apart, *dotp, *hdev;
     float *v32;
     unsigned long long *stats;   // [0] |r|max [1] ||A|| [2] |x|max [3] precond s
+    TrsvChain ch{};
     int nsplit, nchunks;
     double anorm = -1.0;
 };
 
 int precond(RefineCtx &c, const double *r, double *d) {
-    return lp_precond_apply(c.fmt, c.trans, c.n, c.F, c.ldf, c.perm, r, d, c.v32, c.stats + 3, c.s);
+    return lp_precond_apply(c.fmt, c.trans, c.n, c.F, c.ldf, c.perm, r, d, c.v32, c.stats + 3,
+                            c.ch, c.s);
 }
 
 // r = b - op(A) x; returns the scaled residual (host sync).
@@ -427,9 +429,13 @@ extern "C" int mxp_solve(int64_t n, int64_t nrhs, const double *A, int64_t lda, 
     c.hdev = scratch.alloc_n<double>((size_t)2 * m1 + 8);
     c.v32 = scratch.alloc_n<float>((size_t)n);
     c.stats = scratch.alloc_n<unsigned long long>(8);
+    c.ch.xs = scratch.alloc_n<uint64_t>((size_t)n);
+    c.ch.expired = scratch.alloc_n<int>(1);
     if (!c.r || !c.z || !c.w || !c.V || !c.part || !c.apart || !c.dotp || !c.hdev || !c.v32 ||
-        !c.stats)
+        !c.stats || !c.ch.xs || !c.ch.expired)
         return MXLU_E_NOMEM;
+    MXLU_HIP_TRY(hipMemsetAsync(c.ch.xs, 0, sizeof(uint64_t) * (size_t)n, s));
+    MXLU_HIP_TRY(hipMemsetAsync(c.ch.expired, 0, sizeof(int), s));
 
     Timer tr(s);
     tr.start();
@@ -450,6 +456,13 @@ extern "C" int mxp_solve(int64_t n, int64_t nrhs, const double *A, int64_t lda, 
     }
     tr.stop();
     const double t_ref = tr.ms();
+    int expired = 0;
+    MXLU_HIP_TRY(hipMemcpyAsync(&expired, c.ch.expired, sizeof(int), hipMemcpyDeviceToHost, s));
+    MXLU_HIP_TRY(hipStreamSynchronize(s));
+    if (expired) {
+        mxlu::set_error_msg("mxp_solve: triangular-solve wait expired");
+        return MXLU_E_TIMEOUT;
+    }
     if (report) {
         report->converged = all_conv;
         report->outer_iters = outer_sum;

@@ -25,11 +25,20 @@ int gemv_small_f64(int64_t n, int k, const double *V, int64_t ldv, const double 
 int scale_copy_f64(int64_t n, const double *z, double alpha, double *v, hipStream_t s);
 int axpy_f64(int64_t n, const double *z, double *x, hipStream_t s);
 int absmax_f64(int64_t n, const double *v, unsigned long long *out, hipStream_t s);
+// State of the single-launch blocked triangular solves: xs holds n tagged
+// words (zeroed once at allocation), tag the last tag used (each solve takes
+// the next one), expired one device int set when a wait expires.
+struct TrsvChain {
+    uint64_t *xs;
+    int *expired;
+    uint32_t tag;
+};
+
 // d = M r (trans 0) or M^T r (trans 1) with M = U^-1 L^-1 P from the stored
 // factors F; perm (optional) is the row order of P.  v32: n floats scratch;
 // smax: one device word.
 int lp_precond_apply(int fmt, int trans, int64_t n, const uint16_t *F, int64_t ldf,
                      const int32_t *perm, const double *r, double *d, float *v32,
-                     unsigned long long *smax, hipStream_t s);
+                     unsigned long long *smax, TrsvChain &ch, hipStream_t s);
 
 }  // namespace mxlu

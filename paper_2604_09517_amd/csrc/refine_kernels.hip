@@ -206,100 +206,184 @@ __global__ void precond_out_kernel(int64_t n, const float *__restrict__ v32,
     d[perm ? perm[i] : i] = s > 0.0 ? s * (double)v32[i] : 0.0;
 }
 
-// Blocked triangular solve in FP32 with the stored factor F (16-bit),
-// blocks of kTrsvBs rows.  Launch `step` (one per block, in solve order)
-// first applies the finished block `prev` to the rows of the blocks still to
-// be solved (one workgroup per block), then workgroup 0 solves the diagonal
-// block `cur` = the next one in order.  Each element accumulates its terms
-// in the order of the textbook substitution (column-oriented for L and U:
-// ascending k for L, descending k for U; ascending i for the transposed
-// forms within a block).
+// Blocked triangular solve in FP32 with the stored factor F (16-bit), blocks
+// of kTrsvBs rows, in one launch.  Workgroup w owns the w-th block in solve
+// order: it stages its diagonal block in LDS, then, for every earlier block
+// in solve order, waits for that block's solution and applies it to its own
+// rows (thread = row), then solves its diagonal block with one wave and
+// publishes the solution.  Every element accumulates its terms in the order
+// of the textbook substitution (column-oriented for L and U: ascending k for
+// L, descending k for U; ascending i for the transposed forms).
 //   kind 0: L (unit lower), forward;   kind 1: U (upper), backward
 //   kind 2: U^T (lower), forward;      kind 3: L^T (unit upper), backward
+// Publication: each solved value goes to xs as a 64-bit word holding the
+// float's bits and, in the upper half, the launch's tag; writers and readers
+// use agent-scope relaxed atomics and a reader polls each word until it
+// carries the tag, so no fences are needed.  Tags are unique per launch, so
+// words of earlier solves never match.  Workgroup w waits only on
+// workgroups with smaller ids, which are dispatched first, so the chain
+// always progresses even when not all workgroups are resident.  The polling
+// is bounded: on expiry *expired is set and the solve completes with
+// invalid values.
+__device__ __forceinline__ uint64_t ll_load(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Barrier that orders LDS only, so that global loads issued before it stay in
+// flight across it (a full __syncthreads would wait for them).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 template <int FMT, int KIND>
-__global__ __launch_bounds__(256) void trsv_step_kernel(int64_t n, const uint16_t *__restrict__ F,
-                                                        int64_t ldf, float *__restrict__ v,
-                                                        int64_t prev, int64_t cur, int nblk,
-                                                        int dir) {
+__global__ __launch_bounds__(256) void trsv_chain_kernel(int64_t n, const uint16_t *__restrict__ F,
+                                                         int64_t ldf, float *__restrict__ v,
+                                                         uint64_t *xs, uint32_t tag, int nblk,
+                                                         int *expired) {
     constexpr int BS = kTrsvBs;
-    __shared__ float vprev[BS];
-    __shared__ uint16_t Ld[BS][BS + 2];   // raw stored values (128 KB)
-    const int tid = threadIdx.x;
-    // block handled by this workgroup: cur + dir * blockIdx.x
-    const int64_t myblk = cur + (int64_t)dir * blockIdx.x;
-    const int64_t r0 = myblk * BS;
-    const int rows = (int)((n - r0 < BS) ? n - r0 : BS);
-    if (prev >= 0) {
-        const int64_t p0 = prev * BS;
-        const int pr = (int)((n - p0 < BS) ? n - p0 : BS);
-        if (tid < pr) vprev[tid] = v[p0 + tid];
-        __syncthreads();
-        if (tid < rows) {
-            const int64_t i = r0 + tid;
-            float acc = v[i];
-            if (KIND == 0) {          // v_i -= L[i][k] v_k, k ascending
-                for (int k = 0; k < pr; ++k)
-                    acc = fmaf(-lp_to_f32<FMT>(F[(size_t)i + (size_t)(p0 + k) * ldf]), vprev[k], acc);
-            } else if (KIND == 1) {   // v_i -= U[i][k] v_k, k descending
-                for (int k = pr - 1; k >= 0; --k)
-                    acc = fmaf(-lp_to_f32<FMT>(F[(size_t)i + (size_t)(p0 + k) * ldf]), vprev[k], acc);
-            } else if (KIND == 2) {   // v_k -= U[i][k] v_i (i in prev block), i ascending
-                for (int k = 0; k < pr; ++k)
-                    acc = fmaf(-lp_to_f32<FMT>(F[(size_t)(p0 + k) + (size_t)i * ldf]), vprev[k], acc);
-            } else {                  // v_k -= L[i][k] v_i, i ascending
-                for (int k = 0; k < pr; ++k)
-                    acc = fmaf(-lp_to_f32<FMT>(F[(size_t)(p0 + k) + (size_t)i * ldf]), vprev[k], acc);
-            }
-            v[i] = acc;
-        }
-    }
-    if (blockIdx.x != 0) return;
-    // diagonal block of `cur`, staged in LDS as the effective lower/upper factor
-    __syncthreads();
-    for (int t = tid; t < rows * rows; t += 256) {
-        const int i = t % rows, k = t / rows;
-        const uint16_t f = F[(size_t)(r0 + i) + (size_t)(r0 + k) * ldf];
-        if (KIND == 0 || KIND == 1) Ld[i][k] = f;
-        else Ld[k][i] = f;     // transposed forms: Ld[i][k] = F[k][i]
-    }
-    __syncthreads();
-    if (tid >= 64) return;
-    // one wave: lane owns rows lane, lane+64, lane+128, lane+192
-    float x[BS / 64];
-#pragma unroll
-    for (int q = 0; q < BS / 64; ++q) {
-        const int i = tid + 64 * q;
-        x[q] = (i < rows) ? v[r0 + i] : 0.0f;
-    }
     constexpr bool FWD = (KIND == 0 || KIND == 2);
     constexpr bool UNIT = (KIND == 0 || KIND == 3);
+    __shared__ uint16_t Ld[BS][BS + 2];   // raw stored values (129 KB)
+    __shared__ float xprev[BS];
+    const int tid = threadIdx.x;
+    const int w = blockIdx.x;
+    const int64_t myblk = FWD ? w : nblk - 1 - w;
+    const int64_t r0 = myblk * BS;
+    const int rows = (int)((n - r0 < BS) ? n - r0 : BS);
+    const int64_t i = r0 + tid;          // this thread's row
+
+    // diagonal block, staged as the effective lower/upper factor
+    for (int t = tid; t < rows * rows; t += 256) {
+        const int ii = t % rows, k = t / rows;
+        const uint16_t f = F[(size_t)(r0 + ii) + (size_t)(r0 + k) * ldf];
+        if (KIND == 0 || KIND == 1) Ld[ii][k] = f;
+        else Ld[k][ii] = f;     // transposed forms: Ld[i][k] = F[k][i]
+    }
+    float acc = (tid < rows) ? v[i] : 0.0f;
+    // fr: the thread's row of the earlier block, F values for k = 2j, 2j+1
+    // packed in one word; loaded before the wait for that block's solution
+    uint32_t fr[BS / 2];
+    for (int t = 0; t < w; ++t) {
+        const int64_t pb = FWD ? t : nblk - 1 - t;
+        const int64_t p0 = pb * BS;
+        const int pr = (int)((n - p0 < BS) ? n - p0 : BS);
+        const bool full = (pr == BS) && (tid < rows);
+        if (full) {
+            if (KIND == 0 || KIND == 1) {
 #pragma unroll
-    for (int q = 0; q < BS / 64; ++q) {
-        for (int kk = 0; kk < 64; ++kk) {
-            const int s = q * 64 + kk;
-            if (s >= rows) break;
-            const int k = FWD ? s : rows - 1 - s;
-            const int kq = k / 64, kl = k % 64;
-            // finish x_k on its owner lane, then broadcast it
-            float xk = 0.0f;
+                for (int j = 0; j < BS / 2; ++j)
+                    fr[j] = (uint32_t)F[(size_t)i + (size_t)(p0 + 2 * j) * ldf] |
+                            ((uint32_t)F[(size_t)i + (size_t)(p0 + 2 * j + 1) * ldf] << 16);
+            } else {   // F[k][i] for k in the earlier block: contiguous in k
+                const uint4 *q = reinterpret_cast<const uint4 *>(&F[(size_t)p0 + (size_t)i * ldf]);
 #pragma unroll
-            for (int qq = 0; qq < BS / 64; ++qq)
-                if (qq == kq) {
-                    if (!UNIT && tid == kl) x[qq] = x[qq] / lp_to_f32<FMT>(Ld[k][k]);
-                    xk = __shfl(x[qq], kl);
+                for (int j = 0; j < BS / 8; ++j) {
+                    const uint4 u = q[j];
+                    fr[4 * j] = u.x;
+                    fr[4 * j + 1] = u.y;
+                    fr[4 * j + 2] = u.z;
+                    fr[4 * j + 3] = u.w;
                 }
+            }
+        }
+        lds_barrier();   // the previous block's values are consumed
+        if (tid < pr) {
+            const uint64_t *src = &xs[p0 + tid];
+            uint64_t x = ll_load(src);
+            long spins = 0;
+            while ((uint32_t)(x >> 32) != tag) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > (1L << 26)) {
+                    atomicExch(expired, 1);
+                    break;
+                }
+                x = ll_load(src);
+            }
+            xprev[tid] = __uint_as_float((uint32_t)x);
+        }
+        lds_barrier();
+        if (full) {
+            // L, U^T, L^T: k ascending; U: k descending
+            if (KIND == 1) {
 #pragma unroll
-            for (int qq = 0; qq < BS / 64; ++qq) {
-                const int i = tid + 64 * qq;
-                if (i < rows && (FWD ? i > k : i < k))
-                    x[qq] = fmaf(-lp_to_f32<FMT>(Ld[i][k]), xk, x[qq]);
+                for (int j = BS / 2 - 1; j >= 0; --j) {
+                    acc = fmaf(-lp_to_f32<FMT>((uint16_t)(fr[j] >> 16)), xprev[2 * j + 1], acc);
+                    acc = fmaf(-lp_to_f32<FMT>((uint16_t)fr[j]), xprev[2 * j], acc);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < BS / 2; ++j) {
+                    acc = fmaf(-lp_to_f32<FMT>((uint16_t)fr[j]), xprev[2 * j], acc);
+                    acc = fmaf(-lp_to_f32<FMT>((uint16_t)(fr[j] >> 16)), xprev[2 * j + 1], acc);
+                }
+            }
+        } else if (tid < rows) {   // a partial earlier block (the last one of n)
+            if (KIND == 0) {
+                for (int k = 0; k < pr; ++k)
+                    acc = fmaf(-lp_to_f32<FMT>(F[(size_t)i + (size_t)(p0 + k) * ldf]), xprev[k], acc);
+            } else if (KIND == 1) {
+                for (int k = pr - 1; k >= 0; --k)
+                    acc = fmaf(-lp_to_f32<FMT>(F[(size_t)i + (size_t)(p0 + k) * ldf]), xprev[k], acc);
+            } else {
+                for (int k = 0; k < pr; ++k)
+                    acc = fmaf(-lp_to_f32<FMT>(F[(size_t)(p0 + k) + (size_t)i * ldf]), xprev[k], acc);
             }
         }
     }
+    __syncthreads();
+    xprev[tid] = acc;      // hand the accumulated right-hand side to wave 0
+    __syncthreads();
+    if (tid >= 64) return;
+    // one wave: lane owns rows lane + 64 q.  Step s finishes x_k on its owner
+    // lane (division for U), broadcasts it with readlane and updates the
+    // remaining rows; the LDS values of step s + 1 are read during step s.
+    float x[BS / 64];
+#pragma unroll
+    for (int q = 0; q < BS / 64; ++q) x[q] = xprev[tid + 64 * q];
+    auto kof = [&](int st) { return FWD ? st : rows - 1 - st; };
+    float lc[BS / 64], dc = 1.0f;
+    {
+        const int k = kof(0);
+#pragma unroll
+        for (int q = 0; q < BS / 64; ++q) lc[q] = lp_to_f32<FMT>(Ld[min(tid + 64 * q, BS - 1)][k]);
+        if (!UNIT) dc = lp_to_f32<FMT>(Ld[k][k]);
+    }
+    for (int st = 0; st < rows; ++st) {
+        const int k = kof(st);
+        const int kq = k >> 6, kl = k & 63;
+        float ln[BS / 64], dn = 1.0f;
+        if (st + 1 < rows) {
+            const int k1 = kof(st + 1);
+#pragma unroll
+            for (int q = 0; q < BS / 64; ++q) ln[q] = lp_to_f32<FMT>(Ld[min(tid + 64 * q, BS - 1)][k1]);
+            if (!UNIT) dn = lp_to_f32<FMT>(Ld[k1][k1]);
+        }
+        float own = 0.0f;
+#pragma unroll
+        for (int q = 0; q < BS / 64; ++q)
+            if (q == kq) own = x[q];
+        if (!UNIT) own = own / dc;
+        const float xk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(own), kl));
+#pragma unroll
+        for (int q = 0; q < BS / 64; ++q) {
+            const int r = tid + 64 * q;
+            if (r == k) x[q] = xk;
+            else if (r < rows && (FWD ? r > k : r < k)) x[q] = fmaf(-lc[q], xk, x[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < BS / 64; ++q) lc[q] = ln[q];
+        dc = dn;
+    }
 #pragma unroll
     for (int q = 0; q < BS / 64; ++q) {
-        const int i = tid + 64 * q;
-        if (i < rows) v[r0 + i] = x[q];
+        const int r = tid + 64 * q;
+        if (r < rows) {
+            v[r0 + r] = x[q];
+            __hip_atomic_store(&xs[r0 + r], ((uint64_t)tag << 32) | __float_as_uint(x[q]),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
 }
 
@@ -375,24 +459,27 @@ int absmax_f64(int64_t n, const double *v, unsigned long long *out, hipStream_t 
 }
 
 template <int FMT, int KIND>
-static int trsv_run(int64_t n, const uint16_t *F, int64_t ldf, float *v, hipStream_t s) {
+static int trsv_run(int64_t n, const uint16_t *F, int64_t ldf, float *v, TrsvChain &ch,
+                    hipStream_t s) {
     const int64_t nblk = (n + kTrsvBs - 1) / kTrsvBs;
-    const bool fwd = (KIND == 0 || KIND == 2);
-    const int dir = fwd ? 1 : -1;
-    for (int64_t t = 0; t < nblk; ++t) {
-        const int64_t cur = fwd ? t : nblk - 1 - t;
-        const int64_t prev = (t == 0) ? -1 : cur - dir;
-        const unsigned grid = (unsigned)(nblk - t);     // blocks cur, cur+dir, ...
-        hipLaunchKernelGGL((trsv_step_kernel<FMT, KIND>), dim3(grid), dim3(256), 0, s, n, F, ldf, v,
-                           prev, cur, (int)nblk, dir);
-        MXLU_LAUNCH_CHECK();
+    if (nblk > 0x7fffffff) {
+        set_error_msg("trsv: too many blocks");
+        return MXLU_E_NOMEM;
     }
+    if (((uintptr_t)F % 16) || (ldf % 8)) {
+        set_error_msg("trsv: factor storage must be 16-byte aligned with ldf % 8 == 0");
+        return MXLU_E_NOMEM;
+    }
+    const uint32_t tag = ++ch.tag;
+    hipLaunchKernelGGL((trsv_chain_kernel<FMT, KIND>), dim3((unsigned)nblk), dim3(256), 0, s, n, F,
+                       ldf, v, ch.xs, tag, (int)nblk, ch.expired);
+    MXLU_LAUNCH_CHECK();
     return 0;
 }
 
 int lp_precond_apply(int fmt, int trans, int64_t n, const uint16_t *F, int64_t ldf,
                      const int32_t *perm, const double *r, double *d, float *v32,
-                     unsigned long long *smax, hipStream_t s) {
+                     unsigned long long *smax, TrsvChain &ch, hipStream_t s) {
     if (n <= 0) return 0;
     MXLU_HIP_TRY(hipMemsetAsync(smax, 0, sizeof(unsigned long long), s));
     MXLU_TRY(absmax_f64(n, r, smax, s));
@@ -402,11 +489,11 @@ int lp_precond_apply(int fmt, int trans, int64_t n, const uint16_t *F, int64_t l
     MXLU_LAUNCH_CHECK();
     int rc;
     if (fmt == kFmtBf16) {
-        rc = trans ? trsv_run<kFmtBf16, 2>(n, F, ldf, v32, s) : trsv_run<kFmtBf16, 0>(n, F, ldf, v32, s);
-        if (!rc) rc = trans ? trsv_run<kFmtBf16, 3>(n, F, ldf, v32, s) : trsv_run<kFmtBf16, 1>(n, F, ldf, v32, s);
+        rc = trans ? trsv_run<kFmtBf16, 2>(n, F, ldf, v32, ch, s) : trsv_run<kFmtBf16, 0>(n, F, ldf, v32, ch, s);
+        if (!rc) rc = trans ? trsv_run<kFmtBf16, 3>(n, F, ldf, v32, ch, s) : trsv_run<kFmtBf16, 1>(n, F, ldf, v32, ch, s);
     } else {
-        rc = trans ? trsv_run<kFmtFp16, 2>(n, F, ldf, v32, s) : trsv_run<kFmtFp16, 0>(n, F, ldf, v32, s);
-        if (!rc) rc = trans ? trsv_run<kFmtFp16, 3>(n, F, ldf, v32, s) : trsv_run<kFmtFp16, 1>(n, F, ldf, v32, s);
+        rc = trans ? trsv_run<kFmtFp16, 2>(n, F, ldf, v32, ch, s) : trsv_run<kFmtFp16, 0>(n, F, ldf, v32, ch, s);
+        if (!rc) rc = trans ? trsv_run<kFmtFp16, 3>(n, F, ldf, v32, ch, s) : trsv_run<kFmtFp16, 1>(n, F, ldf, v32, ch, s);
     }
     if (rc) return rc;
     hipLaunchKernelGGL(precond_out_kernel, dim3(g1(n)), dim3(256), 0, s, n, v32,
