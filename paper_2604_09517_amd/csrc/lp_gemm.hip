@@ -9,11 +9,12 @@
 //                 and per 128-column tile of U12, v_mfma_scale_f32_16x16x128
 //                 _f8f6f4 with unit block scales, accumulators start at 0.
 //
-// Operands are read with k contiguous: L21 comes transposed (LT, K x M) and
-// U12 is the column-major block of the stored matrix.  A workgroup of 4
-// waves owns a 256 x 128 tile of A22 (each wave 128 x 64 = 8 x 4 MFMA
-// blocks); K is staged through LDS in chunks, double-buffered for the 16-bit
-// form, single-buffered with register prefetch for FP8.
+// Operands are read with k contiguous: chunk-packed L21 and U12 for the
+// 16-bit form, row-major e4m3 copies for FP8.  A workgroup of 4 waves owns a
+// 256 x 128 tile of A22 (each wave 128 x 64 = 8 x 4 MFMA blocks); K is
+// staged through LDS in chunks: a three-stage ring filled by direct
+// global->LDS loads for the 16-bit form, a single buffer with register
+// prefetch for FP8.
 //
 // MFMA lane layouts (measured on gfx950; lane l, i = l % 16, g = l / 16):
 //   16x16x32 16-bit: A lane holds A[i][8g .. 8g+7], B lane B[8g .. 8g+7][i],
@@ -63,16 +64,36 @@ __device__ __forceinline__ v4f mfma16(uint4 a, uint4 b, v4f c) {
 }
 
 // ------------------------------------------------------------ 16-bit form
-constexpr int BK16 = 32;
-constexpr int ST16 = BK16 + 8;   // LDS row stride (elements) of a staged row
+// Operands come chunk-packed (one K chunk of 32 of a tile = one contiguous
+// block: 16 KB of L21, 8 KB of U12) and are copied to an LDS ring of kNs16
+// stages with 16-byte direct global->LDS loads (no register staging): each
+// wave issues 4 + 2 loads of 1 KB per chunk, so up to kNs16 - 1 chunks are in
+// flight while the matrix cores work on the current one, and one workgroup
+// barrier per chunk orders the ring.  A is negated when read from LDS.  C is
+// read and written 8 bytes (4 rows of one column) per lane, the accumulator
+// layout.
+constexpr int BK16 = kLpKc;
+constexpr int kNs16 = 3;
+static_assert(TM == kLpTileM && TN == kLpTileN, "tile and packing must agree");
+
+typedef __attribute__((address_space(1))) void gvoid_t;
+typedef __attribute__((address_space(3))) void lvoid_t;
+
+__device__ __forceinline__ uint4 neg16(uint4 v) {   // flip the sign bit of 8 16-bit values
+    v.x ^= 0x80008000u;
+    v.y ^= 0x80008000u;
+    v.z ^= 0x80008000u;
+    v.w ^= 0x80008000u;
+    return v;
+}
 
 template <int FMT>
 __global__ __launch_bounds__(256, 2) void lp_schur16_kernel(
-    int64_t M, int64_t N, int K, const uint16_t *__restrict__ LT, int64_t ldlt,
-    const uint16_t *__restrict__ U, int64_t ldu, uint16_t *__restrict__ C, int64_t ldc,
+    int64_t M, int64_t N, int K, const uint16_t *__restrict__ Lp, int64_t Mp,
+    const uint16_t *__restrict__ Up, int64_t Np, uint16_t *__restrict__ C, int64_t ldc,
     int tiles_m, int tiles_n) {
-    __shared__ __attribute__((aligned(16))) uint16_t As[2][TM * ST16];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][TN * ST16];
+    constexpr int SA = TM * BK16, SB = TN * BK16;   // elements per stage
+    __shared__ __attribute__((aligned(1024))) uint16_t ring[kNs16][SA + SB];
 
     int tm, tn;
     tile_of(blockIdx.x, tiles_m, tiles_n, tm, tn);
@@ -81,6 +102,7 @@ __global__ __launch_bounds__(256, 2) void lp_schur16_kernel(
     const int wm = wave & 1, wn = wave >> 1;
     const int li = lane & 15, lg = lane >> 4;
 
+    // accumulators <- C (rows r .. r+3 of column c per lane)
     v4f acc[8][4];
 #pragma unroll
     for (int bi = 0; bi < 8; ++bi)
@@ -88,66 +110,68 @@ __global__ __launch_bounds__(256, 2) void lp_schur16_kernel(
         for (int bj = 0; bj < 4; ++bj) {
             const int64_t r = row0 + wm * 128 + bi * 16 + 4 * lg;
             const int64_t c = col0 + wn * 64 + bj * 16 + li;
+            if (r + 3 < M && c < N) {
+                const uint2 v = *reinterpret_cast<const uint2 *>(&C[(size_t)r + (size_t)c * ldc]);
+                acc[bi][bj][0] = lp_to_f32<FMT>((uint16_t)v.x);
+                acc[bi][bj][1] = lp_to_f32<FMT>((uint16_t)(v.x >> 16));
+                acc[bi][bj][2] = lp_to_f32<FMT>((uint16_t)v.y);
+                acc[bi][bj][3] = lp_to_f32<FMT>((uint16_t)(v.y >> 16));
+            } else {
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-                acc[bi][bj][e] =
-                    (r + e < M && c < N) ? lp_to_f32<FMT>(C[(size_t)(r + e) + (size_t)c * ldc]) : 0.0f;
+                for (int e = 0; e < 4; ++e)
+                    acc[bi][bj][e] = (r + e < M && c < N)
+                                         ? lp_to_f32<FMT>(C[(size_t)(r + e) + (size_t)c * ldc])
+                                         : 0.0f;
+            }
         }
 
-    // staging: A row t of the tile (4 x 16 B), B column t/2, half t%2 (2 x 16 B)
-    const int64_t a_row = row0 + tid;
-    const bool a_ok = a_row < M;
-    const int64_t b_col = col0 + (tid >> 1);
-    const bool b_ok = b_col < N;
-    const int b_k = (tid & 1) * 16;
-    uint4 ra[4], rb[2];
-    auto load = [&](int k0) {
-        const uint4 *pa = reinterpret_cast<const uint4 *>(LT + (size_t)a_row * ldlt + k0);
+    // chunk kc of this tile: L21 bytes [4 KB wave, 4 KB (wave+1)), U12 bytes
+    // [2 KB wave, 2 KB (wave+1)) go to stage st
+    const char *gA = reinterpret_cast<const char *>(Lp + (size_t)row0 * BK16) + wave * 4096 + lane * 16;
+    const char *gB = reinterpret_cast<const char *>(Up + (size_t)col0 * BK16) + wave * 2048 + lane * 16;
+    const size_t strideA = (size_t)Mp * BK16 * sizeof(uint16_t);   // bytes per K chunk
+    const size_t strideB = (size_t)Np * BK16 * sizeof(uint16_t);
+    auto issue = [&](int kc, int st) {
+        const char *ga = gA + (size_t)kc * strideA;
+        const char *gb = gB + (size_t)kc * strideB;
+        char *la = reinterpret_cast<char *>(&ring[st][0]) + wave * 4096;
+        char *lb = reinterpret_cast<char *>(&ring[st][SA]) + wave * 2048;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) ra[q] = a_ok ? pa[q] : make_uint4(0, 0, 0, 0);
-        const uint4 *pb = reinterpret_cast<const uint4 *>(U + (size_t)b_col * ldu + k0 + b_k);
+        for (int q = 0; q < 4; ++q)
+            __builtin_amdgcn_global_load_lds((gvoid_t *)(ga + q * 1024), (lvoid_t *)(la + q * 1024),
+                                             16, 0, 0);
 #pragma unroll
-        for (int q = 0; q < 2; ++q) rb[q] = b_ok ? pb[q] : make_uint4(0, 0, 0, 0);
-    };
-    auto store = [&](int buf) {
-        uint4 *da = reinterpret_cast<uint4 *>(&As[buf][tid * ST16]);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            uint4 v = ra[q];   // negate: flip the sign bit of every element
-            v.x ^= 0x80008000u;
-            v.y ^= 0x80008000u;
-            v.z ^= 0x80008000u;
-            v.w ^= 0x80008000u;
-            da[q] = v;
-        }
-        uint4 *db = reinterpret_cast<uint4 *>(&Bs[buf][(tid >> 1) * ST16 + b_k]);
-#pragma unroll
-        for (int q = 0; q < 2; ++q) db[q] = rb[q];
+        for (int q = 0; q < 2; ++q)
+            __builtin_amdgcn_global_load_lds((gvoid_t *)(gb + q * 1024), (lvoid_t *)(lb + q * 1024),
+                                             16, 0, 0);
     };
 
     const int nk = K / BK16;
-    load(0);
-    store(0);
-    __syncthreads();
-    retire_vector_loads();
+#pragma unroll
+    for (int c = 0; c < kNs16 - 1; ++c)
+        if (c < nk) issue(c, c);
     for (int kt = 0; kt < nk; ++kt) {
-        const int buf = kt & 1;
-        if (kt + 1 < nk) load((kt + 1) * BK16);
+        // chunk kt has landed once at most min(kNs16 - 2, nk - 1 - kt) later
+        // chunks (6 loads each) are outstanding; the C loads came first
+        static_assert(kNs16 == 3, "the wait below assumes three stages");
+        if (kt + 1 < nk) __builtin_amdgcn_s_waitcnt(0x0F70 | 6);   // vmcnt(6)
+        else __builtin_amdgcn_s_waitcnt(0x0F70);                   // vmcnt(0)
+        __syncthreads();   // every wave's part of chunk kt; stage (kt - 1) % 3 free
+        if (kt + kNs16 - 1 < nk) issue(kt + kNs16 - 1, (kt + kNs16 - 1) % kNs16);
+        const uint16_t *as = &ring[kt % kNs16][0];
+        const uint16_t *bs = &ring[kt % kNs16][SA];
         uint4 a[8], b[4];
 #pragma unroll
         for (int bi = 0; bi < 8; ++bi)
-            a[bi] = *reinterpret_cast<const uint4 *>(
-                &As[buf][(wm * 128 + bi * 16 + li) * ST16 + lg * 8]);
+            a[bi] = neg16(*reinterpret_cast<const uint4 *>(
+                &as[(wm * 128 + bi * 16 + li) * BK16 + lg * 8]));
 #pragma unroll
         for (int bj = 0; bj < 4; ++bj)
-            b[bj] = *reinterpret_cast<const uint4 *>(
-                &Bs[buf][(wn * 64 + bj * 16 + li) * ST16 + lg * 8]);
+            b[bj] = *reinterpret_cast<const uint4 *>(&bs[(wn * 64 + bj * 16 + li) * BK16 + lg * 8]);
 #pragma unroll
         for (int bi = 0; bi < 8; ++bi)
 #pragma unroll
             for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = mfma16<FMT>(a[bi], b[bj], acc[bi][bj]);
-        if (kt + 1 < nk) store(buf ^ 1);
-        __syncthreads();
     }
 
 #pragma unroll
@@ -156,10 +180,19 @@ __global__ __launch_bounds__(256, 2) void lp_schur16_kernel(
         for (int bj = 0; bj < 4; ++bj) {
             const int64_t r = row0 + wm * 128 + bi * 16 + 4 * lg;
             const int64_t c = col0 + wn * 64 + bj * 16 + li;
+            if (r + 3 < M && c < N) {
+                uint2 v;
+                v.x = (uint32_t)f32_to_lp<FMT>(acc[bi][bj][0]) |
+                      ((uint32_t)f32_to_lp<FMT>(acc[bi][bj][1]) << 16);
+                v.y = (uint32_t)f32_to_lp<FMT>(acc[bi][bj][2]) |
+                      ((uint32_t)f32_to_lp<FMT>(acc[bi][bj][3]) << 16);
+                *reinterpret_cast<uint2 *>(&C[(size_t)r + (size_t)c * ldc]) = v;
+            } else {
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-                if (r + e < M && c < N)
-                    C[(size_t)(r + e) + (size_t)c * ldc] = f32_to_lp<FMT>(acc[bi][bj][e]);
+                for (int e = 0; e < 4; ++e)
+                    if (r + e < M && c < N)
+                        C[(size_t)(r + e) + (size_t)c * ldc] = f32_to_lp<FMT>(acc[bi][bj][e]);
+            }
         }
 }
 
@@ -268,21 +301,22 @@ __global__ __launch_bounds__(256, 2) void lp_schur8_kernel(
 
 namespace mxlu {
 
-int lp_schur_update(int fmt, int64_t M, int64_t N, int K, const uint16_t *LT, int64_t ldlt,
-                    const uint16_t *U, int64_t ldu, uint16_t *C, int64_t ldc, hipStream_t s) {
+int lp_schur_update(int fmt, int64_t M, int64_t N, int K, const uint16_t *Lp, int64_t Mp,
+                    const uint16_t *Up, int64_t Np, uint16_t *C, int64_t ldc, hipStream_t s) {
     if (M <= 0 || N <= 0 || K <= 0) return 0;
-    if (K % BK16 || ldlt % 8 || ldu % 8 || ((uintptr_t)LT | (uintptr_t)U) % 16) {
-        set_error_msg("lp_schur_update: K, leading dimensions or alignment not multiples of 8/16");
+    if (K % BK16 || Mp % TM || Np % TN || Mp < M || Np < N || ldc % 4 ||
+        ((uintptr_t)Lp | (uintptr_t)Up) % 16 || (uintptr_t)C % 8) {
+        set_error_msg("lp_schur_update: K % 32, padded packed operands, ldc % 4 and alignment required");
         return MXLU_E_NOMEM;
     }
     const int64_t tiles_m = (M + TM - 1) / TM, tiles_n = (N + TN - 1) / TN;
     const dim3 grid((unsigned)(tiles_m * tiles_n));
     if (fmt == kFmtBf16)
-        hipLaunchKernelGGL(lp_schur16_kernel<kFmtBf16>, grid, dim3(256), 0, s, M, N, K, LT, ldlt,
-                           U, ldu, C, ldc, (int)tiles_m, (int)tiles_n);
+        hipLaunchKernelGGL(lp_schur16_kernel<kFmtBf16>, grid, dim3(256), 0, s, M, N, K, Lp, Mp,
+                           Up, Np, C, ldc, (int)tiles_m, (int)tiles_n);
     else
-        hipLaunchKernelGGL(lp_schur16_kernel<kFmtFp16>, grid, dim3(256), 0, s, M, N, K, LT, ldlt,
-                           U, ldu, C, ldc, (int)tiles_m, (int)tiles_n);
+        hipLaunchKernelGGL(lp_schur16_kernel<kFmtFp16>, grid, dim3(256), 0, s, M, N, K, Lp, Mp,
+                           Up, Np, C, ldc, (int)tiles_m, (int)tiles_n);
     MXLU_LAUNCH_CHECK();
     return 0;
 }

@@ -27,9 +27,23 @@ int lp_panel_factor_nopiv(int64_t m, int kb, float *P, int64_t ldp, int *info, i
 // B (kb x ncols) <- L^-1 B, L unit lower (FP32), any kb.
 int trsm_f32_llnu(int64_t kb, int64_t ncols, const float *L, int64_t ldl, float *B, int64_t ldb,
                   hipStream_t s);
-// F panel <- round(P); LT (kb x (m - kb)) <- the L21 rows transposed (optional).
+// Chunk-packed operand of the 16-bit trailing update.  Line r (a row of L21
+// or a column of U12), value k, sits at ((k / kLpKc) * Rp + r) * kLpKc +
+// k % kLpKc, where Rp is the line count rounded up to the tile (kLpTileM rows
+// of L21, kLpTileN columns of U12): one K chunk of one tile is one contiguous
+// block, which the update copies to LDS with 16-byte direct loads.
+constexpr int kLpKc = 32;
+constexpr int kLpTileM = 256, kLpTileN = 128;
+inline int64_t lp_round_up(int64_t r, int64_t t) { return (r + t - 1) / t * t; }
+
+// F panel <- round(P); LTp <- the L21 rows (rows kb .. m-1 of the panel),
+// chunk-packed with Mp lines (optional).
 int lp_panel_store(int fmt, int64_t m, int kb, const float *P, int64_t ldp, uint16_t *F,
-                   int64_t ldf, uint16_t *LT, int64_t ldlt, hipStream_t s);
+                   int64_t ldf, uint16_t *LTp, int64_t Mp, hipStream_t s);
+// Up <- U12 (kb x nt block of F, column-major, kb % 8 == 0), chunk-packed
+// with Np lines.
+int lp_pack_u12(int64_t nt, int kb, const uint16_t *U12, int64_t ldf, uint16_t *Up, int64_t Np,
+                hipStream_t s);
 // FP8 operands of the trailing update with power-of-two tile scales.
 int lp_quant_l21(int fmt, int64_t mt, int kb, int tile, const uint16_t *L21, int64_t ldf,
                  uint8_t *LTq, float *sL, hipStream_t s);
@@ -37,10 +51,11 @@ int lp_quant_u12(int fmt, int64_t nt, int kb, int tile, const uint16_t *U12, int
                  uint8_t *Uq, float *sU, hipStream_t s);
 
 // Trailing update on the matrix cores:
-//   16-bit: C <- round(fp32(C) - LT^T U) with LT (K x M), U (K x N) 16-bit
+//   16-bit: C <- round(fp32(C) - L U) with L (M x K) and U (K x N) chunk-packed
+//           (Mp, Np lines), K % kLpKc == 0, C 8-byte aligned with ldc % 4 == 0
 //   FP8:    C <- round(fp32(C) - (LTq^T Uq) sL sU), operands e4m3fn
-int lp_schur_update(int fmt, int64_t M, int64_t N, int K, const uint16_t *LT, int64_t ldlt,
-                    const uint16_t *U, int64_t ldu, uint16_t *C, int64_t ldc, hipStream_t s);
+int lp_schur_update(int fmt, int64_t M, int64_t N, int K, const uint16_t *Lp, int64_t Mp,
+                    const uint16_t *Up, int64_t Np, uint16_t *C, int64_t ldc, hipStream_t s);
 int lp_schur_update_fp8(int fmt, int64_t M, int64_t N, int K, const uint8_t *LTq,
                         const float *sL, const uint8_t *Uq, const float *sU, int tile,
                         uint16_t *C, int64_t ldc, hipStream_t s);

@@ -16,6 +16,8 @@
 //     power-of-two scales.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "common.h"
 #include "lp_common.h"
 #include "lp_kernels.h"
@@ -226,14 +228,14 @@ __global__ __launch_bounds__(256) void trsm_f32_llnu_kernel(int kb, int64_t ncol
 
 // ---------------------------------------------------------------- store
 // F[i, c] <- round(P[i, c]) for the m x kb panel; for rows i >= kb also the
-// transposed copy LT[c, i - kb] (leading dimension ldlt) when LT is given.
+// chunk-packed copy of L21 (line i - kb, value c, Mp lines) when LT is given.
 // 64 x 64 tiles through LDS so that both writes are coalesced.
 template <int FMT>
 __global__ __launch_bounds__(256) void panel_store_kernel(int64_t m, int kb,
                                                           const float *__restrict__ P,
                                                           int64_t ldp, uint16_t *__restrict__ F,
                                                           int64_t ldf, uint16_t *__restrict__ LT,
-                                                          int64_t ldlt, int tiles_m) {
+                                                          int64_t Mp, int tiles_m) {
     __shared__ uint16_t T[64][64 + 2];
     const int tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
     const int64_t r0 = (int64_t)tm * 64;
@@ -256,7 +258,26 @@ __global__ __launch_bounds__(256) void panel_store_kernel(int64_t m, int kb,
         const int j = t % 64, i = t / 64;
         const int64_t r = r0 + i;
         const int c = c0 + j;
-        if (r >= kb && r < m && c < kb) LT[(size_t)c + (size_t)(r - kb) * ldlt] = T[i][j];
+        if (r >= kb && r < m && c < kb)
+            LT[((size_t)(c / kLpKc) * Mp + (size_t)(r - kb)) * kLpKc + (c % kLpKc)] = T[i][j];
+    }
+}
+
+// U12 (kb x nt, column-major in F) -> chunk-packed Up: one thread per 8
+// values (16 bytes) of a column.
+__global__ __launch_bounds__(256) void pack_u12_kernel(int64_t nt, int kb,
+                                                       const uint16_t *__restrict__ U12,
+                                                       int64_t ldf, uint16_t *__restrict__ Up,
+                                                       int64_t Np) {
+    const int per = kb / 8;
+    const int64_t total = nt * per;
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * 256) {
+        const int64_t j = t / per;
+        const int k = (int)(t - j * per) * 8;
+        const uint4 v = *reinterpret_cast<const uint4 *>(U12 + (size_t)k + (size_t)j * ldf);
+        *reinterpret_cast<uint4 *>(Up + ((size_t)(k / kLpKc) * Np + (size_t)j) * kLpKc +
+                                   (k % kLpKc)) = v;
     }
 }
 
@@ -432,15 +453,33 @@ int trsm_f32_llnu(int64_t kb, int64_t ncols, const float *L, int64_t ldl, float 
 }
 
 int lp_panel_store(int fmt, int64_t m, int kb, const float *P, int64_t ldp, uint16_t *F,
-                   int64_t ldf, uint16_t *LT, int64_t ldlt, hipStream_t s) {
+                   int64_t ldf, uint16_t *LTp, int64_t Mp, hipStream_t s) {
     if (m <= 0 || kb <= 0) return 0;
+    if (LTp && (kb % kLpKc || Mp < m - kb)) {
+        set_error_msg("lp_panel_store: packed L21 needs kb % 32 == 0 and Mp >= m - kb");
+        return MXLU_E_NOMEM;
+    }
     const int64_t tm = (m + 63) / 64, tn = (kb + 63) / 64;
     if (fmt == kFmtBf16)
         hipLaunchKernelGGL(panel_store_kernel<kFmtBf16>, dim3((unsigned)(tm * tn)), dim3(256), 0,
-                           s, m, kb, P, ldp, F, ldf, LT, ldlt, (int)tm);
+                           s, m, kb, P, ldp, F, ldf, LTp, Mp, (int)tm);
     else
         hipLaunchKernelGGL(panel_store_kernel<kFmtFp16>, dim3((unsigned)(tm * tn)), dim3(256), 0,
-                           s, m, kb, P, ldp, F, ldf, LT, ldlt, (int)tm);
+                           s, m, kb, P, ldp, F, ldf, LTp, Mp, (int)tm);
+    MXLU_LAUNCH_CHECK();
+    return 0;
+}
+
+int lp_pack_u12(int64_t nt, int kb, const uint16_t *U12, int64_t ldf, uint16_t *Up, int64_t Np,
+                hipStream_t s) {
+    if (nt <= 0 || kb <= 0) return 0;
+    if (kb % kLpKc || ldf % 8 || Np < nt || ((uintptr_t)U12 | (uintptr_t)Up) % 16) {
+        set_error_msg("lp_pack_u12: kb % 32, ldf % 8, Np >= nt and 16-byte alignment required");
+        return MXLU_E_NOMEM;
+    }
+    const int64_t total = nt * (kb / 8);
+    const unsigned grid = (unsigned)std::min<int64_t>((total + 255) / 256, 65536);
+    hipLaunchKernelGGL(pack_u12_kernel, dim3(grid), dim3(256), 0, s, nt, kb, U12, ldf, Up, Np);
     MXLU_LAUNCH_CHECK();
     return 0;
 }

@@ -47,10 +47,11 @@ __device__ __forceinline__ void wave_argmax(double &v, int &idx) {
 //   1. local candidate: first row >= j of largest |a_ij| in the group;
 //   2. publish the candidate (|a|, row) and its whole leaf row and, by the
 //      owner, row j itself;
-//   3. gather: with at most kOnePhaseGroups groups, every group reads all
-//      candidates and candidate rows in one batch of loads; otherwise it
-//      reads the candidates first and then only the winner's row.  Every
-//      wave reduces the G candidates to the same winner p;
+//   3. gather (wave 0 of each group; fewer pollers on the same lines): with
+//      at most kOnePhaseGroups groups all candidates and candidate rows in
+//      one batch of loads, otherwise the candidates first and then only the
+//      winner's row.  Every wave reduces the G candidates to the same
+//      winner p;
 //   4. the owner threads of rows j and p swap those rows (whole leaf rows);
 //   5. every thread divides column j of its rows > j by the pivot and
 //      applies the rank-1 update to their columns > j.
@@ -76,8 +77,9 @@ __device__ __forceinline__ void wave_argmax(double &v, int &idx) {
 constexpr int kRowWords = 2 * mxlu::kLeafW;      // a leaf row, two words per value
 constexpr int kSlotWords = 4 + kRowWords;
 constexpr int kOnePhaseGroups = 8;               // one-batch gather up to this many groups
-constexpr int kOneBatch = (kOnePhaseGroups * kSlotWords + 255) / 256;
-constexpr int kCandPerThread = (mxlu::kMaxGroups * 3 + 255) / 256;
+// the gathers are done by wave 0 alone: fewer pollers on the same lines
+constexpr int kOneBatch = (kOnePhaseGroups * kSlotWords + 63) / 64;
+constexpr int kCandPerLane = (mxlu::kMaxGroups * 3 + 63) / 64;
 constexpr int kWordsLds = (kOnePhaseGroups * kSlotWords > mxlu::kMaxGroups * 3)
                               ? kOnePhaseGroups * kSlotWords
                               : mxlu::kMaxGroups * 3;
@@ -190,19 +192,22 @@ __global__ __launch_bounds__(256) void panel_leaf_kernel(
         if (one_phase) {
             // every slot word in use, and row j, in one batch
             const int nw = G * kSlotWords;
-            uint64_t x[kOneBatch];
+            if (wave == 0) {
+                uint64_t x[kOneBatch];
 #pragma unroll
-            for (int k = 0; k < kOneBatch; ++k) {
-                const int t = tid + 256 * k, u = t % kSlotWords;
-                x[k] = (t < nw && u != 3 && u < 4 + 2 * w) ? ll_load(&gs[t]) : 0ull;
-            }
-            const uint64_t y = (tid < 2 * w) ? ll_load(&grj[tid]) : 0ull;
+                for (int k = 0; k < kOneBatch; ++k) {
+                    const int t = lane + 64 * k, u = t % kSlotWords;
+                    x[k] = (t < nw && u != 3 && u < 4 + 2 * w) ? ll_load(&gs[t]) : 0ull;
+                }
+                const uint64_t y = (lane < 2 * w) ? ll_load(&grj[lane]) : 0ull;
 #pragma unroll
-            for (int k = 0; k < kOneBatch; ++k) {
-                const int t = tid + 256 * k, u = t % kSlotWords;
-                if (t < nw && u != 3 && u < 4 + 2 * w) s_words[t] = ll_wait(&gs[t], x[k], seq, flags);
+                for (int k = 0; k < kOneBatch; ++k) {
+                    const int t = lane + 64 * k, u = t % kSlotWords;
+                    if (t < nw && u != 3 && u < 4 + 2 * w)
+                        s_words[t] = ll_wait(&gs[t], x[k], seq, flags);
+                }
+                if (lane < 2 * w) s_rowj[lane] = ll_wait(&grj[lane], y, seq, flags);
             }
-            if (tid < 2 * w) s_rowj[tid] = ll_wait(&grj[tid], y, seq, flags);
             __syncthreads();
             for (int t = lane; t < G; t += 64)
                 argmax_merge(gv, gi, word_double(&s_words[t * kSlotWords]),
@@ -213,16 +218,19 @@ __global__ __launch_bounds__(256) void panel_leaf_kernel(
         } else {
             // the candidates first, then the winner's row (and row j when it moves)
             const int nc = G * 3;
-            uint64_t x[kCandPerThread];
+            if (wave == 0) {
+                uint64_t x[kCandPerLane];
 #pragma unroll
-            for (int k = 0; k < kCandPerThread; ++k) {
-                const int t = tid + 256 * k;
-                x[k] = (t < nc) ? ll_load(&gs[(t / 3) * kSlotWords + t % 3]) : 0ull;
-            }
+                for (int k = 0; k < kCandPerLane; ++k) {
+                    const int t = lane + 64 * k;
+                    x[k] = (t < nc) ? ll_load(&gs[(t / 3) * kSlotWords + t % 3]) : 0ull;
+                }
 #pragma unroll
-            for (int k = 0; k < kCandPerThread; ++k) {
-                const int t = tid + 256 * k;
-                if (t < nc) s_words[t] = ll_wait(&gs[(t / 3) * kSlotWords + t % 3], x[k], seq, flags);
+                for (int k = 0; k < kCandPerLane; ++k) {
+                    const int t = lane + 64 * k;
+                    if (t < nc)
+                        s_words[t] = ll_wait(&gs[(t / 3) * kSlotWords + t % 3], x[k], seq, flags);
+                }
             }
             __syncthreads();
             for (int t = lane; t < G; t += 64)

@@ -74,7 +74,8 @@ int lp_factorize(const mxp_opts &o, int64_t n, const double *A, int64_t lda, uin
     float *P32 = scratch.alloc_n<float>((size_t)n * nb);
     float *T32 = scratch.alloc_n<float>((size_t)nb * n);
     int *d_info = scratch.alloc_n<int>(4);
-    uint16_t *LT = nullptr;
+    uint16_t *LTp = nullptr, *Up = nullptr;   // chunk-packed L21 and U12 (16-bit form)
+    const int64_t Mp = lp_round_up(n, kLpTileM), Np = lp_round_up(n, kLpTileN);
     uint8_t *LTq = nullptr, *Uq = nullptr;
     float *sL = nullptr, *sU = nullptr;
     if (fp8) {
@@ -84,8 +85,9 @@ int lp_factorize(const mxp_opts &o, int64_t n, const double *A, int64_t lda, uin
         sU = scratch.alloc_n<float>((size_t)(n / tile + 2));
         if (!LTq || !Uq || !sL || !sU) return MXLU_E_NOMEM;
     } else {
-        LT = scratch.alloc_n<uint16_t>((size_t)nb * n);
-        if (!LT) return MXLU_E_NOMEM;
+        LTp = scratch.alloc_n<uint16_t>((size_t)nb * Mp);
+        Up = scratch.alloc_n<uint16_t>((size_t)nb * Np);
+        if (!LTp || !Up) return MXLU_E_NOMEM;
     }
     if (!P32 || !T32 || !d_info) return MXLU_E_NOMEM;
     MXLU_HIP_TRY(hipMemsetAsync(d_info, 0, 4 * sizeof(int), s));
@@ -116,7 +118,7 @@ int lp_factorize(const mxp_opts &o, int64_t n, const double *A, int64_t lda, uin
             else
                 MXLU_TRY(lp_panel_factor_nopiv(m, (int)kb, P32, m, d_info, k0, s));
             const bool need_lt = !fp8 && c1 < n;
-            MXLU_TRY(lp_panel_store(fmt, m, (int)kb, P32, m, Fk, ldf, need_lt ? LT : nullptr, kb, s));
+            MXLU_TRY(lp_panel_store(fmt, m, (int)kb, P32, m, Fk, ldf, need_lt ? LTp : nullptr, Mp, s));
             if (o.pivot && n > kb) {   // the panel's interchanges on the other stored columns
                 MXLU_TRY(swap_compose(ipiv, k0, (int)kb, moves, s));
                 MXLU_TRY(swap_apply<uint16_t>(F, ldf, k0, moves, 0, n - kb, k0, kb, s));
@@ -139,8 +141,9 @@ int lp_factorize(const mxp_opts &o, int64_t n, const double *A, int64_t lda, uin
                 PhaseScope ph(kPhaseLpSchur, s, schur_bytes);
                 MXLU_TRY(lp_schur_update_fp8(fmt, nt, nt, (int)kb, LTq, sL, Uq, sU, tile, A22, ldf, s));
             } else {
+                MXLU_TRY(lp_pack_u12(nt, (int)kb, U12, ldf, Up, Np, s));
                 PhaseScope ph(kPhaseLpSchur, s, schur_bytes);
-                MXLU_TRY(lp_schur_update(fmt, nt, nt, (int)kb, LT, kb, U12, ldf, A22, ldf, s));
+                MXLU_TRY(lp_schur_update(fmt, nt, nt, (int)kb, LTp, Mp, Up, Np, A22, ldf, s));
             }
         }
     }

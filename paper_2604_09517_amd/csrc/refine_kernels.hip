@@ -247,6 +247,9 @@ __global__ __launch_bounds__(256) void trsv_chain_kernel(int64_t n, const uint16
     constexpr bool UNIT = (KIND == 0 || KIND == 3);
     __shared__ uint16_t Ld[BS][BS + 2];   // raw stored values (129 KB)
     __shared__ float xprev[BS];
+    // column-major kinds: 32 columns x 256 rows of an earlier block, staged
+    // with 16-byte loads so that each thread can read its row
+    __shared__ __attribute__((aligned(16))) uint16_t stg[32][BS];
     const int tid = threadIdx.x;
     const int w = blockIdx.x;
     const int64_t myblk = FWD ? w : nblk - 1 - w;
@@ -262,21 +265,58 @@ __global__ __launch_bounds__(256) void trsv_chain_kernel(int64_t n, const uint16
         else Ld[k][ii] = f;     // transposed forms: Ld[i][k] = F[k][i]
     }
     float acc = (tid < rows) ? v[i] : 0.0f;
-    // fr: the thread's row of the earlier block, F values for k = 2j, 2j+1
-    // packed in one word; loaded before the wait for that block's solution
-    uint32_t fr[BS / 2];
+    constexpr bool COLMAJOR = (KIND == 0 || KIND == 1);
+    // column-major kinds, full blocks: chunk cc (32 columns of the earlier
+    // block) is loaded as 4 x 16 bytes per thread (8 rows of one column each)
+    auto ld_chunk = [&](int64_t p0, int cc, uint4 (&g)[4]) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int idx = tid + 256 * q, col = idx >> 5, rg = idx & 31;
+            const uint16_t *src = &F[(size_t)(r0 + 8 * rg) + (size_t)(p0 + 32 * cc + col) * ldf];
+            if (8 * rg + 8 <= rows) {
+                g[q] = *reinterpret_cast<const uint4 *>(src);
+            } else {   // rows past the matrix (last block): zeros
+                uint16_t h[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) h[e] = (8 * rg + e < rows) ? src[e] : (uint16_t)0;
+                g[q] = make_uint4(h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16),
+                                  h[4] | ((uint32_t)h[5] << 16), h[6] | ((uint32_t)h[7] << 16));
+            }
+        }
+    };
+    auto chunk_of = [&](int c) { return (KIND == 1) ? 7 - c : c; };   // solve order
+    auto apply_chunk = [&](int cc, const uint4 (&g)[4]) {
+        lds_barrier();   // the previous chunk is consumed
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int idx = tid + 256 * q, col = idx >> 5, rg = idx & 31;
+            *reinterpret_cast<uint4 *>(&stg[col][8 * rg]) = g[q];
+        }
+    };
+    auto fma_chunk = [&](int cc) {
+        if (KIND == 0) {
+#pragma unroll
+            for (int kk = 0; kk < 32; ++kk)
+                acc = fmaf(-lp_to_f32<FMT>(stg[kk][tid]), xprev[32 * cc + kk], acc);
+        } else {
+#pragma unroll
+            for (int kk = 31; kk >= 0; --kk)
+                acc = fmaf(-lp_to_f32<FMT>(stg[kk][tid]), xprev[32 * cc + kk], acc);
+        }
+    };
+    // transposed kinds: fr holds the thread's row of the earlier block, F
+    // values for k = 2j, 2j+1 packed in one word, loaded before the wait
+    uint32_t fr[COLMAJOR ? 1 : BS / 2];
+    uint4 g0[4], g1[4];
     for (int t = 0; t < w; ++t) {
         const int64_t pb = FWD ? t : nblk - 1 - t;
         const int64_t p0 = pb * BS;
         const int pr = (int)((n - p0 < BS) ? n - p0 : BS);
-        const bool full = (pr == BS) && (tid < rows);
+        const bool full = (pr == BS);   // the earlier block is full
         if (full) {
-            if (KIND == 0 || KIND == 1) {
-#pragma unroll
-                for (int j = 0; j < BS / 2; ++j)
-                    fr[j] = (uint32_t)F[(size_t)i + (size_t)(p0 + 2 * j) * ldf] |
-                            ((uint32_t)F[(size_t)i + (size_t)(p0 + 2 * j + 1) * ldf] << 16);
-            } else {   // F[k][i] for k in the earlier block: contiguous in k
+            if (COLMAJOR) {
+                ld_chunk(p0, chunk_of(0), g0);
+            } else if (tid < rows) {   // F[k][i] for k in the earlier block: contiguous in k
                 const uint4 *q = reinterpret_cast<const uint4 *>(&F[(size_t)p0 + (size_t)i * ldf]);
 #pragma unroll
                 for (int j = 0; j < BS / 8; ++j) {
@@ -289,12 +329,29 @@ __global__ __launch_bounds__(256) void trsv_chain_kernel(int64_t n, const uint16
             }
         }
         lds_barrier();   // the previous block's values are consumed
+        // one thread watches the block's first word (many pollers on the same
+        // lines would slow the producer's stores); then every thread reads
+        // its word, which has normally arrived by then
+        if (tid == 0) {
+            const uint64_t *src = &xs[p0];
+            uint64_t x = ll_load(src);
+            long spins = 0;
+            while ((uint32_t)(x >> 32) != tag) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > (1L << 26)) {
+                    atomicExch(expired, 1);
+                    break;
+                }
+                x = ll_load(src);
+            }
+        }
+        lds_barrier();
         if (tid < pr) {
             const uint64_t *src = &xs[p0 + tid];
             uint64_t x = ll_load(src);
             long spins = 0;
             while ((uint32_t)(x >> 32) != tag) {
-                __builtin_amdgcn_s_sleep(1);
+                __builtin_amdgcn_s_sleep(2);
                 if (++spins > (1L << 26)) {
                     atomicExch(expired, 1);
                     break;
@@ -304,22 +361,28 @@ __global__ __launch_bounds__(256) void trsv_chain_kernel(int64_t n, const uint16
             xprev[tid] = __uint_as_float((uint32_t)x);
         }
         lds_barrier();
-        if (full) {
-            // L, U^T, L^T: k ascending; U: k descending
-            if (KIND == 1) {
+        if (full && COLMAJOR) {
+            // chunks in solve order; the next chunk's loads are in flight
+            // during the current chunk's FMAs
 #pragma unroll
-                for (int j = BS / 2 - 1; j >= 0; --j) {
-                    acc = fmaf(-lp_to_f32<FMT>((uint16_t)(fr[j] >> 16)), xprev[2 * j + 1], acc);
-                    acc = fmaf(-lp_to_f32<FMT>((uint16_t)fr[j]), xprev[2 * j], acc);
-                }
-            } else {
-#pragma unroll
-                for (int j = 0; j < BS / 2; ++j) {
-                    acc = fmaf(-lp_to_f32<FMT>((uint16_t)fr[j]), xprev[2 * j], acc);
-                    acc = fmaf(-lp_to_f32<FMT>((uint16_t)(fr[j] >> 16)), xprev[2 * j + 1], acc);
-                }
+            for (int c = 0; c < 8; c += 2) {
+                apply_chunk(chunk_of(c), g0);
+                ld_chunk(p0, chunk_of(c + 1), g1);
+                lds_barrier();
+                fma_chunk(chunk_of(c));
+                apply_chunk(chunk_of(c + 1), g1);
+                if (c + 2 < 8) ld_chunk(p0, chunk_of(c + 2), g0);
+                lds_barrier();
+                fma_chunk(chunk_of(c + 1));
             }
-        } else if (tid < rows) {   // a partial earlier block (the last one of n)
+        } else if (full && tid < rows) {
+            // U^T, L^T: k ascending
+#pragma unroll
+            for (int j = 0; j < BS / 2; ++j) {
+                acc = fmaf(-lp_to_f32<FMT>((uint16_t)fr[j]), xprev[2 * j], acc);
+                acc = fmaf(-lp_to_f32<FMT>((uint16_t)(fr[j] >> 16)), xprev[2 * j + 1], acc);
+            }
+        } else if (tid < rows) {   // a partial block (the last one of n)
             if (KIND == 0) {
                 for (int k = 0; k < pr; ++k)
                     acc = fmaf(-lp_to_f32<FMT>(F[(size_t)i + (size_t)(p0 + k) * ldf]), xprev[k], acc);
@@ -332,58 +395,78 @@ __global__ __launch_bounds__(256) void trsv_chain_kernel(int64_t n, const uint16
             }
         }
     }
-    __syncthreads();
-    xprev[tid] = acc;      // hand the accumulated right-hand side to wave 0
-    __syncthreads();
-    if (tid >= 64) return;
-    // one wave: lane owns rows lane + 64 q.  Step s finishes x_k on its owner
-    // lane (division for U), broadcasts it with readlane and updates the
-    // remaining rows; the LDS values of step s + 1 are read during step s.
-    float x[BS / 64];
+    // Diagonal block: four sub-blocks of 64 rows in solve order.  Wave sb
+    // owns the rows of sub-block sb (thread = row, as above): it solves them
+    // (step j finishes x_k on its owner lane, division for U, and broadcasts
+    // it with readlane; the LDS value of step j + 1 is read during step j),
+    // publishes them in LDS, and the waves of the sub-blocks still to be
+    // solved apply them to their rows, k in solve order.  Every element still
+    // takes its terms in the textbook order.
+    constexpr int NSB = BS / 64;
+    const int wave = tid >> 6;
+    float x = acc;
+    const bool mine = tid < rows;
+    __syncthreads();   // xprev is reused for the solution
 #pragma unroll
-    for (int q = 0; q < BS / 64; ++q) x[q] = xprev[tid + 64 * q];
-    auto kof = [&](int st) { return FWD ? st : rows - 1 - st; };
-    float lc[BS / 64], dc = 1.0f;
-    {
-        const int k = kof(0);
+    for (int s = 0; s < NSB; ++s) {
+        const int sb = FWD ? s : NSB - 1 - s;
+        const int base = sb * 64;
+        const int len = min(64, rows - base);   // rows of this sub-block (<= 0: none)
+        if (wave == sb && len == 64) {
+            // full sub-block: the lane's row of it in registers, steps unrolled
+            const int lane = tid & 63;
+            uint32_t rr[32];
 #pragma unroll
-        for (int q = 0; q < BS / 64; ++q) lc[q] = lp_to_f32<FMT>(Ld[min(tid + 64 * q, BS - 1)][k]);
-        if (!UNIT) dc = lp_to_f32<FMT>(Ld[k][k]);
+            for (int p = 0; p < 32; ++p)
+                rr[p] = *reinterpret_cast<const uint32_t *>(&Ld[tid][base + 2 * p]);
+#pragma unroll
+            for (int j = 0; j < 64; ++j) {
+                const int kl = FWD ? j : 63 - j;
+                const uint32_t w2 = rr[kl >> 1];
+                const float lv = lp_to_f32<FMT>((uint16_t)((kl & 1) ? (w2 >> 16) : w2));
+                // on the owner lane lv is the diagonal entry
+                const float own = UNIT ? x : x / lv;
+                const float xk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(own), kl));
+                const float upd = fmaf(-lv, xk, x);
+                const bool later = FWD ? lane > kl : lane < kl;
+                x = (lane == kl) ? xk : (later ? upd : x);
+            }
+            xprev[tid] = x;
+        } else if (wave == sb && len > 0) {
+            auto kat = [&](int j) { return FWD ? base + j : base + len - 1 - j; };
+            // raw values of step j + 1 are read during step j (unconditionally:
+            // every thread's row is inside the LDS block; rows past the
+            // matrix are never stored)
+            uint16_t lc = Ld[tid][kat(0)], dc = Ld[kat(0)][kat(0)];
+            for (int j = 0; j < len; ++j) {
+                const int k = kat(j);
+                const int k1 = kat(j + 1 < len ? j + 1 : j);
+                const uint16_t ln = Ld[tid][k1], dn = Ld[k1][k1];
+                const float own = UNIT ? x : x / lp_to_f32<FMT>(dc);
+                const float xk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(own), k - base));
+                const float upd = fmaf(-lp_to_f32<FMT>(lc), xk, x);
+                const bool later = FWD ? tid > k : tid < k;
+                x = (tid == k) ? xk : (later ? upd : x);
+                lc = ln;
+                dc = dn;
+            }
+            xprev[tid] = x;
+        }
+        __syncthreads();
+        if (len > 0 && (FWD ? wave > sb : wave < sb) && mine) {
+            if (FWD) {
+                for (int j = 0; j < len; ++j)
+                    x = fmaf(-lp_to_f32<FMT>(Ld[tid][base + j]), xprev[base + j], x);
+            } else {
+                for (int j = len - 1; j >= 0; --j)
+                    x = fmaf(-lp_to_f32<FMT>(Ld[tid][base + j]), xprev[base + j], x);
+            }
+        }
     }
-    for (int st = 0; st < rows; ++st) {
-        const int k = kof(st);
-        const int kq = k >> 6, kl = k & 63;
-        float ln[BS / 64], dn = 1.0f;
-        if (st + 1 < rows) {
-            const int k1 = kof(st + 1);
-#pragma unroll
-            for (int q = 0; q < BS / 64; ++q) ln[q] = lp_to_f32<FMT>(Ld[min(tid + 64 * q, BS - 1)][k1]);
-            if (!UNIT) dn = lp_to_f32<FMT>(Ld[k1][k1]);
-        }
-        float own = 0.0f;
-#pragma unroll
-        for (int q = 0; q < BS / 64; ++q)
-            if (q == kq) own = x[q];
-        if (!UNIT) own = own / dc;
-        const float xk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(own), kl));
-#pragma unroll
-        for (int q = 0; q < BS / 64; ++q) {
-            const int r = tid + 64 * q;
-            if (r == k) x[q] = xk;
-            else if (r < rows && (FWD ? r > k : r < k)) x[q] = fmaf(-lc[q], xk, x[q]);
-        }
-#pragma unroll
-        for (int q = 0; q < BS / 64; ++q) lc[q] = ln[q];
-        dc = dn;
-    }
-#pragma unroll
-    for (int q = 0; q < BS / 64; ++q) {
-        const int r = tid + 64 * q;
-        if (r < rows) {
-            v[r0 + r] = x[q];
-            __hip_atomic_store(&xs[r0 + r], ((uint64_t)tag << 32) | __float_as_uint(x[q]),
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+    if (mine) {
+        v[i] = x;
+        __hip_atomic_store(&xs[i], ((uint64_t)tag << 32) | __float_as_uint(x), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
