@@ -107,7 +107,7 @@ typedef struct {
     int32_t max_inner_total; /* GMRES Arnoldi steps over all cycles */
     double inner_tol;        /* GMRES: stop a cycle when the estimate <= inner_tol * beta */
     double resid_threshold;  /* stop when the HPL scaled residual < this (16) */
-    int32_t scale_tile;      /* FP8: rows (cols) per scale tile of L21 (U12) */
+    int32_t scale_tile;      /* FP8: rows (cols) per scale tile of L21 (U12); a multiple of 4, <= 256 */
     int32_t reuse_factors;   /* 1: the factors in `work` come from an earlier call
                                 with the same A, n, opts: skip conversion and LU */
     int32_t trans;           /* 0: solve A X = B; 1: solve A^T X = B */

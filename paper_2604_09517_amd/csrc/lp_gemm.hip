@@ -5,16 +5,13 @@
 //   16-bit form:  A22 <- round( fp32(A22) - L21 U12 ), bf16 or fp16 operands,
 //                 v_mfma_f32_16x16x32_{bf16,f16}, accumulators start at A22.
 //   FP8 form:     A22 <- round_fp16( fp32(A22) - (Lq Uq) sL sU ), e4m3fn
-//                 operands with one power-of-two scale per 128-row tile of L21
-//                 and per 128-column tile of U12, v_mfma_scale_f32_16x16x128
-//                 _f8f6f4 with unit block scales, accumulators start at 0.
+//                 operands with one power-of-two scale per tile of rows of L21
+//                 and of columns of U12, v_mfma_scale_f32_16x16x128_f8f6f4
+//                 with unit block scales.
 //
-// Operands are read with k contiguous: chunk-packed L21 and U12 for the
-// 16-bit form, row-major e4m3 copies for FP8.  A workgroup of 4 waves owns a
-// 256 x 128 tile of A22 (each wave 128 x 64 = 8 x 4 MFMA blocks); K is
-// staged through LDS in chunks: a three-stage ring filled by direct
-// global->LDS loads for the 16-bit form, a single buffer with register
-// prefetch for FP8.
+// Operands come chunk-packed (one K chunk of one tile is one contiguous
+// block) and are staged through LDS rings filled by direct global->LDS
+// loads; see each form below for its tile and ring.
 //
 // MFMA lane layouts (measured on gfx950; lane l, i = l % 16, g = l / 16):
 //   16x16x32 16-bit: A lane holds A[i][8g .. 8g+7], B lane B[8g .. 8g+7][i],
@@ -197,102 +194,131 @@ __global__ __launch_bounds__(256, 2) void lp_schur16_kernel(
 }
 
 // ------------------------------------------------------------ FP8 form
-constexpr int BK8 = 128;
-constexpr int ST8 = BK8 + 16;   // bytes per staged row
+// A 4-wave workgroup owns a 128 x 128 tile (each wave 64 x 64 = 4 x 4 MFMA
+// blocks); two workgroups per CU.  One K chunk is 128 values (one MFMA K
+// step): 16 KB of L21 and 16 KB of U12, copied into a two-stage LDS ring with
+// 16-byte direct global->LDS loads (8 loads of 1 KB per wave and chunk).
+// The accumulators start at -C / (sL sU) (exact: power-of-two scales) and
+// take +Lq Uq, so that -acc sL sU = C - (Lq Uq) sL sU needs no operand
+// negation; C is read and written 8 bytes (4 rows) per lane.
+constexpr int kTm8 = 128, kTn8 = 128;
+constexpr int BK8 = kLp8Kc;
+constexpr int kNs8 = 2;
+static_assert(kTm8 == kLp8Tile && kTn8 == kLp8Tile, "tile and packing must agree");
 
 template <int FMT>
 __global__ __launch_bounds__(256, 2) void lp_schur8_kernel(
-    int64_t M, int64_t N, int K, const uint8_t *__restrict__ LTq, const float *__restrict__ sL,
-    const uint8_t *__restrict__ Uq, const float *__restrict__ sU, int tile,
-    uint16_t *__restrict__ C, int64_t ldc, int tiles_m, int tiles_n) {
-    __shared__ __attribute__((aligned(16))) uint8_t As[TM * ST8];
-    __shared__ __attribute__((aligned(16))) uint8_t Bs[TN * ST8];
+    int64_t M, int64_t N, int K, const uint8_t *__restrict__ Lq, int64_t Mp,
+    const float *__restrict__ sL, const uint8_t *__restrict__ Uq, int64_t Np,
+    const float *__restrict__ sU, int tile, uint16_t *__restrict__ C, int64_t ldc, int tiles_m,
+    int tiles_n) {
+    constexpr int SA = kTm8 * BK8, SB = kTn8 * BK8;   // bytes per stage
+    constexpr int NA = SA / 4 / 1024, NB = SB / 4 / 1024;
+    __shared__ __attribute__((aligned(1024))) uint8_t ring[kNs8][SA + SB];
 
     int tm, tn;
     tile_of(blockIdx.x, tiles_m, tiles_n, tm, tn);
-    const int64_t row0 = (int64_t)tm * TM, col0 = (int64_t)tn * TN;
+    const int64_t row0 = (int64_t)tm * kTm8, col0 = (int64_t)tn * kTn8;
+    // scale-tile index of a row or column (32-bit; a shift for power-of-two tiles)
+    const bool pow2 = (tile & (tile - 1)) == 0;
+    const int tshift = __builtin_ctz((unsigned)tile);
+    auto tix = [&](int64_t x) {
+        return pow2 ? (int)((uint32_t)x >> tshift) : (int)((uint32_t)x / (uint32_t)tile);
+    };
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int wm = wave & 1, wn = wave >> 1;
     const int li = lane & 15, lg = lane >> 4;
 
-    v4f acc[8][4];
+    v4f acc[4][4];
 #pragma unroll
-    for (int bi = 0; bi < 8; ++bi)
+    for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int bj = 0; bj < 4; ++bj) {
+            const int64_t r = row0 + wm * 64 + bi * 16 + 4 * lg;
+            const int64_t c = col0 + wn * 64 + bj * 16 + li;
+            if (c >= N || r >= M) {
+                acc[bi][bj] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+                continue;
+            }
+            const float inv = 1.0f / (sL[tix(r)] * sU[tix(c)]);   // rows r..r+3 share a tile
+            if (r + 3 < M) {
+                const uint2 v = *reinterpret_cast<const uint2 *>(&C[(size_t)r + (size_t)c * ldc]);
+                acc[bi][bj][0] = -lp_to_f32<FMT>((uint16_t)v.x) * inv;
+                acc[bi][bj][1] = -lp_to_f32<FMT>((uint16_t)(v.x >> 16)) * inv;
+                acc[bi][bj][2] = -lp_to_f32<FMT>((uint16_t)v.y) * inv;
+                acc[bi][bj][3] = -lp_to_f32<FMT>((uint16_t)(v.y >> 16)) * inv;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    acc[bi][bj][e] = (r + e < M) ? -lp_to_f32<FMT>(C[(size_t)(r + e) + (size_t)c * ldc]) * inv
+                                                 : 0.0f;
+            }
+        }
 
-    // staging: A row t (8 x 16 B = 128 k), B column t/2, half t%2 (4 x 16 B)
-    const int64_t a_row = row0 + tid;
-    const bool a_ok = a_row < M;
-    const int64_t b_col = col0 + (tid >> 1);
-    const bool b_ok = b_col < N;
-    const int b_k = (tid & 1) * 64;
-    uint4 ra[8], rb[4];
-    auto load = [&](int k0) {
-        const uint4 *pa = reinterpret_cast<const uint4 *>(LTq + (size_t)a_row * K + k0);
+    const char *gA = reinterpret_cast<const char *>(Lq + (size_t)row0 * BK8) + wave * (SA / 4) + lane * 16;
+    const char *gB = reinterpret_cast<const char *>(Uq + (size_t)col0 * BK8) + wave * (SB / 4) + lane * 16;
+    auto issue = [&](int kc, int st) {
+        const char *ga = gA + (size_t)kc * Mp * BK8;
+        const char *gb = gB + (size_t)kc * Np * BK8;
+        char *la = reinterpret_cast<char *>(&ring[st][0]) + wave * (SA / 4);
+        char *lb = reinterpret_cast<char *>(&ring[st][SA]) + wave * (SB / 4);
 #pragma unroll
-        for (int q = 0; q < 8; ++q) ra[q] = a_ok ? pa[q] : make_uint4(0, 0, 0, 0);
-        const uint4 *pb = reinterpret_cast<const uint4 *>(Uq + (size_t)b_col * K + k0 + b_k);
+        for (int q = 0; q < NA; ++q)
+            __builtin_amdgcn_global_load_lds((gvoid_t *)(ga + q * 1024), (lvoid_t *)(la + q * 1024),
+                                             16, 0, 0);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) rb[q] = b_ok ? pb[q] : make_uint4(0, 0, 0, 0);
+        for (int q = 0; q < NB; ++q)
+            __builtin_amdgcn_global_load_lds((gvoid_t *)(gb + q * 1024), (lvoid_t *)(lb + q * 1024),
+                                             16, 0, 0);
     };
-    auto store = [&]() {
-        uint4 *da = reinterpret_cast<uint4 *>(&As[tid * ST8]);
-#pragma unroll
-        for (int q = 0; q < 8; ++q) da[q] = ra[q];
-        uint4 *db = reinterpret_cast<uint4 *>(&Bs[(tid >> 1) * ST8 + b_k]);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) db[q] = rb[q];
+    auto frag = [](const uint8_t *p) {
+        const uint4 lo = reinterpret_cast<const uint4 *>(p)[0];
+        const uint4 hi = reinterpret_cast<const uint4 *>(p)[1];
+        return v8i{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
     };
 
     const int nk = K / BK8;
-    load(0);
+    static_assert(kNs8 == 2, "the wait below assumes two stages");
+    issue(0, 0);
     for (int kt = 0; kt < nk; ++kt) {
-        store();
-        __syncthreads();
-        if (kt + 1 < nk) load((kt + 1) * BK8);
-        v8i a[8], b[4];
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): chunk kt (and the C loads) landed
+        __syncthreads();                      // every wave's part; stage (kt + 1) % 2 free
+        if (kt + 1 < nk) issue(kt + 1, (kt + 1) % kNs8);
+        const uint8_t *as = &ring[kt % kNs8][0];
+        const uint8_t *bs = &ring[kt % kNs8][SA];
+        v8i a[4], b[4];
 #pragma unroll
-        for (int bi = 0; bi < 8; ++bi) {
-            const uint4 *p = reinterpret_cast<const uint4 *>(
-                &As[(wm * 128 + bi * 16 + li) * ST8 + lg * 32]);
-            const uint4 lo = p[0], hi = p[1];
-            a[bi] = v8i{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w,
-                        (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
-        }
+        for (int bi = 0; bi < 4; ++bi) a[bi] = frag(&as[(wm * 64 + bi * 16 + li) * BK8 + lg * 32]);
 #pragma unroll
-        for (int bj = 0; bj < 4; ++bj) {
-            const uint4 *p = reinterpret_cast<const uint4 *>(
-                &Bs[(wn * 64 + bj * 16 + li) * ST8 + lg * 32]);
-            const uint4 lo = p[0], hi = p[1];
-            b[bj] = v8i{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w,
-                        (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
-        }
+        for (int bj = 0; bj < 4; ++bj) b[bj] = frag(&bs[(wn * 64 + bj * 16 + li) * BK8 + lg * 32]);
 #pragma unroll
-        for (int bi = 0; bi < 8; ++bi)
+        for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
             for (int bj = 0; bj < 4; ++bj)
                 acc[bi][bj] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
                     a[bi], b[bj], acc[bi][bj], 0, 0, 0, 127, 0, 127);
-        __syncthreads();
     }
 
 #pragma unroll
-    for (int bi = 0; bi < 8; ++bi)
+    for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 4; ++bj) {
-            const int64_t r = row0 + wm * 128 + bi * 16 + 4 * lg;
+            const int64_t r = row0 + wm * 64 + bi * 16 + 4 * lg;
             const int64_t c = col0 + wn * 64 + bj * 16 + li;
-            if (c >= N) continue;
-            const float su = sU[c / tile];
+            if (c >= N || r >= M) continue;
+            const float sc = sL[tix(r)] * sU[tix(c)];
+            if (r + 3 < M) {
+                uint2 v;
+                v.x = (uint32_t)f32_to_lp<FMT>(-acc[bi][bj][0] * sc) |
+                      ((uint32_t)f32_to_lp<FMT>(-acc[bi][bj][1] * sc) << 16);
+                v.y = (uint32_t)f32_to_lp<FMT>(-acc[bi][bj][2] * sc) |
+                      ((uint32_t)f32_to_lp<FMT>(-acc[bi][bj][3] * sc) << 16);
+                *reinterpret_cast<uint2 *>(&C[(size_t)r + (size_t)c * ldc]) = v;
+            } else {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                if (r + e >= M) continue;
-                const float sl = sL[(r + e) / tile];
-                float upd = acc[bi][bj][e] * sl;   // exact: power-of-two scales
-                upd = upd * su;
-                uint16_t *p = &C[(size_t)(r + e) + (size_t)c * ldc];
-                *p = f32_to_lp<FMT>(lp_to_f32<FMT>(*p) - upd);
+                for (int e = 0; e < 4; ++e)
+                    if (r + e < M)
+                        C[(size_t)(r + e) + (size_t)c * ldc] = f32_to_lp<FMT>(-acc[bi][bj][e] * sc);
             }
         }
 }
@@ -321,22 +347,24 @@ int lp_schur_update(int fmt, int64_t M, int64_t N, int K, const uint16_t *Lp, in
     return 0;
 }
 
-int lp_schur_update_fp8(int fmt, int64_t M, int64_t N, int K, const uint8_t *LTq,
-                        const float *sL, const uint8_t *Uq, const float *sU, int tile,
-                        uint16_t *C, int64_t ldc, hipStream_t s) {
+int lp_schur_update_fp8(int fmt, int64_t M, int64_t N, int K, const uint8_t *Lq, int64_t Mp,
+                        const float *sL, const uint8_t *Uq, int64_t Np, const float *sU,
+                        int tile, uint16_t *C, int64_t ldc, hipStream_t s) {
     if (M <= 0 || N <= 0 || K <= 0) return 0;
-    if (K % BK8 || ((uintptr_t)LTq | (uintptr_t)Uq) % 16) {
-        set_error_msg("lp_schur_update_fp8: K must be a multiple of 128");
+    if (K % BK8 || Mp % kTm8 || Np % kTn8 || Mp < M || Np < N || tile % 4 || tile <= 0 ||
+        ldc % 4 || ((uintptr_t)Lq | (uintptr_t)Uq) % 16 || (uintptr_t)C % 8) {
+        set_error_msg("lp_schur_update_fp8: K % 128, padded packed operands, tile % 4, ldc % 4 "
+                      "and alignment required");
         return MXLU_E_NOMEM;
     }
-    const int64_t tiles_m = (M + TM - 1) / TM, tiles_n = (N + TN - 1) / TN;
+    const int64_t tiles_m = (M + kTm8 - 1) / kTm8, tiles_n = (N + kTn8 - 1) / kTn8;
     const dim3 grid((unsigned)(tiles_m * tiles_n));
     if (fmt == kFmtBf16)
-        hipLaunchKernelGGL(lp_schur8_kernel<kFmtBf16>, grid, dim3(256), 0, s, M, N, K, LTq, sL,
-                           Uq, sU, tile, C, ldc, (int)tiles_m, (int)tiles_n);
+        hipLaunchKernelGGL(lp_schur8_kernel<kFmtBf16>, grid, dim3(256), 0, s, M, N, K, Lq, Mp, sL,
+                           Uq, Np, sU, tile, C, ldc, (int)tiles_m, (int)tiles_n);
     else
-        hipLaunchKernelGGL(lp_schur8_kernel<kFmtFp16>, grid, dim3(256), 0, s, M, N, K, LTq, sL,
-                           Uq, sU, tile, C, ldc, (int)tiles_m, (int)tiles_n);
+        hipLaunchKernelGGL(lp_schur8_kernel<kFmtFp16>, grid, dim3(256), 0, s, M, N, K, Lq, Mp, sL,
+                           Uq, Np, sU, tile, C, ldc, (int)tiles_m, (int)tiles_n);
     MXLU_LAUNCH_CHECK();
     return 0;
 }

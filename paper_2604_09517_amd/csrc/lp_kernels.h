@@ -44,20 +44,26 @@ int lp_panel_store(int fmt, int64_t m, int kb, const float *P, int64_t ldp, uint
 // with Np lines.
 int lp_pack_u12(int64_t nt, int kb, const uint16_t *U12, int64_t ldf, uint16_t *Up, int64_t Np,
                 hipStream_t s);
-// FP8 operands of the trailing update with power-of-two tile scales.
+// FP8 operands of the trailing update with power-of-two tile scales, chunk-
+// packed like the 16-bit ones with chunks of kLp8Kc values (one byte each)
+// and lines rounded up to kLp8Tile: line r, value k at
+// ((k / kLp8Kc) * Rp + r) * kLp8Kc + k % kLp8Kc.
+constexpr int kLp8Kc = 128;
+constexpr int kLp8Tile = 128;
 int lp_quant_l21(int fmt, int64_t mt, int kb, int tile, const uint16_t *L21, int64_t ldf,
-                 uint8_t *LTq, float *sL, hipStream_t s);
+                 uint8_t *LTq, int64_t Mp, float *sL, hipStream_t s);
 int lp_quant_u12(int fmt, int64_t nt, int kb, int tile, const uint16_t *U12, int64_t ldf,
-                 uint8_t *Uq, float *sU, hipStream_t s);
+                 uint8_t *Uq, int64_t Np, float *sU, hipStream_t s);
 
 // Trailing update on the matrix cores:
 //   16-bit: C <- round(fp32(C) - L U) with L (M x K) and U (K x N) chunk-packed
 //           (Mp, Np lines), K % kLpKc == 0, C 8-byte aligned with ldc % 4 == 0
-//   FP8:    C <- round(fp32(C) - (LTq^T Uq) sL sU), operands e4m3fn
+//   FP8:    C <- round(fp32(C) - (Lq Uq) sL sU), e4m3fn operands chunk-packed
+//           (Mp, Np lines), K % kLp8Kc == 0, tile % 4 == 0
 int lp_schur_update(int fmt, int64_t M, int64_t N, int K, const uint16_t *Lp, int64_t Mp,
                     const uint16_t *Up, int64_t Np, uint16_t *C, int64_t ldc, hipStream_t s);
-int lp_schur_update_fp8(int fmt, int64_t M, int64_t N, int K, const uint8_t *LTq,
-                        const float *sL, const uint8_t *Uq, const float *sU, int tile,
-                        uint16_t *C, int64_t ldc, hipStream_t s);
+int lp_schur_update_fp8(int fmt, int64_t M, int64_t N, int K, const uint8_t *Lq, int64_t Mp,
+                        const float *sL, const uint8_t *Uq, int64_t Np, const float *sU,
+                        int tile, uint16_t *C, int64_t ldc, hipStream_t s);
 
 }  // namespace mxlu

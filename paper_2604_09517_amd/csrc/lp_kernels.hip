@@ -24,6 +24,14 @@
 
 namespace {
 
+// Barrier that orders LDS only, so that global loads issued before it stay in
+// flight across it (a full __syncthreads would wait for them).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 using namespace mxlu;
 
 // ---------------------------------------------------------------- convert
@@ -195,7 +203,8 @@ __global__ __launch_bounds__(256) void gemm_f32_sub_kernel(int64_t M, int64_t N,
 
 // ---------------------------------------------------------------- FP32 TRSM
 // B (kb x ncols) <- L^-1 B, L unit lower kb x kb (kb <= 256), thread per row,
-// 16 columns per workgroup, one LDS barrier per step.
+// 16 columns per workgroup, one LDS barrier per step; each thread reads its
+// row of L 32 columns at a time into registers, the next 32 in flight.
 __global__ __launch_bounds__(256) void trsm_f32_llnu_kernel(int kb, int64_t ncols,
                                                             const float *__restrict__ L,
                                                             int64_t ldl, float *__restrict__ B,
@@ -208,17 +217,33 @@ __global__ __launch_bounds__(256) void trsm_f32_llnu_kernel(int kb, int64_t ncol
 #pragma unroll
     for (int c = 0; c < 16; ++c)
         b[c] = (i < kb && c < nc) ? B[(size_t)i + (size_t)(c0 + c) * ldb] : 0.0f;
-    float lnext = (i < kb && i > 0) ? L[(size_t)i] : 0.0f;
-    for (int k = 0; k < kb; ++k) {
-        const float l = lnext;
-        lnext = (k + 1 < kb && i < kb && i > k + 1) ? L[(size_t)i + (size_t)(k + 1) * ldl] : 0.0f;
-        if (i == k)
+    // the thread's row of L in chunks of 32 columns, the next chunk in flight
+    // while the current one is used
+    float lc[32], ln[32];
+    auto load_chunk = [&](int k0, float (&l)[32]) {
 #pragma unroll
-            for (int c = 0; c < 16; ++c) xs[k & 1][c] = b[c];
-        __syncthreads();
-        if (i > k && i < kb)
+        for (int kk = 0; kk < 32; ++kk) {
+            const int k = k0 + kk;
+            l[kk] = (i < kb && k < kb && i > k) ? L[(size_t)i + (size_t)k * ldl] : 0.0f;
+        }
+    };
+    load_chunk(0, lc);
+    for (int k0 = 0; k0 < kb; k0 += 32) {
+        if (k0 + 32 < kb) load_chunk(k0 + 32, ln);
 #pragma unroll
-            for (int c = 0; c < 16; ++c) b[c] = fmaf(-l, xs[k & 1][c], b[c]);
+        for (int kk = 0; kk < 32; ++kk) {
+            const int k = k0 + kk;
+            if (k >= kb) break;
+            if (i == k)
+#pragma unroll
+                for (int c = 0; c < 16; ++c) xs[k & 1][c] = b[c];
+            lds_barrier();
+            if (i > k && i < kb)
+#pragma unroll
+                for (int c = 0; c < 16; ++c) b[c] = fmaf(-lc[kk], xs[k & 1][c], b[c]);
+        }
+#pragma unroll
+        for (int kk = 0; kk < 32; ++kk) lc[kk] = ln[kk];
     }
     if (i < kb)
 #pragma unroll
@@ -290,7 +315,7 @@ template <int FMT>
 __global__ __launch_bounds__(256) void quant_l21_kernel(int64_t mt, int kb, int tile,
                                                         const uint16_t *__restrict__ L21,
                                                         int64_t ldf, uint8_t *__restrict__ LTq,
-                                                        float *__restrict__ sL) {
+                                                        int64_t Mp, float *__restrict__ sL) {
     __shared__ float red[256];
     __shared__ uint8_t T[64][256 + 4];
     const int64_t r0 = (int64_t)blockIdx.x * tile;
@@ -319,7 +344,8 @@ __global__ __launch_bounds__(256) void quant_l21_kernel(int64_t mt, int kb, int 
         __syncthreads();
         for (int t = tid; t < cw * rows; t += 256) {
             const int j = t % cw, i = t / cw;
-            LTq[(size_t)(c0 + j) + (size_t)(r0 + i) * kb] = T[j][i];
+            const int k = c0 + j;
+            LTq[((size_t)(k / kLp8Kc) * Mp + (size_t)(r0 + i)) * kLp8Kc + (k % kLp8Kc)] = T[j][i];
         }
     }
 }
@@ -330,7 +356,7 @@ template <int FMT>
 __global__ __launch_bounds__(256) void quant_u12_kernel(int64_t nt, int kb, int tile,
                                                         const uint16_t *__restrict__ U12,
                                                         int64_t ldf, uint8_t *__restrict__ Uq,
-                                                        float *__restrict__ sU) {
+                                                        int64_t Np, float *__restrict__ sU) {
     __shared__ float red[256];
     const int64_t q0 = (int64_t)blockIdx.x * tile;
     const int cols = (int)((nt - q0 < tile) ? nt - q0 : tile);
@@ -350,7 +376,7 @@ __global__ __launch_bounds__(256) void quant_u12_kernel(int64_t nt, int kb, int 
     const float inv = 1.0f / sc;
     for (int j = 0; j < cols; ++j)
         for (int k = tid; k < kb; k += 256)
-            Uq[(size_t)k + (size_t)(q0 + j) * kb] =
+            Uq[((size_t)(k / kLp8Kc) * Np + (size_t)(q0 + j)) * kLp8Kc + (k % kLp8Kc)] =
                 f32_to_e4m3(lp_to_f32<FMT>(U12[(size_t)k + (size_t)(q0 + j) * ldf]) * inv);
 }
 
@@ -415,25 +441,36 @@ int gemm_f32_sub(int64_t M, int64_t N, int64_t K, const float *A, int64_t lda, c
     return 0;
 }
 
+// Columns [c0, c0 + w) of the panel (rows c0 .. m-1 still to be finished),
+// factored recursively: left half, its U12 (unit-lower TRSM), the update of
+// the right half (one GEMM with K = the left width), right half; leaves of
+// kLpIb columns.  Every element still takes its terms in ascending k, one
+// fused multiply-add each, so the result equals the column-by-column order.
+static int panel_nopiv_rec(int64_t m, int64_t c0, int64_t w, float *P, int64_t ldp, int *info,
+                           int64_t col_base, hipStream_t s) {
+    if (w <= kLpIb) {
+        const int64_t rows_below = m - c0 - w;
+        const int nrow = (int)((rows_below + 255) / 256);
+        hipLaunchKernelGGL(lp_leaf_nopiv_kernel, dim3((unsigned)(nrow > 0 ? nrow : 1)), dim3(256), 0,
+                           s, (int)m, (int)(c0 + w), (int)c0, (int)w, P, ldp, nrow, info, col_base);
+        MXLU_LAUNCH_CHECK();
+        return 0;
+    }
+    const int64_t w1 = std::max<int64_t>(kLpIb, (w / 2) / kLpIb * kLpIb);
+    MXLU_TRY(panel_nopiv_rec(m, c0, w1, P, ldp, info, col_base, s));
+    float *L11 = P + (size_t)c0 + (size_t)c0 * ldp;
+    float *U12 = P + (size_t)c0 + (size_t)(c0 + w1) * ldp;
+    MXLU_TRY(trsm_f32_llnu(w1, w - w1, L11, ldp, U12, ldp, s));
+    if (m - c0 - w1 > 0)
+        MXLU_TRY(gemm_f32_sub(m - c0 - w1, w - w1, w1, P + (size_t)(c0 + w1) + (size_t)c0 * ldp, ldp,
+                              U12, ldp, P + (size_t)(c0 + w1) + (size_t)(c0 + w1) * ldp, ldp, s));
+    return panel_nopiv_rec(m, c0 + w1, w - w1, P, ldp, info, col_base, s);
+}
+
 int lp_panel_factor_nopiv(int64_t m, int kb, float *P, int64_t ldp, int *info, int64_t col_base,
                           hipStream_t s) {
-    for (int c = 0; c < kb; c += kLpIb) {
-        const int ib = (kb - c < kLpIb) ? kb - c : kLpIb;
-        const int64_t rows_below = m - c - ib;
-        const int nrow = (int)((rows_below + 255) / 256);
-        const int ncol = (kb - c - ib + 255) / 256;
-        const int grid = (nrow + ncol > 0) ? nrow + ncol : 1;
-        hipLaunchKernelGGL(lp_leaf_nopiv_kernel, dim3(grid), dim3(256), 0, s, (int)m, kb, c, ib, P,
-                           ldp, nrow, info, col_base);
-        MXLU_LAUNCH_CHECK();
-        if (c + ib < kb && rows_below > 0) {
-            int rc = gemm_f32_sub(rows_below, kb - c - ib, ib, P + (size_t)(c + ib) + (size_t)c * ldp,
-                                  ldp, P + (size_t)c + (size_t)(c + ib) * ldp, ldp,
-                                  P + (size_t)(c + ib) + (size_t)(c + ib) * ldp, ldp, s);
-            if (rc) return rc;
-        }
-    }
-    return 0;
+    if (m <= 0 || kb <= 0) return 0;
+    return panel_nopiv_rec(m, 0, kb, P, ldp, info, col_base, s);
 }
 
 int trsm_f32_llnu(int64_t kb, int64_t ncols, const float *L, int64_t ldl, float *B, int64_t ldb,
@@ -485,33 +522,37 @@ int lp_pack_u12(int64_t nt, int kb, const uint16_t *U12, int64_t ldf, uint16_t *
 }
 
 int lp_quant_l21(int fmt, int64_t mt, int kb, int tile, const uint16_t *L21, int64_t ldf,
-                 uint8_t *LTq, float *sL, hipStream_t s) {
+                 uint8_t *LTq, int64_t Mp, float *sL, hipStream_t s) {
     if (mt <= 0 || kb <= 0) return 0;
-    if (tile > 256) {
-        set_error_msg("lp_quant_l21: scale tile larger than 256 rows");
+    if (tile > 256 || kb % kLp8Kc || Mp < mt) {
+        set_error_msg("lp_quant_l21: scale tile > 256, kb % 128 or Mp < rows");
         return MXLU_E_NOMEM;
     }
     const unsigned grid = (unsigned)((mt + tile - 1) / tile);
     if (fmt == kFmtBf16)
         hipLaunchKernelGGL(quant_l21_kernel<kFmtBf16>, dim3(grid), dim3(256), 0, s, mt, kb, tile,
-                           L21, ldf, LTq, sL);
+                           L21, ldf, LTq, Mp, sL);
     else
         hipLaunchKernelGGL(quant_l21_kernel<kFmtFp16>, dim3(grid), dim3(256), 0, s, mt, kb, tile,
-                           L21, ldf, LTq, sL);
+                           L21, ldf, LTq, Mp, sL);
     MXLU_LAUNCH_CHECK();
     return 0;
 }
 
 int lp_quant_u12(int fmt, int64_t nt, int kb, int tile, const uint16_t *U12, int64_t ldf,
-                 uint8_t *Uq, float *sU, hipStream_t s) {
+                 uint8_t *Uq, int64_t Np, float *sU, hipStream_t s) {
     if (nt <= 0 || kb <= 0) return 0;
+    if (kb % kLp8Kc || Np < nt) {
+        set_error_msg("lp_quant_u12: kb % 128 or Np < columns");
+        return MXLU_E_NOMEM;
+    }
     const unsigned grid = (unsigned)((nt + tile - 1) / tile);
     if (fmt == kFmtBf16)
         hipLaunchKernelGGL(quant_u12_kernel<kFmtBf16>, dim3(grid), dim3(256), 0, s, nt, kb, tile,
-                           U12, ldf, Uq, sU);
+                           U12, ldf, Uq, Np, sU);
     else
         hipLaunchKernelGGL(quant_u12_kernel<kFmtFp16>, dim3(grid), dim3(256), 0, s, nt, kb, tile,
-                           U12, ldf, Uq, sU);
+                           U12, ldf, Uq, Np, sU);
     MXLU_LAUNCH_CHECK();
     return 0;
 }

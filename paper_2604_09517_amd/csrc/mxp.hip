@@ -78,9 +78,10 @@ int lp_factorize(const mxp_opts &o, int64_t n, const double *A, int64_t lda, uin
     const int64_t Mp = lp_round_up(n, kLpTileM), Np = lp_round_up(n, kLpTileN);
     uint8_t *LTq = nullptr, *Uq = nullptr;
     float *sL = nullptr, *sU = nullptr;
+    const int64_t Mp8 = lp_round_up(n, kLp8Tile), Np8 = lp_round_up(n, kLp8Tile);
     if (fp8) {
-        LTq = scratch.alloc_n<uint8_t>((size_t)nb * n);
-        Uq = scratch.alloc_n<uint8_t>((size_t)nb * n);
+        LTq = scratch.alloc_n<uint8_t>((size_t)nb * Mp8);
+        Uq = scratch.alloc_n<uint8_t>((size_t)nb * Np8);
         sL = scratch.alloc_n<float>((size_t)(n / tile + 2));
         sU = scratch.alloc_n<float>((size_t)(n / tile + 2));
         if (!LTq || !Uq || !sL || !sU) return MXLU_E_NOMEM;
@@ -136,10 +137,11 @@ int lp_factorize(const mxp_opts &o, int64_t n, const double *A, int64_t lda, uin
                 4.0 * (double)nt * (double)nt + 2.0 * ob * (double)nt * (double)kb;
             if (fp8) {
                 const uint16_t *L21 = F + (size_t)c1 + (size_t)k0 * ldf;
-                MXLU_TRY(lp_quant_l21(fmt, nt, (int)kb, tile, L21, ldf, LTq, sL, s));
-                MXLU_TRY(lp_quant_u12(fmt, nt, (int)kb, tile, U12, ldf, Uq, sU, s));
+                MXLU_TRY(lp_quant_l21(fmt, nt, (int)kb, tile, L21, ldf, LTq, Mp8, sL, s));
+                MXLU_TRY(lp_quant_u12(fmt, nt, (int)kb, tile, U12, ldf, Uq, Np8, sU, s));
                 PhaseScope ph(kPhaseLpSchur, s, schur_bytes);
-                MXLU_TRY(lp_schur_update_fp8(fmt, nt, nt, (int)kb, LTq, sL, Uq, sU, tile, A22, ldf, s));
+                MXLU_TRY(lp_schur_update_fp8(fmt, nt, nt, (int)kb, LTq, Mp8, sL, Uq, Np8, sU, tile,
+                                             A22, ldf, s));
             } else {
                 MXLU_TRY(lp_pack_u12(nt, (int)kb, U12, ldf, Up, Np, s));
                 PhaseScope ph(kPhaseLpSchur, s, schur_bytes);
@@ -364,7 +366,7 @@ extern "C" int mxp_convert(int32_t prec, int64_t rows, int64_t cols, const doubl
 extern "C" int mxp_solve(int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *B,
                          int64_t ldb, double *X, int64_t ldx, void *work, size_t work_bytes,
                          int32_t *ipiv, const mxp_opts *opts, mxp_report *report, void *stream) {
-    if (n < 0) return -1;
+    if (n < 0 || n > 0x7fffffff) return -1;
     if (nrhs < 0) return -2;
     if (n > 0 && !A) return -3;
     if (lda < std::max<int64_t>(1, n)) return -4;
@@ -376,8 +378,8 @@ extern "C" int mxp_solve(int64_t n, int64_t nrhs, const double *A, int64_t lda, 
     if (!opts) return -12;
     const mxp_opts &o = *opts;
     if (o.prec < 0 || o.prec > 2 || (o.pivot != 0 && o.pivot != 1) || o.nb < 32 ||
-        o.nb % 32 != 0 || (o.prec == MXLU_PREC_FP8 && (o.nb % 128 != 0 || o.scale_tile < 1 ||
-                                                       o.scale_tile > 256)) ||
+        o.nb % 32 != 0 || (o.prec == MXLU_PREC_FP8 && (o.nb % 128 != 0 || o.scale_tile < 4 ||
+                                                       o.scale_tile > 256 || o.scale_tile % 4)) ||
         (o.refine != MXLU_IR_CLASSICAL && o.refine != MXLU_IR_GMRES) || o.restart < 1 ||
         o.restart > 255 || o.max_outer < 0 || o.max_inner_total < 0 || o.trans < 0 ||
         o.trans > 1)
