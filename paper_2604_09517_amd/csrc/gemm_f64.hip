@@ -163,6 +163,125 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_sub_kernel(
         }
 }
 
+// Trailing update of the factorization, full tiles only: C -= A B with the
+// same 128 x 128 tile and wave layout as above, but both operands are copied
+// into an LDS ring of kRing stages (K chunks of 8) with 16-byte direct
+// global->LDS loads, so no registers stage them and two chunks are in flight
+// during the MFMAs of the current one (one barrier per chunk).  A is read
+// from the column-major matrix (one 1 KB load per k column of a tile); B is
+// read from Bn, a packed copy of -B^T (row k holds -B[k][0 .. N), leading
+// dimension ldbn), so the product needs no negation.
+constexpr int kRingBK = 8, kRing = 3;
+constexpr int kRingSA = kRingBK * AST, kRingSB = kRingBK * BST;   // doubles per stage
+
+typedef __attribute__((address_space(1))) void gvoid_t;
+typedef __attribute__((address_space(3))) void lvoid_t;
+
+__global__ __launch_bounds__(256, 2) void gemm_f64_ring_kernel(
+    int64_t M, int64_t N, int64_t K, const double *__restrict__ A, int64_t lda,
+    const double *__restrict__ Bn, int64_t ldbn, double *__restrict__ C, int64_t ldc,
+    int tiles_m, int tiles_n) {
+    __shared__ __attribute__((aligned(1024))) double ring[kRing][kRingSA + kRingSB];
+
+    int tm, tn;
+    tile_of(blockIdx.x, tiles_m, tiles_n, tm, tn);
+    const int64_t row0 = (int64_t)tm * BM;
+    const int64_t col0 = (int64_t)tn * BN;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int li = lane & 15, lq = lane >> 4;
+
+    v4d acc[4][4];
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj) {
+            const int64_t r = row0 + wm * 64 + bi * 16 + lq;
+            const int64_t c = col0 + wn * 64 + bj * 16 + li;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[bi][bj][e] = MXLU_AT(C, r + 4 * e, c, ldc);
+        }
+
+    // wave w copies k rows 2w and 2w + 1 of a chunk: 128 values of A's
+    // column and 128 values of Bn's row each (64 lanes x 16 bytes)
+    auto issue = [&](int kc, int st) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int r = 2 * wave + h;
+            const int64_t k = (int64_t)kc * kRingBK + r;
+            __builtin_amdgcn_global_load_lds((gvoid_t *)&MXLU_AT(A, row0 + 2 * lane, k, lda),
+                                             (lvoid_t *)&ring[st][r * AST], 16, 0, 0);
+            __builtin_amdgcn_global_load_lds((gvoid_t *)&Bn[(size_t)k * ldbn + col0 + 2 * lane],
+                                             (lvoid_t *)&ring[st][kRingSA + r * BST], 16, 0, 0);
+        }
+    };
+
+    const int nk = (int)(K / kRingBK);
+#pragma unroll
+    for (int c = 0; c < kRing - 1; ++c)
+        if (c < nk) issue(c, c);
+    for (int kt = 0; kt < nk; ++kt) {
+        // chunk kt has landed once the loads of the chunk issued after it (4
+        // per wave) are the only ones outstanding; the C loads came first
+        static_assert(kRing == 3, "the wait below assumes three stages");
+        if (kt + 1 < nk) __builtin_amdgcn_s_waitcnt(0x0F70 | 4);   // vmcnt(4)
+        else __builtin_amdgcn_s_waitcnt(0x0F70);                   // vmcnt(0)
+        __syncthreads();   // every wave's part of chunk kt; stage (kt - 1) % 3 free
+        if (kt + kRing - 1 < nk) issue(kt + kRing - 1, (kt + kRing - 1) % kRing);
+        const double *as = &ring[kt % kRing][0];
+        const double *bs = &ring[kt % kRing][kRingSA];
+#pragma unroll
+        for (int kk = 0; kk < kRingBK; kk += 4) {
+            double a[4], b[4];
+#pragma unroll
+            for (int bi = 0; bi < 4; ++bi) a[bi] = as[(kk + lq) * AST + wm * 64 + bi * 16 + li];
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj) b[bj] = bs[(kk + lq) * BST + wn * 64 + bj * 16 + li];
+#pragma unroll
+            for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 4; ++bj)
+                    acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], acc[bi][bj],
+                                                                       0, 0, 0);
+        }
+    }
+
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj) {
+            const int64_t r = row0 + wm * 64 + bi * 16 + lq;
+            const int64_t c = col0 + wn * 64 + bj * 16 + li;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) MXLU_AT(C, r + 4 * e, c, ldc) = acc[bi][bj][e];
+        }
+}
+
+// Bn[k][j] = -B[k][j] (B column-major K x N, Bn row-major with ldbn), through
+// 32 x 32 LDS tiles so that reads and writes are both coalesced.
+__global__ __launch_bounds__(256) void pack_neg_transpose_kernel(int64_t K, int64_t N,
+                                                                 const double *__restrict__ B,
+                                                                 int64_t ldb,
+                                                                 double *__restrict__ Bn,
+                                                                 int64_t ldbn, int tiles_k) {
+    __shared__ double T[32][33];
+    const int64_t k0 = (int64_t)(blockIdx.x % tiles_k) * 32;
+    const int64_t j0 = (int64_t)(blockIdx.x / tiles_k) * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t k = k0 + tx, j = j0 + ty + 8 * q;
+        T[ty + 8 * q][tx] = (k < K && j < N) ? -B[(size_t)k + (size_t)j * ldb] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t k = k0 + ty + 8 * q, j = j0 + tx;
+        if (k < K && j < N) Bn[(size_t)k * ldbn + j] = T[tx][ty + 8 * q];
+    }
+}
+
 // Tall-skinny update for few right-hand sides (N <= 16): C -= A * B with one
 // thread per row of C; B (K x N) is staged in LDS.  Memory-bound on A.
 template <int NMAX>
@@ -230,6 +349,43 @@ int gemm_f64_sub(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
     else
         hipLaunchKernelGGL((gemm_f64_sub_kernel<false, false, false>), grid, dim3(256), 0, s, M, N,
                            K, A, lda, B, ldb, C, ldc, (int)tiles_m, (int)tiles_n);
+    MXLU_LAUNCH_CHECK();
+    return 0;
+}
+
+bool gemm_f64_ring_ok(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda) {
+    return M > 0 && N > 0 && K > 0 && M % BM == 0 && N % BN == 0 && K % kRingBK == 0 &&
+           lda % 2 == 0 && ((uintptr_t)A % 16) == 0;
+}
+
+int pack_neg_transpose_f64(int64_t K, int64_t N, const double *B, int64_t ldb, double *Bn,
+                           int64_t ldbn, hipStream_t s) {
+    if (K <= 0 || N <= 0) return 0;
+    const int64_t tiles_k = (K + 31) / 32, tiles_j = (N + 31) / 32;
+    if (tiles_k * tiles_j > 0x7fffffff || ldbn < N) {
+        set_error_msg("pack_neg_transpose_f64: bad shape");
+        return MXLU_E_NOMEM;
+    }
+    hipLaunchKernelGGL(pack_neg_transpose_kernel, dim3((unsigned)(tiles_k * tiles_j)), dim3(256), 0,
+                       s, K, N, B, ldb, Bn, ldbn, (int)tiles_k);
+    MXLU_LAUNCH_CHECK();
+    return 0;
+}
+
+int gemm_f64_ring(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
+                  const double *Bn, int64_t ldbn, double *C, int64_t ldc, hipStream_t s) {
+    if (M <= 0 || N <= 0 || K <= 0) return 0;
+    if (!gemm_f64_ring_ok(M, N, K, A, lda) || !Bn || ldbn < N || ldbn % 2 || (uintptr_t)Bn % 16) {
+        set_error_msg("gemm_f64_ring: shape, leading dimension or alignment not supported");
+        return MXLU_E_NOMEM;
+    }
+    const int64_t tiles_m = M / BM, tiles_n = N / BN;
+    if (tiles_m * tiles_n > 0x7fffffff) {
+        set_error_msg("gemm_f64_ring: grid too large");
+        return MXLU_E_NOMEM;
+    }
+    hipLaunchKernelGGL(gemm_f64_ring_kernel, dim3((unsigned)(tiles_m * tiles_n)), dim3(256), 0, s,
+                       M, N, K, A, lda, Bn, ldbn, C, ldc, (int)tiles_m, (int)tiles_n);
     MXLU_LAUNCH_CHECK();
     return 0;
 }

@@ -99,28 +99,37 @@ __global__ __launch_bounds__(256, 2) void lp_schur16_kernel(
     const int wm = wave & 1, wn = wave >> 1;
     const int li = lane & 15, lg = lane >> 4;
 
-    // accumulators <- C (rows r .. r+3 of column c per lane)
+    // accumulators <- C (rows r .. r+3 of column c per lane); interior tiles
+    // (uniform branch) issue all their loads back to back without checks
+    const bool full = row0 + TM <= M && col0 + TN <= N;
     v4f acc[8][4];
+    if (full) {
 #pragma unroll
-    for (int bi = 0; bi < 8; ++bi)
+        for (int bi = 0; bi < 8; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < 4; ++bj) {
-            const int64_t r = row0 + wm * 128 + bi * 16 + 4 * lg;
-            const int64_t c = col0 + wn * 64 + bj * 16 + li;
-            if (r + 3 < M && c < N) {
+            for (int bj = 0; bj < 4; ++bj) {
+                const int64_t r = row0 + wm * 128 + bi * 16 + 4 * lg;
+                const int64_t c = col0 + wn * 64 + bj * 16 + li;
                 const uint2 v = *reinterpret_cast<const uint2 *>(&C[(size_t)r + (size_t)c * ldc]);
                 acc[bi][bj][0] = lp_to_f32<FMT>((uint16_t)v.x);
                 acc[bi][bj][1] = lp_to_f32<FMT>((uint16_t)(v.x >> 16));
                 acc[bi][bj][2] = lp_to_f32<FMT>((uint16_t)v.y);
                 acc[bi][bj][3] = lp_to_f32<FMT>((uint16_t)(v.y >> 16));
-            } else {
+            }
+    } else {
+#pragma unroll
+        for (int bi = 0; bi < 8; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj) {
+                const int64_t r = row0 + wm * 128 + bi * 16 + 4 * lg;
+                const int64_t c = col0 + wn * 64 + bj * 16 + li;
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
                     acc[bi][bj][e] = (r + e < M && c < N)
                                          ? lp_to_f32<FMT>(C[(size_t)(r + e) + (size_t)c * ldc])
                                          : 0.0f;
             }
-        }
+    }
 
     // chunk kc of this tile: L21 bytes [4 KB wave, 4 KB (wave+1)), U12 bytes
     // [2 KB wave, 2 KB (wave+1)) go to stage st
@@ -177,7 +186,7 @@ __global__ __launch_bounds__(256, 2) void lp_schur16_kernel(
         for (int bj = 0; bj < 4; ++bj) {
             const int64_t r = row0 + wm * 128 + bi * 16 + 4 * lg;
             const int64_t c = col0 + wn * 64 + bj * 16 + li;
-            if (r + 3 < M && c < N) {
+            if (full) {
                 uint2 v;
                 v.x = (uint32_t)f32_to_lp<FMT>(acc[bi][bj][0]) |
                       ((uint32_t)f32_to_lp<FMT>(acc[bi][bj][1]) << 16);
@@ -229,31 +238,40 @@ __global__ __launch_bounds__(256, 2) void lp_schur8_kernel(
     const int wm = wave & 1, wn = wave >> 1;
     const int li = lane & 15, lg = lane >> 4;
 
+    // accumulators <- -C / (sL sU); interior tiles (uniform branch) issue all
+    // their loads back to back without checks
+    const bool full = row0 + kTm8 <= M && col0 + kTn8 <= N;
     v4f acc[4][4];
+    if (full) {
 #pragma unroll
-    for (int bi = 0; bi < 4; ++bi)
+        for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < 4; ++bj) {
-            const int64_t r = row0 + wm * 64 + bi * 16 + 4 * lg;
-            const int64_t c = col0 + wn * 64 + bj * 16 + li;
-            if (c >= N || r >= M) {
-                acc[bi][bj] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-                continue;
-            }
-            const float inv = 1.0f / (sL[tix(r)] * sU[tix(c)]);   // rows r..r+3 share a tile
-            if (r + 3 < M) {
+            for (int bj = 0; bj < 4; ++bj) {
+                const int64_t r = row0 + wm * 64 + bi * 16 + 4 * lg;
+                const int64_t c = col0 + wn * 64 + bj * 16 + li;
                 const uint2 v = *reinterpret_cast<const uint2 *>(&C[(size_t)r + (size_t)c * ldc]);
+                const float inv = 1.0f / (sL[tix(r)] * sU[tix(c)]);   // rows r..r+3 share a tile
                 acc[bi][bj][0] = -lp_to_f32<FMT>((uint16_t)v.x) * inv;
                 acc[bi][bj][1] = -lp_to_f32<FMT>((uint16_t)(v.x >> 16)) * inv;
                 acc[bi][bj][2] = -lp_to_f32<FMT>((uint16_t)v.y) * inv;
                 acc[bi][bj][3] = -lp_to_f32<FMT>((uint16_t)(v.y >> 16)) * inv;
-            } else {
+            }
+    } else {
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj) {
+                const int64_t r = row0 + wm * 64 + bi * 16 + 4 * lg;
+                const int64_t c = col0 + wn * 64 + bj * 16 + li;
+                const bool in = r < M && c < N;
+                const float inv = in ? 1.0f / (sL[tix(r)] * sU[tix(c)]) : 0.0f;
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
-                    acc[bi][bj][e] = (r + e < M) ? -lp_to_f32<FMT>(C[(size_t)(r + e) + (size_t)c * ldc]) * inv
-                                                 : 0.0f;
+                    acc[bi][bj][e] = (in && r + e < M)
+                                         ? -lp_to_f32<FMT>(C[(size_t)(r + e) + (size_t)c * ldc]) * inv
+                                         : 0.0f;
             }
-        }
+    }
 
     const char *gA = reinterpret_cast<const char *>(Lq + (size_t)row0 * BK8) + wave * (SA / 4) + lane * 16;
     const char *gB = reinterpret_cast<const char *>(Uq + (size_t)col0 * BK8) + wave * (SB / 4) + lane * 16;
@@ -305,16 +323,16 @@ __global__ __launch_bounds__(256, 2) void lp_schur8_kernel(
         for (int bj = 0; bj < 4; ++bj) {
             const int64_t r = row0 + wm * 64 + bi * 16 + 4 * lg;
             const int64_t c = col0 + wn * 64 + bj * 16 + li;
-            if (c >= N || r >= M) continue;
-            const float sc = sL[tix(r)] * sU[tix(c)];
-            if (r + 3 < M) {
+            if (full) {
+                const float sc = sL[tix(r)] * sU[tix(c)];
                 uint2 v;
                 v.x = (uint32_t)f32_to_lp<FMT>(-acc[bi][bj][0] * sc) |
                       ((uint32_t)f32_to_lp<FMT>(-acc[bi][bj][1] * sc) << 16);
                 v.y = (uint32_t)f32_to_lp<FMT>(-acc[bi][bj][2] * sc) |
                       ((uint32_t)f32_to_lp<FMT>(-acc[bi][bj][3] * sc) << 16);
                 *reinterpret_cast<uint2 *>(&C[(size_t)r + (size_t)c * ldc]) = v;
-            } else {
+            } else if (r < M && c < N) {
+                const float sc = sL[tix(r)] * sU[tix(c)];
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
                     if (r + e < M)

@@ -131,6 +131,10 @@ int factor_impl(int64_t n, int64_t nb, double *A, int64_t lda, int32_t *ipiv, hi
     MXLU_TRY(alloc_panel_exchange(scratch, n, &ex, s));
     int *moves = scratch.alloc_n<int>(kSwapMovesInts);
     if (!moves) return MXLU_E_NOMEM;
+    // packed -U12^T for the trailing update (nb rows of up to n values)
+    const int64_t ldbn = (n + 1) / 2 * 2;
+    double *Bn = scratch.alloc_n<double>((size_t)nb * (size_t)ldbn);
+    if (!Bn) return MXLU_E_NOMEM;
 
     for (int64_t k0 = 0; k0 < n; k0 += nb) {
         const int64_t kb = std::min(nb, n - k0);
@@ -145,17 +149,22 @@ int factor_impl(int64_t n, int64_t nb, double *A, int64_t lda, int32_t *ipiv, hi
             MXLU_TRY(laswp_f64(A, lda, ipiv, k0, (int)kb, 0, n - kb, k0, kb, moves, s));
         }
         if (c1 < n) {
-            {   // DTRSM: U12 = L11^-1 A12
-                PhaseScope ph(kPhaseTrsm, s, (double)kb * (kb - 1) * (double)(n - c1));
-                MXLU_TRY(PanelOps<double>::trsm(kb, n - c1, &MXLU_AT(A, k0, k0, lda), lda,
-                                           &MXLU_AT(A, k0, c1, lda), lda, s));
+            const int64_t nt = n - c1;
+            double *L21 = &MXLU_AT(A, c1, k0, lda), *U12 = &MXLU_AT(A, k0, c1, lda);
+            const bool ring = gemm_f64_ring_ok(nt, nt, kb, L21, lda);
+            {   // DTRSM: U12 = L11^-1 A12 (then, for the ring kernel, -U12^T packed)
+                PhaseScope ph(kPhaseTrsm, s, (double)kb * (kb - 1) * (double)nt);
+                MXLU_TRY(PanelOps<double>::trsm(kb, nt, &MXLU_AT(A, k0, k0, lda), lda, U12, lda, s));
+                if (ring) MXLU_TRY(pack_neg_transpose_f64(kb, nt, U12, lda, Bn, ldbn, s));
             }
             {   // DGEMM: A22 -= L21 U12
-                const double mt = (double)(n - c1);
-                PhaseScope ph(kPhaseGemm, s, 2.0 * mt * mt * (double)kb);
-                MXLU_TRY(gemm_f64_sub(n - c1, n - c1, kb, &MXLU_AT(A, c1, k0, lda), lda,
-                                      &MXLU_AT(A, k0, c1, lda), lda, &MXLU_AT(A, c1, c1, lda),
-                                      lda, s, true));
+                PhaseScope ph(kPhaseGemm, s, 2.0 * (double)nt * (double)nt * (double)kb);
+                if (ring)
+                    MXLU_TRY(gemm_f64_ring(nt, nt, kb, L21, lda, Bn, ldbn, &MXLU_AT(A, c1, c1, lda),
+                                           lda, s));
+                else
+                    MXLU_TRY(gemm_f64_sub(nt, nt, kb, L21, lda, U12, lda, &MXLU_AT(A, c1, c1, lda),
+                                          lda, s, true));
             }
         }
     }
