@@ -105,7 +105,9 @@ def run_fp64(args, cfg):
     n, nb = cfg["n"], cfg["nb"]
     seed = inputs.config_seed(cfg["index"])
     total = args.warmup + args.steps
-    log(f"workload fp64 n={n} nb={nb}: generating {total} matrices in HBM")
+    api.set_lookahead(args.lookahead)
+    log(f"workload fp64 n={n} nb={nb} lookahead={args.lookahead}: "
+        f"generating {total} matrices in HBM")
     mats = []
     for _ in range(total):
         A = api.fortran_empty(n, n)
@@ -163,6 +165,7 @@ def run_fp64(args, cfg):
         "dtype": "f64",
         "config": {"workload": "fp64_lu_partial_pivoting_plus_solve", "n": n, "nb": nb,
                    "nrhs": 1, "matrix": "i.i.d. uniform[-0.5,0.5), column-major, lda=n",
+                   "lookahead": args.lookahead,
                    "peak_frac_f64_mfma": round(value / PEAK_TFLOPS["f64"], 4)},
         "roofline": roofline,
         "scaled_residual": rho,
@@ -297,6 +300,8 @@ def main():
     ap.add_argument("--workload", default="fp64_large",
                     choices=["fp64_large", "fp64_small", "bf16_ir", "fp8_ir"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--lookahead", type=int, default=1, choices=[0, 1],
+                    help="look-ahead depth of the FP64 factorization")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="run only a plain copy of this many bytes (counter calibration)")
     args = ap.parse_args()

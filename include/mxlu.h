@@ -60,6 +60,24 @@ int lu_factor(int64_t n, int64_t nb, double *A, int64_t lda, int32_t *ipiv,
               void *stream);
 
 /*
+ * mxlu_set_lookahead -- look-ahead depth of lu_factor (Sec. III-A.1 names
+ * look-ahead as the way to take the panel off the critical path; Sec. IV-B's
+ * configuration table runs HPL with depth 1).  Process-wide, default 1.
+ *   depth 0: each step runs PFACT, SWAP, DTRSM and DGEMM in order on the
+ *            caller's stream.
+ *   depth 1: the update of the next panel's columns runs first; that panel
+ *            is then factored on a stream masked to a quarter of the CUs
+ *            while the rest of the update runs on a stream masked to the
+ *            other CUs; both join the caller's stream before the next SWAP.
+ *            Used when n and nb are multiples of 128, lda is even, A is
+ *            16-byte aligned and n > nb; otherwise lu_factor runs depth 0.
+ * The factors and ipiv are the same at both depths (each element takes the
+ * same operations in the same order).  Returns 0, or -1 for a depth other
+ * than 0 or 1.
+ */
+int mxlu_set_lookahead(int depth);
+
+/*
  * lu_solve -- triangular solves with the factors of lu_factor (Sec. III-A.1).
  *   trans = 0: solves A X = B  (apply P, L y = P b, U x = y)
  *   trans = 1: solves A^T X = B (U^T y = b, L^T z = y, x = P^T z)

@@ -40,6 +40,7 @@ class MxpReport(ctypes.Structure):
 # name -> (restype, argtypes); exactly the functions declared in include/mxlu.h
 SIGNATURES = {
     "lu_factor": (_int, [_i64, _i64, _vp, _i64, _vp, _vp]),
+    "mxlu_set_lookahead": (_int, [_int]),
     "lu_solve": (_int, [_i64, _i64, _vp, _i64, _vp, _vp, _i64, _int, _vp]),
     "mxlu_schur_update_f64": (_int, [_i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp]),
     "mxlu_outer_update_f64": (_int, [_i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _int,

@@ -54,6 +54,11 @@ def _mat(t, name, dtype=torch.float64):
     return t.data_ptr(), rows, cols, ld
 
 
+def set_lookahead(depth):
+    """Look-ahead depth of lu_factor (0 or 1, process-wide; default 1)."""
+    check("mxlu_set_lookahead", lib().mxlu_set_lookahead(int(depth)))
+
+
 def lu_factor(A, nb=256, ipiv=None):
     """In-place blocked LU with partial pivoting.  Returns (A, ipiv, info)."""
     pa, n, n2, lda = _mat(A, "A")

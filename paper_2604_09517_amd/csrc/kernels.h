@@ -35,6 +35,7 @@ struct PanelExchange {
     uint64_t *slots;  // [2][kMaxGroups][4] candidates, then [2][kMaxGroups][kLeafW * 2] rows
     uint64_t *rowj;   // [2][kLeafW * 2] the current pivot row's old contents
     int *flags;       // [0]: first zero pivot (1-based), [1]: wait expired
+    int group_cap;    // most workgroups a leaf may launch (0: one per CU, about 64)
 };
 constexpr int kLeafW = 32;        // columns factored by one leaf kernel
 constexpr int kMaxGroups = 256;   // workgroups of one leaf kernel (<= CUs)
@@ -44,6 +45,10 @@ constexpr int kMaxGroups = 256;   // workgroups of one leaf kernel (<= CUs)
 // index within the caller's numbering: ipiv[r0 .. r0+w) receives r0 + the
 // pivot row within the leaf; the column numbers r0 + j + 1 are the values of
 // the workgroups' sequence flags, so they must grow from leaf to leaf.
+// Workgroups the leaf kernel launches for an m-row leaf with group cap `cap`
+// (they must all be resident at once), or -1 when no geometry fits.
+template <typename T> int panel_leaf_groups(int64_t m, int cap);
+
 template <typename T>
 int panel_leaf(int64_t m, int w, T *P, int64_t ldp, int64_t r0, int32_t *ipiv,
                const PanelExchange &ex, hipStream_t s);

@@ -6,9 +6,12 @@
 // updates inside the panel), SWAP of the panel's interchanges on the columns
 // left and right of it, DTRSM for the block row U12, and the MFMA DGEMM
 // trailing update A22 -= L21 U12.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <mutex>
 
 #include "common.h"
 #include "kernels.h"
@@ -112,6 +115,7 @@ int alloc_panel_exchange(Scratch &scratch, int64_t n, PanelExchange *ex, hipStre
     ex->slots = scratch.alloc_n<uint64_t>(slot_words);
     ex->rowj = scratch.alloc_n<uint64_t>(rowj_words);
     ex->flags = scratch.alloc_n<int>(4);
+    ex->group_cap = 0;
     (void)n;
     if (!ex->slots || !ex->rowj || !ex->flags) return MXLU_E_NOMEM;
     // sequence number 0 is never current: zeroed words never match
@@ -123,6 +127,139 @@ int alloc_panel_exchange(Scratch &scratch, int64_t n, PanelExchange *ex, hipStre
 }  // namespace mxlu
 
 namespace {
+
+// Look-ahead depth of lu_factor (0 or 1; Sec. IV-B runs HPL with depth 1).
+std::atomic<int> g_lookahead{1};
+
+// Streams of the depth-1 look-ahead: the next panel is factored on `panel`
+// while part of the trailing update runs on `update`.  Both carry a CU mask
+// so that the two never compete for a CU: the panel's leaf kernel needs all
+// of its workgroups resident at once, and it gets CUs that no update
+// workgroup holds.  The panel gets mask bits [0, cus/4): the KFD spreads
+// mask bits round-robin over the XCDs and then over the shader engines of
+// each, so these are the first two CUs of every shader engine (present
+// however the engines are harvested); a driver that numbers the bits
+// XCD-major would give it two whole XCDs instead, also cus/4 CUs.  Created
+// once per device with the default priority; kept for the life of the
+// process.
+struct OverlapStreams {
+    hipStream_t panel = nullptr, update = nullptr;
+    int panel_cus = 0, update_cus = 0;
+};
+
+const OverlapStreams *overlap_streams() {
+    constexpr int kMaxDev = 64;
+    static std::mutex mu;
+    static OverlapStreams per_dev[kMaxDev];
+    static bool tried[kMaxDev] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    if (!tried[dev]) {
+        tried[dev] = true;
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cus = 0;
+        if (cus >= 128 && cus <= 1024) {
+            uint32_t pm[32] = {}, um[32] = {};
+            const int np = cus / 4;
+            for (int i = 0; i < cus; ++i) (i < np ? pm : um)[i / 32] |= 1u << (i % 32);
+            const uint32_t words = (uint32_t)((cus + 31) / 32);
+            hipStream_t a = nullptr, b = nullptr;
+            if (hipExtStreamCreateWithCUMask(&a, words, pm) == hipSuccess &&
+                hipExtStreamCreateWithCUMask(&b, words, um) == hipSuccess) {
+                per_dev[dev] = {a, b, np, cus - np};
+            } else {
+                if (a) (void)hipStreamDestroy(a);
+                per_dev[dev] = {};
+            }
+        }
+        (void)hipGetLastError();
+    }
+    return per_dev[dev].panel ? &per_dev[dev] : nullptr;
+}
+
+// Joins the look-ahead streams back into the factorization stream when it
+// goes out of scope (also on an error return, so that no work of the call is
+// still running when its scratch memory is released).
+class ForkJoin {
+  public:
+    ForkJoin(hipStream_t s, const OverlapStreams *ov) : s_(s), ov_(ov) {}
+    ~ForkJoin() {
+        if (!active_) return;
+        (void)hipEventRecord(ev_[1], ov_->panel);
+        (void)hipStreamWaitEvent(s_, ev_[1], 0);
+        (void)hipEventRecord(ev_[2], ov_->update);
+        (void)hipStreamWaitEvent(s_, ev_[2], 0);
+        for (hipEvent_t e : ev_) (void)hipEventDestroy(e);
+    }
+    int create() {
+        for (hipEvent_t &e : ev_)
+            MXLU_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        active_ = true;
+        return 0;
+    }
+    // the look-ahead streams start after everything enqueued so far on s
+    int fork() {
+        MXLU_HIP_TRY(hipEventRecord(ev_[0], s_));
+        MXLU_HIP_TRY(hipStreamWaitEvent(ov_->panel, ev_[0], 0));
+        MXLU_HIP_TRY(hipStreamWaitEvent(ov_->update, ev_[0], 0));
+        return 0;
+    }
+    // s continues after everything enqueued so far on the panel stream
+    int join_panel() {
+        MXLU_HIP_TRY(hipEventRecord(ev_[1], ov_->panel));
+        MXLU_HIP_TRY(hipStreamWaitEvent(s_, ev_[1], 0));
+        return 0;
+    }
+    // s continues after everything enqueued so far on the update stream
+    int join_update() {
+        MXLU_HIP_TRY(hipEventRecord(ev_[2], ov_->update));
+        MXLU_HIP_TRY(hipStreamWaitEvent(s_, ev_[2], 0));
+        return 0;
+    }
+
+  private:
+    hipStream_t s_;
+    const OverlapStreams *ov_;
+    hipEvent_t ev_[3] = {};
+    bool active_ = false;
+};
+
+// Leaf workgroups allowed on the panel stream: 7/8 of its CUs, so that a
+// leaf still fits when a few of them are unavailable.
+int lookahead_group_cap(const OverlapStreams *ov) { return ov->panel_cus * 7 / 8; }
+
+// Depth-1 look-ahead applies when every trailing update can be split at the
+// next panel's columns into ring-kernel updates (sizes multiples of 128) and
+// the tallest panel's leaf fits on the panel stream's CUs.
+bool lookahead_fits(int64_t n, int64_t nb, const double *A, int64_t lda,
+                    const OverlapStreams *ov) {
+    if (!ov || nb % 128 != 0 || n % 128 != 0 || n <= nb) return false;
+    if (!gemm_f64_ring_ok(n - nb, n - nb, nb, A, lda)) return false;
+    const int g = panel_leaf_groups<double>(n - nb, lookahead_group_cap(ov));
+    (void)hipGetLastError();
+    clear_error();
+    return g > 0;
+}
+
+// Columns of the remaining update given to the update stream while the next
+// panel is factored: about 1.5x what its CUs finish in the panel's expected
+// time (the leaves take ~7 us per column, the update kernel ~0.19 TFLOP/s per
+// CU).  The rest runs on all CUs once the panel is done, alongside the tail
+// of this part, so erring high costs little and erring low leaves the update
+// CUs idle until the panel ends.
+int64_t lookahead_split(int64_t nt, int64_t kb, int64_t kb1, const OverlapStreams *ov) {
+    constexpr double kPanelSecPerCol = 7.0e-6, kUpdateFlopsPerCu = 1.9e11;
+    const double flops = 1.5 * kPanelSecPerCol * (double)kb1 * kUpdateFlopsPerCu * ov->update_cus;
+    const int64_t rest = nt - kb1;
+    int64_t n1 = (int64_t)(flops / (2.0 * (double)nt * (double)kb));
+    n1 = (n1 + 127) / 128 * 128;
+    return std::min(rest, std::max<int64_t>(128, n1));
+}
 
 int factor_impl(int64_t n, int64_t nb, double *A, int64_t lda, int32_t *ipiv, hipStream_t s,
                 int *info_out) {
@@ -136,37 +273,80 @@ int factor_impl(int64_t n, int64_t nb, double *A, int64_t lda, int32_t *ipiv, hi
     double *Bn = scratch.alloc_n<double>((size_t)nb * (size_t)ldbn);
     if (!Bn) return MXLU_E_NOMEM;
 
+    const OverlapStreams *ov =
+        g_lookahead.load() > 0 ? overlap_streams() : nullptr;
+    const bool la = lookahead_fits(n, nb, A, lda, ov);
+    ForkJoin fj(s, ov);
+    if (la) {
+        MXLU_TRY(fj.create());
+        ex.group_cap = lookahead_group_cap(ov);
+    }
+
+    bool ahead = false;  // the current panel was factored during the previous update
     for (int64_t k0 = 0; k0 < n; k0 += nb) {
         const int64_t kb = std::min(nb, n - k0);
         const int64_t m = n - k0, c1 = k0 + kb;
-        {   // PFACT
+        if (!ahead) {   // PFACT
             PhaseScope ph(kPhasePfact, s, (double)m * kb * 8.0);
             MXLU_TRY(panel_factor<double>(&MXLU_AT(A, k0, k0, lda), lda, m, kb, k0, ipiv, ex, moves,
                                      s));
         }
+        ahead = false;
         {   // SWAP on the columns left and right of the panel
             PhaseScope ph(kPhaseSwap, s, 32.0 * kb * (double)(n - kb));
             MXLU_TRY(laswp_f64(A, lda, ipiv, k0, (int)kb, 0, n - kb, k0, kb, moves, s));
         }
-        if (c1 < n) {
-            const int64_t nt = n - c1;
-            double *L21 = &MXLU_AT(A, c1, k0, lda), *U12 = &MXLU_AT(A, k0, c1, lda);
-            const bool ring = gemm_f64_ring_ok(nt, nt, kb, L21, lda);
-            {   // DTRSM: U12 = L11^-1 A12 (then, for the ring kernel, -U12^T packed)
-                PhaseScope ph(kPhaseTrsm, s, (double)kb * (kb - 1) * (double)nt);
-                MXLU_TRY(PanelOps<double>::trsm(kb, nt, &MXLU_AT(A, k0, k0, lda), lda, U12, lda, s));
-                if (ring) MXLU_TRY(pack_neg_transpose_f64(kb, nt, U12, lda, Bn, ldbn, s));
-            }
-            {   // DGEMM: A22 -= L21 U12
-                PhaseScope ph(kPhaseGemm, s, 2.0 * (double)nt * (double)nt * (double)kb);
-                if (ring)
-                    MXLU_TRY(gemm_f64_ring(nt, nt, kb, L21, lda, Bn, ldbn, &MXLU_AT(A, c1, c1, lda),
-                                           lda, s));
-                else
-                    MXLU_TRY(gemm_f64_sub(nt, nt, kb, L21, lda, U12, lda, &MXLU_AT(A, c1, c1, lda),
-                                          lda, s, true));
-            }
+        if (c1 >= n) continue;
+        const int64_t nt = n - c1;
+        double *L21 = &MXLU_AT(A, c1, k0, lda), *U12 = &MXLU_AT(A, k0, c1, lda);
+        const bool ring = la || gemm_f64_ring_ok(nt, nt, kb, L21, lda);
+        {   // DTRSM: U12 = L11^-1 A12 (then, for the ring kernel, -U12^T packed)
+            PhaseScope ph(kPhaseTrsm, s, (double)kb * (kb - 1) * (double)nt);
+            MXLU_TRY(PanelOps<double>::trsm(kb, nt, &MXLU_AT(A, k0, k0, lda), lda, U12, lda, s));
+            if (ring) MXLU_TRY(pack_neg_transpose_f64(kb, nt, U12, lda, Bn, ldbn, s));
         }
+        if (!la) {   // DGEMM: A22 -= L21 U12
+            PhaseScope ph(kPhaseGemm, s, 2.0 * (double)nt * (double)nt * (double)kb);
+            if (ring)
+                MXLU_TRY(gemm_f64_ring(nt, nt, kb, L21, lda, Bn, ldbn, &MXLU_AT(A, c1, c1, lda),
+                                       lda, s));
+            else
+                MXLU_TRY(gemm_f64_sub(nt, nt, kb, L21, lda, U12, lda, &MXLU_AT(A, c1, c1, lda),
+                                      lda, s, true));
+            continue;
+        }
+        // Look-ahead: update the next panel's columns first, then factor that
+        // panel on the panel stream while the update stream takes the next n1
+        // columns; the remaining columns follow on all CUs once the panel is
+        // done.  The three updates and the panel touch disjoint columns of A;
+        // the next SWAP (which reads them all) waits for all of them.
+        const int64_t kb1 = std::min(nb, nt);
+        {
+            PhaseScope ph(kPhaseGemm, s, 2.0 * (double)nt * (double)kb1 * (double)kb);
+            MXLU_TRY(gemm_f64_ring(nt, kb1, kb, L21, lda, Bn, ldbn, &MXLU_AT(A, c1, c1, lda), lda,
+                                   s));
+        }
+        MXLU_TRY(fj.fork());
+        {
+            PhaseScope ph(kPhasePfact, ov->panel, (double)nt * kb1 * 8.0);
+            MXLU_TRY(panel_factor<double>(&MXLU_AT(A, c1, c1, lda), lda, nt, kb1, c1, ipiv, ex,
+                                     moves, ov->panel));
+        }
+        const int64_t n1 = nt > kb1 ? lookahead_split(nt, kb, kb1, ov) : 0;
+        if (n1 > 0) {
+            PhaseScope ph(kPhaseGemm, ov->update, 2.0 * (double)nt * (double)n1 * (double)kb);
+            MXLU_TRY(gemm_f64_ring(nt, n1, kb, L21, lda, Bn + kb1, ldbn,
+                                   &MXLU_AT(A, c1, c1 + kb1, lda), lda, ov->update));
+        }
+        MXLU_TRY(fj.join_panel());
+        const int64_t n2 = nt - kb1 - n1, j2 = kb1 + n1;
+        if (n2 > 0) {
+            PhaseScope ph(kPhaseGemm, s, 2.0 * (double)nt * (double)n2 * (double)kb);
+            MXLU_TRY(gemm_f64_ring(nt, n2, kb, L21, lda, Bn + j2, ldbn,
+                                   &MXLU_AT(A, c1, c1 + j2, lda), lda, s));
+        }
+        MXLU_TRY(fj.join_update());
+        ahead = true;
     }
     int flags[4] = {0, 0, 0, 0};
     MXLU_HIP_TRY(hipMemcpyAsync(flags, ex.flags, sizeof(flags), hipMemcpyDeviceToHost, s));
@@ -180,6 +360,12 @@ int factor_impl(int64_t n, int64_t nb, double *A, int64_t lda, int32_t *ipiv, hi
 }
 
 }  // namespace
+
+extern "C" int mxlu_set_lookahead(int depth) {
+    if (depth < 0 || depth > 1) return -1;
+    g_lookahead.store(depth);
+    return 0;
+}
 
 extern "C" int lu_factor(int64_t n, int64_t nb, double *A, int64_t lda, int32_t *ipiv,
                          void *stream) {

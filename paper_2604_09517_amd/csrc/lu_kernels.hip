@@ -98,11 +98,17 @@ __device__ __forceinline__ uint32_t ll_wait(const uint64_t *p, uint64_t x, uint3
                                            int *flags) {
     long spins = 0;
     while ((uint32_t)(x >> 32) != seq) {
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins > (1L << 26)) {
-            atomicExch(&flags[1], 1);
-            break;
+        if ((spins & 1023) == 0) {
+            // once any wait has expired the results are invalid: later waits
+            // give up at their first check instead of spinning
+            if (__hip_atomic_load(&flags[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+            if (spins > (1L << 22)) {
+                atomicExch(&flags[1], 1);
+                break;
+            }
         }
+        ++spins;
+        __builtin_amdgcn_s_sleep(1);
         x = ll_load(p);
     }
     return (uint32_t)x;
@@ -577,6 +583,50 @@ static int max_dynamic_lds() {
     return cached;
 }
 
+// Rows per workgroup (R) and workgroups (G) of the leaf kernel for an m-row
+// leaf, and the dynamic LDS budget.  The dynamic LDS holds the group's rows of
+// the leaf (the static part holds the gathered words): about `cap` groups
+// (64 when cap is 0) of at least 256 rows, more groups when LDS is short.
+// Returns 0, or MXLU_E_NOMEM when the panel cannot be held by co-resident
+// workgroups (at most `cap` of them when cap > 0, else at most one per CU).
+template <typename T>
+static int leaf_geometry(int64_t m, int cap, int64_t *R_out, int64_t *G_out,
+                         int64_t *budget_out) {
+    static int64_t static_lds = -1;
+    if (static_lds < 0) {
+        hipFuncAttributes fa;
+        MXLU_HIP_TRY(hipFuncGetAttributes(&fa, (const void *)panel_leaf_kernel<T>));
+        static_lds = (int64_t)fa.sharedSizeBytes;
+    }
+    const int64_t budget = max_dynamic_lds() - static_lds;
+    const int64_t target = cap > 0 ? cap : 64;
+    int64_t R = std::max<int64_t>(256, (m + target - 1) / target);
+    int64_t G = (m + R - 1) / R;
+    auto need = [&](int64_t r) { return (int64_t)sizeof(T) * kLeafW * r; };
+    while (need(R) > budget && G < kMaxGroups) {
+        R = std::max<int64_t>(64, (R * 7) / 8);
+        G = (m + R - 1) / R;
+    }
+    if (G > kMaxGroups || G > compute_units() || (cap > 0 && G > cap) || need(R) > budget) {
+        set_error_msg("panel_leaf: panel too tall for the LDS of the device");
+        return MXLU_E_NOMEM;
+    }
+    *R_out = R;
+    *G_out = G;
+    *budget_out = budget;
+    return 0;
+}
+
+template <typename T>
+int panel_leaf_groups(int64_t m, int cap) {
+    int64_t R = 0, G = 0, budget = 0;
+    if (m <= 0) return 0;
+    if (m > 0x7fffffff || leaf_geometry<T>(m, cap, &R, &G, &budget)) return -1;
+    return (int)G;
+}
+template int panel_leaf_groups<double>(int64_t, int);
+template int panel_leaf_groups<float>(int64_t, int);
+
 template <typename T>
 int panel_leaf(int64_t m, int w, T *P, int64_t ldp, int64_t r0, int32_t *ipiv,
                const PanelExchange &ex, hipStream_t s) {
@@ -585,28 +635,9 @@ int panel_leaf(int64_t m, int w, T *P, int64_t ldp, int64_t r0, int32_t *ipiv,
         set_error_msg("panel_leaf: bad shape");
         return MXLU_E_NOMEM;
     }
-    // dynamic LDS: the group's rows of the leaf (the static part holds the
-    // gathered words); about 64 groups of at least 256 rows, more groups when
-    // LDS is short
-    static int64_t static_lds = -1;
-    if (static_lds < 0) {
-        hipFuncAttributes fa;
-        MXLU_HIP_TRY(hipFuncGetAttributes(&fa, (const void *)panel_leaf_kernel<T>));
-        static_lds = (int64_t)fa.sharedSizeBytes;
-    }
-    const int64_t budget = max_dynamic_lds() - static_lds;
-    int64_t R = std::max<int64_t>(256, (m + 63) / 64);
-    int64_t G = (m + R - 1) / R;
-    auto need = [&](int64_t r) { return (int64_t)sizeof(T) * kLeafW * r; };
-    while (need(R) > budget && G < kMaxGroups) {
-        R = std::max<int64_t>(64, (R * 7) / 8);
-        G = (m + R - 1) / R;
-    }
-    if (G > kMaxGroups || G > compute_units() || need(R) > budget) {
-        set_error_msg("panel_leaf: panel too tall for the LDS of the device");
-        return MXLU_E_NOMEM;
-    }
-    const size_t lds = (size_t)need(R);
+    int64_t R = 0, G = 0, budget = 0;
+    MXLU_TRY(leaf_geometry<T>(m, ex.group_cap, &R, &G, &budget));
+    const size_t lds = (size_t)sizeof(T) * kLeafW * R;
     static bool attr_set = false;
     if (!attr_set) {
         MXLU_HIP_TRY(hipFuncSetAttribute((const void *)panel_leaf_kernel<T>,

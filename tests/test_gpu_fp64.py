@@ -136,6 +136,45 @@ def test_lu_factor_matches_oracle(api, n, nb):
         assert np.abs(LU - LU_ref).max() <= 1e-9 * scale
 
 
+# Sizes where depth-1 look-ahead applies (n, nb multiples of 128): the next
+# panel is factored on its own CU-masked stream while the rest of the update
+# runs on another.  Each element takes the same operations in the same order
+# as at depth 0, so the factors must agree bit for bit.
+LOOKAHEAD_CASES = [(1024, 128), (1152, 256), (2048, 256), (2560, 512)]
+
+
+@pytest.mark.parametrize("n,nb", LOOKAHEAD_CASES)
+def test_lookahead_matches_depth0_and_oracle(api, n, nb):
+    note(f"lookahead n={n} nb={nb}")
+    seed = inputs.config_seed(0) + 7 * n + nb
+    A_h = inputs.uniform_matrix(seed, 0, n, n)
+    out = {}
+    try:
+        for depth in (0, 1):
+            api.set_lookahead(depth)
+            dA = to_dev(A_h)
+            _, ipiv, info = api.lu_factor(dA, nb)
+            torch.cuda.synchronize()
+            out[depth] = (dA.cpu().numpy(), ipiv.cpu().numpy(), info)
+    finally:
+        api.set_lookahead(1)
+    (LU0, piv0, info0), (LU1, piv1, info1) = out[0], out[1]
+    assert info0 == info1 == 0
+    assert np.array_equal(piv0, piv1)
+    assert np.array_equal(LU0, LU1)
+    LU_ref, piv_ref, _ = oracle.getrf(A_h, nb)
+    same = assert_pivots_match(A_h, piv1, piv_ref)
+    assert checks.factorization_ratio(A_h, LU1, piv1) < 10
+    if same:
+        assert np.abs(LU1 - LU_ref).max() <= 1e-9 * max(1.0, np.abs(LU_ref).max())
+
+
+def test_lookahead_depth_argument(api):
+    assert api.lib().mxlu_set_lookahead(2) == -1
+    assert api.lib().mxlu_set_lookahead(-1) == -1
+    assert api.lib().mxlu_set_lookahead(1) == 0
+
+
 def test_lu_factor_c1_configuration(api):
     """The small configuration (n = 1024, NB = 64, device-generated input)."""
     n, nb = 1024, 64
