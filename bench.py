@@ -152,7 +152,7 @@ def run_fp64(args, cfg):
     roofline = {
         "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["f64"],
         "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["f64"], 4),
-        "traffic": traffic, "kernel": "gemm_f64_ring_kernel (trailing update)",
+        "traffic": traffic, "kernel": "gemm_f64_direct_kernel (trailing update)",
         "launches": gcnt, "avg_launch_ms": round(gms / max(1, gcnt), 4),
     }
     phases = {p: round(v[0] / args.steps, 3) for p, v in prof.items() if v[2] > 0}

@@ -164,97 +164,99 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_sub_kernel(
 }
 
 // Trailing update of the factorization, full tiles only: C -= A B with the
-// same 128 x 128 tile and wave layout as above, but both operands are copied
-// into an LDS ring of kRing stages (K chunks of 8) with 16-byte direct
-// global->LDS loads, so no registers stage them and two chunks are in flight
-// during the MFMAs of the current one (one barrier per chunk).  A is read
-// from the column-major matrix (one 1 KB load per k column of a tile); B is
-// read from Bn, a packed copy of -B^T (row k holds -B[k][0 .. N), leading
-// dimension ldbn), so the product needs no negation.
-constexpr int kRingBK = 8, kRing = 3;
-constexpr int kRingSA = kRingBK * AST, kRingSB = kRingBK * BST;   // doubles per stage
+// same 128 x 128 tile and 2 x 2 wave arrangement as above, but with no LDS
+// and no barrier: every wave loads its own operand fragments straight into
+// registers with 16-byte loads, kDirectSets chunks of 4 k deep (three in
+// flight while the MFMAs consume the fourth), so the four waves of a tile
+// never wait for each other.  B is read from Bn, a packed copy of -B^T (row k
+// holds -B[k][0 .. N), leading dimension ldbn), so the product needs no
+// negation and a fragment of 2 adjacent columns is one 16-byte load.
+//
+// A 16-byte load gives a lane two adjacent rows of A (or columns of Bn), so
+// the MFMA row index i' of fragment pair p, half h stands for tile row
+// 32 p + 2 i' + h of the wave's 64 (columns likewise): lane (li, lq) loads
+// A rows wm*64 + 32p + 2li + {0, 1} and Bn columns wn*64 + 32p + 2li + {0, 1}
+// at k = 4 kc + lq.  MFMA (a, b) with a = 2 pa + ha, b = 2 pb + hb leaves in
+// accumulator register r of lane (li, lq) the element at tile row
+// wm*64 + 32 pa + 2 (lq + 4 r) + ha and tile column wn*64 + 32 pb + 2 li + hb,
+// so C moves as 16-byte pairs of rows too.  Every element still takes its
+// k terms in ascending groups of 4, starting from C, as in the LDS kernel.
+constexpr int kDirectSets = 4, kDirectK = 4 * kDirectSets;
+typedef double v2d __attribute__((ext_vector_type(2)));
 
-typedef __attribute__((address_space(1))) void gvoid_t;
-typedef __attribute__((address_space(3))) void lvoid_t;
-
-__global__ __launch_bounds__(256, 2) void gemm_f64_ring_kernel(
+__global__ __launch_bounds__(256, 2) void gemm_f64_direct_kernel(
     int64_t M, int64_t N, int64_t K, const double *__restrict__ A, int64_t lda,
     const double *__restrict__ Bn, int64_t ldbn, double *__restrict__ C, int64_t ldc,
     int tiles_m, int tiles_n) {
-    __shared__ __attribute__((aligned(1024))) double ring[kRing][kRingSA + kRingSB];
-
     int tm, tn;
     tile_of(blockIdx.x, tiles_m, tiles_n, tm, tn);
-    const int64_t row0 = (int64_t)tm * BM;
-    const int64_t col0 = (int64_t)tn * BN;
-    const int tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
-    const int wm = wave & 1, wn = wave >> 1;
+    const int64_t row0 = (int64_t)tm * BM + ((threadIdx.x >> 6) & 1) * 64;
+    const int64_t col0 = (int64_t)tn * BN + (threadIdx.x >> 7) * 64;
+    const int lane = threadIdx.x & 63;
     const int li = lane & 15, lq = lane >> 4;
 
     v4d acc[4][4];
 #pragma unroll
-    for (int bi = 0; bi < 4; ++bi)
+    for (int pa = 0; pa < 2; ++pa)
 #pragma unroll
-        for (int bj = 0; bj < 4; ++bj) {
-            const int64_t r = row0 + wm * 64 + bi * 16 + lq;
-            const int64_t c = col0 + wn * 64 + bj * 16 + li;
+        for (int b = 0; b < 4; ++b) {
+            const int64_t c = col0 + 32 * (b >> 1) + 2 * li + (b & 1);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) acc[bi][bj][e] = MXLU_AT(C, r + 4 * e, c, ldc);
+            for (int r = 0; r < 4; ++r) {
+                const v2d v = *(const v2d *)&MXLU_AT(C, row0 + 32 * pa + 2 * (lq + 4 * r), c, ldc);
+                acc[2 * pa][b][r] = v.x;
+                acc[2 * pa + 1][b][r] = v.y;
+            }
         }
 
-    // wave w copies k rows 2w and 2w + 1 of a chunk: 128 values of A's
-    // column and 128 values of Bn's row each (64 lanes x 16 bytes)
-    auto issue = [&](int kc, int st) {
+    const double *Ab = &MXLU_AT(A, row0 + 2 * li, lq, lda);
+    const double *Bb = Bn + (size_t)lq * ldbn + col0 + 2 * li;
+    const int nk = (int)(K / 4);
+    v2d fa[kDirectSets][2], fb[kDirectSets][2];
+    // chunks past the end reload the last one (never consumed), so that every
+    // step issues the same loads and the wait before each step is the same
+    auto load = [&](int kc, v2d (&xa)[2], v2d (&xb)[2]) {
+        const int64_t k = (int64_t)4 * min(kc, nk - 1);
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int r = 2 * wave + h;
-            const int64_t k = (int64_t)kc * kRingBK + r;
-            __builtin_amdgcn_global_load_lds((gvoid_t *)&MXLU_AT(A, row0 + 2 * lane, k, lda),
-                                             (lvoid_t *)&ring[st][r * AST], 16, 0, 0);
-            __builtin_amdgcn_global_load_lds((gvoid_t *)&Bn[(size_t)k * ldbn + col0 + 2 * lane],
-                                             (lvoid_t *)&ring[st][kRingSA + r * BST], 16, 0, 0);
+        for (int p = 0; p < 2; ++p) {
+            xa[p] = *(const v2d *)(Ab + 32 * p + k * lda);
+            xb[p] = *(const v2d *)(Bb + 32 * p + k * ldbn);
         }
     };
-
-    const int nk = (int)(K / kRingBK);
 #pragma unroll
-    for (int c = 0; c < kRing - 1; ++c)
-        if (c < nk) issue(c, c);
-    for (int kt = 0; kt < nk; ++kt) {
-        // chunk kt has landed once the loads of the chunk issued after it (4
-        // per wave) are the only ones outstanding; the C loads came first
-        static_assert(kRing == 3, "the wait below assumes three stages");
-        if (kt + 1 < nk) __builtin_amdgcn_s_waitcnt(0x0F70 | 4);   // vmcnt(4)
-        else __builtin_amdgcn_s_waitcnt(0x0F70);                   // vmcnt(0)
-        __syncthreads();   // every wave's part of chunk kt; stage (kt - 1) % 3 free
-        if (kt + kRing - 1 < nk) issue(kt + kRing - 1, (kt + kRing - 1) % kRing);
-        const double *as = &ring[kt % kRing][0];
-        const double *bs = &ring[kt % kRing][kRingSA];
+    for (int st = 0; st < kDirectSets - 1; ++st) load(st, fa[st], fb[st]);
+    // the scheduling barriers keep each prefetch where it is written: left
+    // alone, the scheduler sinks the loads next to their use
+    __builtin_amdgcn_sched_barrier(0);
+    for (int kt0 = 0; kt0 < nk; kt0 += kDirectSets) {
 #pragma unroll
-        for (int kk = 0; kk < kRingBK; kk += 4) {
-            double a[4], b[4];
+        for (int u = 0; u < kDirectSets; ++u) {
+            constexpr int D = kDirectSets;
+            load(kt0 + u + D - 1, fa[(u + D - 1) % D], fb[(u + D - 1) % D]);
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int bi = 0; bi < 4; ++bi) a[bi] = as[(kk + lq) * AST + wm * 64 + bi * 16 + li];
+            for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int bj = 0; bj < 4; ++bj) b[bj] = bs[(kk + lq) * BST + wn * 64 + bj * 16 + li];
-#pragma unroll
-            for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-                for (int bj = 0; bj < 4; ++bj)
-                    acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], acc[bi][bj],
-                                                                       0, 0, 0);
+                for (int b = 0; b < 4; ++b) {
+                    const double av = (a & 1) ? fa[u][a >> 1].y : fa[u][a >> 1].x;
+                    const double bv = (b & 1) ? fb[u][b >> 1].y : fb[u][b >> 1].x;
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[a][b], 0, 0, 0);
+                }
         }
     }
 
 #pragma unroll
-    for (int bi = 0; bi < 4; ++bi)
+    for (int pa = 0; pa < 2; ++pa)
 #pragma unroll
-        for (int bj = 0; bj < 4; ++bj) {
-            const int64_t r = row0 + wm * 64 + bi * 16 + lq;
-            const int64_t c = col0 + wn * 64 + bj * 16 + li;
+        for (int b = 0; b < 4; ++b) {
+            const int64_t c = col0 + 32 * (b >> 1) + 2 * li + (b & 1);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) MXLU_AT(C, r + 4 * e, c, ldc) = acc[bi][bj][e];
+            for (int r = 0; r < 4; ++r) {
+                v2d v;
+                v.x = acc[2 * pa][b][r];
+                v.y = acc[2 * pa + 1][b][r];
+                *(v2d *)&MXLU_AT(C, row0 + 32 * pa + 2 * (lq + 4 * r), c, ldc) = v;
+            }
         }
 }
 
@@ -353,8 +355,8 @@ int gemm_f64_sub(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
     return 0;
 }
 
-bool gemm_f64_ring_ok(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda) {
-    return M > 0 && N > 0 && K > 0 && M % BM == 0 && N % BN == 0 && K % kRingBK == 0 &&
+bool gemm_f64_update_ok(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda) {
+    return M > 0 && N > 0 && K > 0 && M % BM == 0 && N % BN == 0 && K % kDirectK == 0 &&
            lda % 2 == 0 && ((uintptr_t)A % 16) == 0;
 }
 
@@ -372,20 +374,21 @@ int pack_neg_transpose_f64(int64_t K, int64_t N, const double *B, int64_t ldb, d
     return 0;
 }
 
-int gemm_f64_ring(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
-                  const double *Bn, int64_t ldbn, double *C, int64_t ldc, hipStream_t s) {
+int gemm_f64_update(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
+                    const double *Bn, int64_t ldbn, double *C, int64_t ldc, hipStream_t s) {
     if (M <= 0 || N <= 0 || K <= 0) return 0;
-    if (!gemm_f64_ring_ok(M, N, K, A, lda) || !Bn || ldbn < N || ldbn % 2 || (uintptr_t)Bn % 16) {
-        set_error_msg("gemm_f64_ring: shape, leading dimension or alignment not supported");
+    if (!gemm_f64_update_ok(M, N, K, A, lda) || !Bn || ldbn < N || ldbn % 2 ||
+        (uintptr_t)Bn % 16 || !C || ldc % 2 || (uintptr_t)C % 16) {
+        set_error_msg("gemm_f64_update: shape, leading dimension or alignment not supported");
         return MXLU_E_NOMEM;
     }
     const int64_t tiles_m = M / BM, tiles_n = N / BN;
     if (tiles_m * tiles_n > 0x7fffffff) {
-        set_error_msg("gemm_f64_ring: grid too large");
+        set_error_msg("gemm_f64_update: grid too large");
         return MXLU_E_NOMEM;
     }
-    hipLaunchKernelGGL(gemm_f64_ring_kernel, dim3((unsigned)(tiles_m * tiles_n)), dim3(256), 0, s,
-                       M, N, K, A, lda, Bn, ldbn, C, ldc, (int)tiles_m, (int)tiles_n);
+    hipLaunchKernelGGL(gemm_f64_direct_kernel, dim3((unsigned)(tiles_m * tiles_n)), dim3(256), 0,
+                       s, M, N, K, A, lda, Bn, ldbn, C, ldc, (int)tiles_m, (int)tiles_n);
     MXLU_LAUNCH_CHECK();
     return 0;
 }

@@ -15,16 +15,16 @@ int gemm_f64_sub(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
                  const double *B, int64_t ldb, double *C, int64_t ldc, hipStream_t s,
                  bool trailing = false);
 // C(M x N) = (accumulate ? C : 0) - A(M x K) * B(N x K)^T.
-// The trailing update A22 -= L21 U12 of the factorization with the LDS-ring
-// kernel: full 128 x 128 tiles, K % 8 == 0, lda even and A 16-byte aligned
-// (gemm_f64_ring_ok); B comes as Bn = -U12^T, row-major with leading
-// dimension ldbn >= N (even, 16-byte aligned), written by
-// pack_neg_transpose_f64.
-bool gemm_f64_ring_ok(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda);
+// The trailing update A22 -= L21 U12 of the factorization with the
+// register-direct kernel: full 128 x 128 tiles, K % 16 == 0, lda even and A
+// 16-byte aligned (gemm_f64_update_ok; C must also be 16-byte aligned with
+// ldc even); B comes as Bn = -U12^T, row-major with leading dimension
+// ldbn >= N (even, 16-byte aligned), written by pack_neg_transpose_f64.
+bool gemm_f64_update_ok(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda);
 int pack_neg_transpose_f64(int64_t K, int64_t N, const double *B, int64_t ldb, double *Bn,
                            int64_t ldbn, hipStream_t s);
-int gemm_f64_ring(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
-                  const double *Bn, int64_t ldbn, double *C, int64_t ldc, hipStream_t s);
+int gemm_f64_update(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
+                    const double *Bn, int64_t ldbn, double *C, int64_t ldc, hipStream_t s);
 int gemm_f64_nt_sub(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
                     const double *B, int64_t ldb, double *C, int64_t ldc, bool accumulate,
                     hipStream_t s);

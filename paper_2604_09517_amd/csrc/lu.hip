@@ -234,12 +234,12 @@ class ForkJoin {
 int lookahead_group_cap(const OverlapStreams *ov) { return ov->panel_cus * 7 / 8; }
 
 // Depth-1 look-ahead applies when every trailing update can be split at the
-// next panel's columns into ring-kernel updates (sizes multiples of 128) and
+// next panel's columns into direct-kernel updates (sizes multiples of 128) and
 // the tallest panel's leaf fits on the panel stream's CUs.
 bool lookahead_fits(int64_t n, int64_t nb, const double *A, int64_t lda,
                     const OverlapStreams *ov) {
     if (!ov || nb % 128 != 0 || n % 128 != 0 || n <= nb) return false;
-    if (!gemm_f64_ring_ok(n - nb, n - nb, nb, A, lda)) return false;
+    if (!gemm_f64_update_ok(n - nb, n - nb, nb, A, lda)) return false;
     const int g = panel_leaf_groups<double>(n - nb, lookahead_group_cap(ov));
     (void)hipGetLastError();
     clear_error();
@@ -248,12 +248,12 @@ bool lookahead_fits(int64_t n, int64_t nb, const double *A, int64_t lda,
 
 // Columns of the remaining update given to the update stream while the next
 // panel is factored: about 1.5x what its CUs finish in the panel's expected
-// time (the leaves take ~7 us per column, the update kernel ~0.19 TFLOP/s per
+// time (the leaves take ~7 us per column, the update kernel ~0.24 TFLOP/s per
 // CU).  The rest runs on all CUs once the panel is done, alongside the tail
 // of this part, so erring high costs little and erring low leaves the update
 // CUs idle until the panel ends.
 int64_t lookahead_split(int64_t nt, int64_t kb, int64_t kb1, const OverlapStreams *ov) {
-    constexpr double kPanelSecPerCol = 7.0e-6, kUpdateFlopsPerCu = 1.9e11;
+    constexpr double kPanelSecPerCol = 7.0e-6, kUpdateFlopsPerCu = 2.4e11;
     const double flops = 1.5 * kPanelSecPerCol * (double)kb1 * kUpdateFlopsPerCu * ov->update_cus;
     const int64_t rest = nt - kb1;
     int64_t n1 = (int64_t)(flops / (2.0 * (double)nt * (double)kb));
@@ -299,16 +299,16 @@ int factor_impl(int64_t n, int64_t nb, double *A, int64_t lda, int32_t *ipiv, hi
         if (c1 >= n) continue;
         const int64_t nt = n - c1;
         double *L21 = &MXLU_AT(A, c1, k0, lda), *U12 = &MXLU_AT(A, k0, c1, lda);
-        const bool ring = la || gemm_f64_ring_ok(nt, nt, kb, L21, lda);
-        {   // DTRSM: U12 = L11^-1 A12 (then, for the ring kernel, -U12^T packed)
+        const bool direct = la || gemm_f64_update_ok(nt, nt, kb, L21, lda);
+        {   // DTRSM: U12 = L11^-1 A12 (then, for the direct kernel, -U12^T packed)
             PhaseScope ph(kPhaseTrsm, s, (double)kb * (kb - 1) * (double)nt);
             MXLU_TRY(PanelOps<double>::trsm(kb, nt, &MXLU_AT(A, k0, k0, lda), lda, U12, lda, s));
-            if (ring) MXLU_TRY(pack_neg_transpose_f64(kb, nt, U12, lda, Bn, ldbn, s));
+            if (direct) MXLU_TRY(pack_neg_transpose_f64(kb, nt, U12, lda, Bn, ldbn, s));
         }
         if (!la) {   // DGEMM: A22 -= L21 U12
             PhaseScope ph(kPhaseGemm, s, 2.0 * (double)nt * (double)nt * (double)kb);
-            if (ring)
-                MXLU_TRY(gemm_f64_ring(nt, nt, kb, L21, lda, Bn, ldbn, &MXLU_AT(A, c1, c1, lda),
+            if (direct)
+                MXLU_TRY(gemm_f64_update(nt, nt, kb, L21, lda, Bn, ldbn, &MXLU_AT(A, c1, c1, lda),
                                        lda, s));
             else
                 MXLU_TRY(gemm_f64_sub(nt, nt, kb, L21, lda, U12, lda, &MXLU_AT(A, c1, c1, lda),
@@ -323,7 +323,7 @@ int factor_impl(int64_t n, int64_t nb, double *A, int64_t lda, int32_t *ipiv, hi
         const int64_t kb1 = std::min(nb, nt);
         {
             PhaseScope ph(kPhaseGemm, s, 2.0 * (double)nt * (double)kb1 * (double)kb);
-            MXLU_TRY(gemm_f64_ring(nt, kb1, kb, L21, lda, Bn, ldbn, &MXLU_AT(A, c1, c1, lda), lda,
+            MXLU_TRY(gemm_f64_update(nt, kb1, kb, L21, lda, Bn, ldbn, &MXLU_AT(A, c1, c1, lda), lda,
                                    s));
         }
         MXLU_TRY(fj.fork());
@@ -335,14 +335,14 @@ int factor_impl(int64_t n, int64_t nb, double *A, int64_t lda, int32_t *ipiv, hi
         const int64_t n1 = nt > kb1 ? lookahead_split(nt, kb, kb1, ov) : 0;
         if (n1 > 0) {
             PhaseScope ph(kPhaseGemm, ov->update, 2.0 * (double)nt * (double)n1 * (double)kb);
-            MXLU_TRY(gemm_f64_ring(nt, n1, kb, L21, lda, Bn + kb1, ldbn,
+            MXLU_TRY(gemm_f64_update(nt, n1, kb, L21, lda, Bn + kb1, ldbn,
                                    &MXLU_AT(A, c1, c1 + kb1, lda), lda, ov->update));
         }
         MXLU_TRY(fj.join_panel());
         const int64_t n2 = nt - kb1 - n1, j2 = kb1 + n1;
         if (n2 > 0) {
             PhaseScope ph(kPhaseGemm, s, 2.0 * (double)nt * (double)n2 * (double)kb);
-            MXLU_TRY(gemm_f64_ring(nt, n2, kb, L21, lda, Bn + j2, ldbn,
+            MXLU_TRY(gemm_f64_update(nt, n2, kb, L21, lda, Bn + j2, ldbn,
                                    &MXLU_AT(A, c1, c1 + j2, lda), lda, s));
         }
         MXLU_TRY(fj.join_update());
