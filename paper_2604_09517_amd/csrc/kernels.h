@@ -35,7 +35,7 @@ struct PanelExchange {
     uint64_t *slots;  // [2][kMaxGroups][4] candidates, then [2][kMaxGroups][kLeafW * 2] rows
     uint64_t *rowj;   // [2][kLeafW * 2] the current pivot row's old contents
     int *flags;       // [0]: first zero pivot (1-based), [1]: wait expired
-    int group_cap;    // most workgroups a leaf may launch (0: one per CU, about 64)
+    int group_cap;    // CUs a leaf may occupy (0: all); the LDS form puts one workgroup on each
 };
 constexpr int kLeafW = 32;        // columns factored by one leaf kernel
 constexpr int kMaxGroups = 256;   // workgroups of one leaf kernel (<= CUs)

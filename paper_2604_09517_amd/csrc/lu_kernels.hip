@@ -114,6 +114,35 @@ __device__ __forceinline__ uint32_t ll_wait(const uint64_t *p, uint64_t x, uint3
     return (uint32_t)x;
 }
 
+// Wait until each word x[k] with bit k of `valid` carries `seq` (x holds
+// loads already issued; addr(k) is the word's address).  Every round re-issues
+// the loads of all words still stale at once, so a round costs one load
+// latency however many words are late; the loop is wave-uniform.
+template <int K, class Addr>
+__device__ __forceinline__ void ll_gather(uint64_t (&x)[K], uint32_t valid, Addr addr, uint32_t seq,
+                                          int *flags) {
+    long rounds = 0;
+    while (true) {
+        uint32_t stale = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (((valid >> k) & 1u) && (uint32_t)(x[k] >> 32) != seq) stale |= 1u << k;
+        if (__builtin_amdgcn_ballot_w64(stale != 0) == 0) break;
+        if ((rounds & 63) == 0) {
+            if (__hip_atomic_load(&flags[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+            if (rounds > (1L << 22)) {
+                atomicExch(&flags[1], 1);
+                break;
+            }
+        }
+        ++rounds;
+        __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if ((stale >> k) & 1u) x[k] = ll_load(addr(k));
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void panel_leaf_kernel(
     int m, int w, T *__restrict__ P, int64_t lda, int R, int G, int64_t r0,
@@ -199,20 +228,26 @@ __global__ __launch_bounds__(256) void panel_leaf_kernel(
             // every slot word in use, and row j, in one batch
             const int nw = G * kSlotWords;
             if (wave == 0) {
-                uint64_t x[kOneBatch];
+                // word k < kOneBatch: slot word lane + 64 k; word kOneBatch: row j
+                uint64_t x[kOneBatch + 1];
+                uint32_t valid = 0;
+                auto addr = [&](int k) -> const uint64_t * {
+                    return k < kOneBatch ? &gs[lane + 64 * k] : &grj[lane];
+                };
 #pragma unroll
                 for (int k = 0; k < kOneBatch; ++k) {
                     const int t = lane + 64 * k, u = t % kSlotWords;
-                    x[k] = (t < nw && u != 3 && u < 4 + 2 * w) ? ll_load(&gs[t]) : 0ull;
+                    const bool use = t < nw && u != 3 && u < 4 + 2 * w;
+                    valid |= (uint32_t)use << k;
+                    x[k] = use ? ll_load(addr(k)) : 0ull;
                 }
-                const uint64_t y = (lane < 2 * w) ? ll_load(&grj[lane]) : 0ull;
+                valid |= (uint32_t)(lane < 2 * w) << kOneBatch;
+                x[kOneBatch] = (lane < 2 * w) ? ll_load(addr(kOneBatch)) : 0ull;
+                ll_gather(x, valid, addr, seq, flags);
 #pragma unroll
-                for (int k = 0; k < kOneBatch; ++k) {
-                    const int t = lane + 64 * k, u = t % kSlotWords;
-                    if (t < nw && u != 3 && u < 4 + 2 * w)
-                        s_words[t] = ll_wait(&gs[t], x[k], seq, flags);
-                }
-                if (lane < 2 * w) s_rowj[lane] = ll_wait(&grj[lane], y, seq, flags);
+                for (int k = 0; k < kOneBatch; ++k)
+                    if ((valid >> k) & 1u) s_words[lane + 64 * k] = (uint32_t)x[k];
+                if (lane < 2 * w) s_rowj[lane] = (uint32_t)x[kOneBatch];
             }
             __syncthreads();
             for (int t = lane; t < G; t += 64)
@@ -226,17 +261,21 @@ __global__ __launch_bounds__(256) void panel_leaf_kernel(
             const int nc = G * 3;
             if (wave == 0) {
                 uint64_t x[kCandPerLane];
+                uint32_t valid = 0;
+                auto addr = [&](int k) -> const uint64_t * {
+                    const int t = lane + 64 * k;
+                    return &gs[(t / 3) * kSlotWords + t % 3];
+                };
 #pragma unroll
                 for (int k = 0; k < kCandPerLane; ++k) {
-                    const int t = lane + 64 * k;
-                    x[k] = (t < nc) ? ll_load(&gs[(t / 3) * kSlotWords + t % 3]) : 0ull;
+                    const bool use = lane + 64 * k < nc;
+                    valid |= (uint32_t)use << k;
+                    x[k] = use ? ll_load(addr(k)) : 0ull;
                 }
+                ll_gather(x, valid, addr, seq, flags);
 #pragma unroll
-                for (int k = 0; k < kCandPerLane; ++k) {
-                    const int t = lane + 64 * k;
-                    if (t < nc)
-                        s_words[t] = ll_wait(&gs[(t / 3) * kSlotWords + t % 3], x[k], seq, flags);
-                }
+                for (int k = 0; k < kCandPerLane; ++k)
+                    if ((valid >> k) & 1u) s_words[lane + 64 * k] = (uint32_t)x[k];
             }
             __syncthreads();
             for (int t = lane; t < G; t += 64)
@@ -288,6 +327,360 @@ __global__ __launch_bounds__(256) void panel_leaf_kernel(
     __syncthreads();
     for (int c = 0; c < w; ++c)
         for (int i = tid; i < rows; i += 256) MXLU_AT(P, rb + i, c, lda) = sp[c * R + i];
+}
+
+// ---------------------------------------------------------------------------
+// PFACT leaf, register form (FP64): the same column steps, exchange protocol,
+// pivot choice and arithmetic as panel_leaf_kernel (the factors are bitwise
+// the same), with the leaf rows held in registers (RPT rows per thread,
+// R = 256 RPT rows per workgroup, columns unrolled at compile time) and the
+// column steps reordered to shorten the chain of dependent latencies per
+// column:
+//   * after the pivot row of column j arrives, every thread swaps, scales
+//     column j and updates only column j + 1 of its rows, then the group's
+//     candidate for column j + 1 is found and its (|a|, row) published;
+//   * the rest of the rank-1 update of column j (columns > j + 1) runs while
+//     that exchange is in flight, after which the candidate row and row j + 1
+//     (their values are final only now) are staged in LDS and published by
+//     2w threads, one word each (readers of a row word wait for its tag);
+//   * wave reductions use DPP row operations and readlane instead of LDS
+//     permutes.
+// The exchange words are the slots and rows of panel_leaf_kernel, so the two
+// forms can follow each other within one factorization.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double words_double(const uint32_t *q) {
+    return __longlong_as_double((long long)(((uint64_t)q[1] << 32) | q[0]));
+}
+
+template <int CTRL>
+__device__ __forceinline__ void argmax_dpp(double &v, int &idx) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+    const int oi = __builtin_amdgcn_update_dpp(0, idx, CTRL, 0xF, 0xF, false);
+    argmax_merge(v, idx,
+                 __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo)), oi);
+}
+
+// every lane ends with the wave's (max, first index); all lanes active
+__device__ __forceinline__ void wave_argmax_dpp(double &v, int &idx) {
+    argmax_dpp<0xB1>(v, idx);    // quad_perm [1,0,3,2]
+    argmax_dpp<0x4E>(v, idx);    // quad_perm [2,3,0,1]
+    argmax_dpp<0x124>(v, idx);   // row_ror:4
+    argmax_dpp<0x128>(v, idx);   // row_ror:8 (each row of 16 lanes now agrees)
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    double rv = -1.0;
+    int ri = INT_MAX;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, 16 * r);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 16 * r);
+        argmax_merge(rv, ri, __longlong_as_double((long long)(((uint64_t)hi << 32) | lo)),
+                     __builtin_amdgcn_readlane(idx, 16 * r));
+    }
+    v = rv;
+    idx = ri;
+}
+
+struct RegLeafShared {
+    uint32_t words[kWordsLds];
+    uint32_t prow[kRowWords];
+    uint32_t rowj[kRowWords];
+    uint32_t crow[kRowWords];   // the group's candidate row, staged for publication
+    uint32_t jrow[kRowWords];   // row j of the leaf (group holding it), staged
+    double wv[4];
+    int wi[4];
+};
+
+struct RegLeafArgs {
+    int w, G, rows, rb, g, tid, lane, wave;
+    int64_t r0;
+    int32_t *ipiv;
+    uint64_t *slots, *rowj;
+    int *flags;
+};
+
+template <int RPT>
+struct RegLeafState {
+    double x[RPT][mxlu::kLeafW];
+    double l[RPT];   // multipliers of the last pivot column (0 above it)
+    int idx;         // the group's candidate row of the current column
+};
+
+// scan column J, reduce to the group's candidate, publish (|a|, row)
+template <int RPT, int J>
+__device__ __forceinline__ void reg_leaf_candidate(RegLeafState<RPT> &st, const RegLeafArgs &a,
+                                                   RegLeafShared &sh) {
+    double v = -1.0;
+    int idx = INT_MAX;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int r = a.tid + 256 * q;
+        if (r < a.rows && a.rb + r >= J) {
+            const double av = fabs(st.x[q][J]);
+            if (av > v) {
+                v = av;
+                idx = a.rb + r;
+            }
+        }
+    }
+    wave_argmax_dpp(v, idx);
+    if (a.lane == 0) {
+        sh.wv[a.wave] = v;
+        sh.wi[a.wave] = idx;
+    }
+    __syncthreads();
+    v = sh.wv[0];
+    idx = sh.wi[0];
+#pragma unroll
+    for (int k = 1; k < 4; ++k) argmax_merge(v, idx, sh.wv[k], sh.wi[k]);
+    st.idx = idx;
+    if (a.tid == 0) {
+        const uint32_t seq = (uint32_t)(a.r0 + J + 1);
+        uint64_t *mine =
+            a.slots + (size_t)(J & 1) * mxlu::kMaxGroups * kSlotWords + (size_t)a.g * kSlotWords;
+        const uint64_t vb = (uint64_t)__double_as_longlong(v);
+        ll_store(&mine[0], seq, (uint32_t)vb);
+        ll_store(&mine[1], seq, (uint32_t)(vb >> 32));
+        ll_store(&mine[2], seq, (uint32_t)idx);
+    }
+}
+
+// stage the candidate row and row J in LDS, then publish them one word per thread
+template <int RPT, int J>
+__device__ __forceinline__ void reg_leaf_publish_rows(RegLeafState<RPT> &st, const RegLeafArgs &a,
+                                                      RegLeafShared &sh) {
+    const int w = a.w;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int r = a.tid + 256 * q;
+        const int rr = a.rb + r;
+        if (st.idx != INT_MAX && rr == st.idx) {
+#pragma unroll
+            for (int c = 0; c < mxlu::kLeafW; ++c)
+                if (c < w) {
+                    const uint64_t xb = (uint64_t)__double_as_longlong(st.x[q][c]);
+                    sh.crow[2 * c] = (uint32_t)xb;
+                    sh.crow[2 * c + 1] = (uint32_t)(xb >> 32);
+                }
+        }
+        if (r < a.rows && rr == J) {
+#pragma unroll
+            for (int c = 0; c < mxlu::kLeafW; ++c)
+                if (c < w) {
+                    const uint64_t xb = (uint64_t)__double_as_longlong(st.x[q][c]);
+                    sh.jrow[2 * c] = (uint32_t)xb;
+                    sh.jrow[2 * c + 1] = (uint32_t)(xb >> 32);
+                }
+        }
+    }
+    __syncthreads();
+    const uint32_t seq = (uint32_t)(a.r0 + J + 1);
+    uint64_t *mine =
+        a.slots + (size_t)(J & 1) * mxlu::kMaxGroups * kSlotWords + (size_t)a.g * kSlotWords;
+    if (st.idx != INT_MAX && a.tid < 2 * w) ll_store(&mine[4 + a.tid], seq, sh.crow[a.tid]);
+    if (J >= a.rb && J < a.rb + a.rows && a.tid >= 64 && a.tid < 64 + 2 * w)
+        ll_store(&a.rowj[(J & 1) * kRowWords + a.tid - 64], seq, sh.jrow[a.tid - 64]);
+}
+
+// rank-1 update of columns [c0, c1) (within (JP, w)) with the multipliers of
+// pivot column JP and the pivot row
+template <int RPT, int JP>
+__device__ __forceinline__ void reg_leaf_update(RegLeafState<RPT> &st, const RegLeafArgs &a,
+                                                const uint32_t *prow, int c0, int c1) {
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int r = a.tid + 256 * q;
+        if (r < a.rows && a.rb + r > JP) {
+#pragma unroll
+            for (int c = JP + 1; c < mxlu::kLeafW; ++c)
+                if (c >= c0 && c < c1 && c < a.w)
+                    st.x[q][c] = fma(-st.l[q], words_double(&prow[2 * c]), st.x[q][c]);
+        }
+    }
+}
+
+// gather the candidates of column J, choose the pivot, fetch its row (and
+// row J when it moves into this group), swap, scale column J; returns the
+// pivot row (LDS)
+template <int RPT, int J>
+__device__ __forceinline__ const uint32_t *reg_leaf_column(RegLeafState<RPT> &st,
+                                                           const RegLeafArgs &a,
+                                                           RegLeafShared &sh) {
+    constexpr int R = 256 * RPT;
+    const int tid = a.tid, lane = a.lane, wave = a.wave, w = a.w, G = a.G;
+    const uint32_t seq = (uint32_t)(a.r0 + J + 1);
+    uint64_t *gs = a.slots + (size_t)(J & 1) * mxlu::kMaxGroups * kSlotWords;
+    uint64_t *grj = a.rowj + (J & 1) * kRowWords;
+    double gv = -1.0;
+    int gi = INT_MAX;
+    const uint32_t *prow;
+    bool swap;
+    if (G <= kOnePhaseGroups) {
+        // every slot word in use in one batch
+        const int nw = G * kSlotWords;
+        if (wave == 0) {
+            uint64_t x[kOneBatch];
+            uint32_t valid = 0;
+            auto addr = [&](int k) -> const uint64_t * { return &gs[lane + 64 * k]; };
+#pragma unroll
+            for (int k = 0; k < kOneBatch; ++k) {
+                const int t = lane + 64 * k, u = t % kSlotWords;
+                const bool use = t < nw && u != 3 && u < 4 + 2 * w;
+                valid |= (uint32_t)use << k;
+                x[k] = use ? ll_load(addr(k)) : 0ull;
+            }
+            ll_gather(x, valid, addr, seq, a.flags);
+#pragma unroll
+            for (int k = 0; k < kOneBatch; ++k)
+                if ((valid >> k) & 1u) sh.words[lane + 64 * k] = (uint32_t)x[k];
+        }
+        __syncthreads();
+        for (int t = lane; t < G; t += 64)
+            argmax_merge(gv, gi, words_double(&sh.words[t * kSlotWords]),
+                         (int)sh.words[t * kSlotWords + 2]);
+        wave_argmax_dpp(gv, gi);
+        prow = &sh.words[(gi / R) * kSlotWords + 4];
+        swap = (gv != 0.0) && gi != J;
+        if (swap && gi >= a.rb && gi < a.rb + a.rows && tid >= 64 && tid < 64 + 2 * w) {
+            const uint64_t *src = &grj[tid - 64];
+            sh.rowj[tid - 64] = ll_wait(src, ll_load(src), seq, a.flags);
+        }
+        __syncthreads();
+    } else {
+        // the candidates first, then the winner's row (and row J when it
+        // moves into this group)
+        const int nc = G * 3;
+        if (wave == 0) {
+            uint64_t x[kCandPerLane];
+            uint32_t valid = 0;
+            auto addr = [&](int k) -> const uint64_t * {
+                const int t = lane + 64 * k;
+                return &gs[(t / 3) * kSlotWords + t % 3];
+            };
+#pragma unroll
+            for (int k = 0; k < kCandPerLane; ++k) {
+                const bool use = lane + 64 * k < nc;
+                valid |= (uint32_t)use << k;
+                x[k] = use ? ll_load(addr(k)) : 0ull;
+            }
+            ll_gather(x, valid, addr, seq, a.flags);
+#pragma unroll
+            for (int k = 0; k < kCandPerLane; ++k)
+                if ((valid >> k) & 1u) sh.words[lane + 64 * k] = (uint32_t)x[k];
+        }
+        __syncthreads();
+        for (int t = lane; t < G; t += 64)
+            argmax_merge(gv, gi, words_double(&sh.words[3 * t]), (int)sh.words[3 * t + 2]);
+        wave_argmax_dpp(gv, gi);
+        swap = (gv != 0.0) && gi != J;
+        if (tid < 2 * w) {
+            const uint64_t *src = gs + (size_t)(gi / R) * kSlotWords + 4 + tid;
+            sh.prow[tid] = ll_wait(src, ll_load(src), seq, a.flags);
+        } else if (swap && gi >= a.rb && gi < a.rb + a.rows && tid >= 64 && tid < 64 + 2 * w) {
+            const uint64_t *src = &grj[tid - 64];
+            sh.rowj[tid - 64] = ll_wait(src, ll_load(src), seq, a.flags);
+        }
+        __syncthreads();
+        prow = sh.prow;
+    }
+    // gi is a valid row >= J (the group holding row J has a candidate)
+    const int p = gi;
+    const bool nonzero = (gv != 0.0);
+    if (a.g == 0 && tid == 0) {
+        a.ipiv[J] = (int32_t)(a.r0 + (nonzero ? p : J));
+        if (!nonzero && a.flags[0] == 0) a.flags[0] = (int)(a.r0 + J + 1);
+    }
+    const double piv = words_double(&prow[2 * J]);
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int r = tid + 256 * q;
+        const int rr = a.rb + r;
+        if (swap && rr == J) {
+#pragma unroll
+            for (int c = 0; c < mxlu::kLeafW; ++c)
+                if (c < w) st.x[q][c] = words_double(&prow[2 * c]);
+        } else if (swap && rr == p) {
+#pragma unroll
+            for (int c = 0; c < mxlu::kLeafW; ++c)
+                if (c < w) st.x[q][c] = words_double(&sh.rowj[2 * c]);
+        }
+        st.l[q] = 0.0;
+        if (r < a.rows && rr > J) {
+            double l = st.x[q][J];
+            if (nonzero) {
+                l = l / piv;
+                st.x[q][J] = l;
+            }
+            st.l[q] = l;
+        }
+    }
+    return prow;
+}
+
+template <int RPT, int J>
+struct RegLeafSteps {
+    static __device__ __forceinline__ void run(RegLeafState<RPT> &st, const RegLeafArgs &a,
+                                               RegLeafShared &sh) {
+        if (J < a.w) {
+            const uint32_t *prow = reg_leaf_column<RPT, J>(st, a, sh);
+            if (J + 1 < a.w) {
+                constexpr int JN = (J + 1 < mxlu::kLeafW) ? J + 1 : J;
+                reg_leaf_update<RPT, J>(st, a, prow, J + 1, J + 2);
+                reg_leaf_candidate<RPT, JN>(st, a, sh);
+                reg_leaf_update<RPT, J>(st, a, prow, J + 2, mxlu::kLeafW);
+                reg_leaf_publish_rows<RPT, JN>(st, a, sh);
+            }
+            RegLeafSteps<RPT, J + 1>::run(st, a, sh);
+        }
+    }
+};
+template <int RPT>
+struct RegLeafSteps<RPT, mxlu::kLeafW> {
+    static __device__ __forceinline__ void run(RegLeafState<RPT> &, const RegLeafArgs &,
+                                               RegLeafShared &) {}
+};
+
+template <int RPT>
+__global__ __launch_bounds__(256) void panel_leaf_reg_kernel(int m, int w, double *__restrict__ P,
+                                                             int64_t lda, int G, int64_t r0,
+                                                             int32_t *__restrict__ ipiv,
+                                                             uint64_t *slots, uint64_t *rowj,
+                                                             int *flags) {
+    constexpr int R = 256 * RPT;
+    __shared__ RegLeafShared sh;
+    RegLeafArgs a;
+    a.w = w;
+    a.G = G;
+    a.g = blockIdx.x;
+    a.tid = threadIdx.x;
+    a.lane = a.tid & 63;
+    a.wave = a.tid >> 6;
+    a.rb = a.g * R;
+    a.rows = min(R, m - a.rb);
+    a.r0 = r0;
+    a.ipiv = ipiv;
+    a.slots = slots;
+    a.rowj = rowj;
+    a.flags = flags;
+    RegLeafState<RPT> st;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q)
+#pragma unroll
+        for (int c = 0; c < mxlu::kLeafW; ++c) {
+            const int r = a.tid + 256 * q;
+            st.x[q][c] = (r < a.rows && c < w) ? P[(size_t)(a.rb + r) + (size_t)c * lda] : 0.0;
+        }
+    reg_leaf_candidate<RPT, 0>(st, a, sh);
+    reg_leaf_publish_rows<RPT, 0>(st, a, sh);
+    RegLeafSteps<RPT, 0>::run(st, a, sh);
+#pragma unroll
+    for (int q = 0; q < RPT; ++q)
+#pragma unroll
+        for (int c = 0; c < mxlu::kLeafW; ++c) {
+            const int r = a.tid + 256 * q;
+            if (r < a.rows && c < w) P[(size_t)(a.rb + r) + (size_t)c * lda] = st.x[q][c];
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -617,11 +1010,44 @@ static int leaf_geometry(int64_t m, int cap, int64_t *R_out, int64_t *G_out,
     return 0;
 }
 
+// Register form of the FP64 leaf: rows per thread (1 or 2) and workgroups,
+// or 0 when it does not apply.  All G workgroups must be resident at once:
+// G stays within the workgroups per CU the kernel's resources allow times the
+// CUs available (`cap` CUs when cap > 0, else all of them).
+static int reg_leaf_occupancy(int rpt) {
+    static int occ[3] = {-1, -1, -1};
+    if (occ[rpt] < 0) {
+        int v = 0;
+        const void *k = rpt == 1 ? (const void *)panel_leaf_reg_kernel<1>
+                                 : (const void *)panel_leaf_reg_kernel<2>;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k, 256, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            v = 1;
+        }
+        occ[rpt] = std::max(1, v);
+    }
+    return occ[rpt];
+}
+
+static int reg_leaf_plan(int64_t m, int cap, int64_t *G_out) {
+    const int64_t cus = cap > 0 ? cap : compute_units();
+    for (int rpt = 1; rpt <= 2; ++rpt) {
+        const int64_t G = (m + 256 * rpt - 1) / (256 * rpt);
+        if (G <= mxlu::kMaxGroups && G <= (int64_t)reg_leaf_occupancy(rpt) * cus) {
+            *G_out = G;
+            return rpt;
+        }
+    }
+    return 0;
+}
+
 template <typename T>
 int panel_leaf_groups(int64_t m, int cap) {
     int64_t R = 0, G = 0, budget = 0;
     if (m <= 0) return 0;
-    if (m > 0x7fffffff || leaf_geometry<T>(m, cap, &R, &G, &budget)) return -1;
+    if (m > 0x7fffffff) return -1;
+    if (sizeof(T) == 8 && reg_leaf_plan(m, cap, &G)) return (int)G;
+    if (leaf_geometry<T>(m, cap, &R, &G, &budget)) return -1;
     return (int)G;
 }
 template int panel_leaf_groups<double>(int64_t, int);
@@ -634,6 +1060,23 @@ int panel_leaf(int64_t m, int w, T *P, int64_t ldp, int64_t r0, int32_t *ipiv,
     if (w > kLeafW || m > 0x7fffffff) {
         set_error_msg("panel_leaf: bad shape");
         return MXLU_E_NOMEM;
+    }
+    if (sizeof(T) == 8) {
+        int64_t Gr = 0;
+        const int rpt = reg_leaf_plan(m, ex.group_cap, &Gr);
+        if (rpt) {
+            double *Pd = reinterpret_cast<double *>(P);
+            if (rpt == 1)
+                hipLaunchKernelGGL(panel_leaf_reg_kernel<1>, dim3((unsigned)Gr), dim3(256), 0, s,
+                                   (int)m, w, Pd, ldp, (int)Gr, r0, ipiv + r0, ex.slots, ex.rowj,
+                                   ex.flags);
+            else
+                hipLaunchKernelGGL(panel_leaf_reg_kernel<2>, dim3((unsigned)Gr), dim3(256), 0, s,
+                                   (int)m, w, Pd, ldp, (int)Gr, r0, ipiv + r0, ex.slots, ex.rowj,
+                                   ex.flags);
+            MXLU_LAUNCH_CHECK();
+            return 0;
+        }
     }
     int64_t R = 0, G = 0, budget = 0;
     MXLU_TRY(leaf_geometry<T>(m, ex.group_cap, &R, &G, &budget));
