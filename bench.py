@@ -39,6 +39,7 @@ METRIC = "Effective TFLOP/s (2N\u00b3/3): FP64 LU vs BF16/FP8 LU+FP64 IR at resi
 PEAK_TFLOPS = {"f64": 78.6, "bf16": 2500.0, "f16": 2500.0, "fp8": 5000.0}
 PROFILES = os.path.join(ROOT, "profiles")
 GEMM_SRC = os.path.join(ROOT, "paper_2604_09517_amd", "csrc", "gemm_f64.hip")
+LP_SRC = os.path.join(ROOT, "paper_2604_09517_amd", "csrc", "lp_gemm.hip")
 
 
 def log(msg):
@@ -257,7 +258,10 @@ def run_mxp(args, cfg, name):
                    "storage": "bf16" if prec == "bf16" else "fp16",
                    "peak_frac_fp64_equivalent_vs_mfma": round(value / mma_peak, 4)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0,
-                     "unit": "GB/s", "frac": round(achieved / 8000.0, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / 8000.0, 4),
+                     "traffic": traffic_from_profile(
+                         "lp_schur16_bf16_ir.md" if name == "bf16_ir" else "lp_schur8_fp8_ir.md",
+                         LP_SRC),
                      "kernel": f"lp_schur{'16' if prec == 'bf16' else '8'}_kernel "
                                f"(trailing update)",
                      "launches": scnt, "avg_launch_ms": round(sms / max(1, scnt), 4),
