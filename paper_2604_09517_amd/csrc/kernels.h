@@ -73,6 +73,9 @@ int laswp_f64(double *A, int64_t lda, const int32_t *ipiv, int64_t j0, int cnt,
 int trsm_llnu_f64(int kb, int64_t ncols, const double *L, int64_t ldl, double *B,
                   int64_t ldb, hipStream_t s);
 // B(kb x ncols) = U^-1 B with U upper, non-unit (kb <= 256).
+// One right-hand side y (bb <= 256 values) through the diagonal block T:
+// lower = unit lower forward, else upper (non-unit) backward.
+int trsv_block_f64(int bb, bool lower, const double *T, int64_t ldt, double *y, hipStream_t s);
 int trsm_lunn_f64(int kb, int64_t ncols, const double *U, int64_t ldu, double *B,
                   int64_t ldb, hipStream_t s);
 // B(kb x ncols) = U^-T B (U upper non-unit) and B = L^-T B (L unit lower).

@@ -419,7 +419,11 @@ extern "C" int lu_solve(int64_t n, int64_t nrhs, const double *LU, int64_t lda,
             // L y = P b: diagonal blocks forward, updates below
             for (int64_t b0 = 0; b0 < n; b0 += bs) {
                 const int64_t bb = std::min(bs, n - b0);
-                MXLU_TRY(trsm_llnu_f64((int)bb, nr, &MXLU_AT(LU, b0, b0, lda), lda, Y + b0, ldy, s));
+                if (nr == 1)
+                    MXLU_TRY(trsv_block_f64((int)bb, true, &MXLU_AT(LU, b0, b0, lda), lda, Y + b0, s));
+                else
+                    MXLU_TRY(trsm_llnu_f64((int)bb, nr, &MXLU_AT(LU, b0, b0, lda), lda, Y + b0, ldy,
+                                           s));
                 if (b0 + bb < n)
                     MXLU_TRY(gemm_f64_sub(n - b0 - bb, nr, bb, &MXLU_AT(LU, b0 + bb, b0, lda), lda,
                                      Y + b0, ldy, Y + b0 + bb, ldy, s));
@@ -428,7 +432,11 @@ extern "C" int lu_solve(int64_t n, int64_t nrhs, const double *LU, int64_t lda,
             const int64_t nblk = (n + bs - 1) / bs;
             for (int64_t bi = nblk - 1; bi >= 0; --bi) {
                 const int64_t b0 = bi * bs, bb = std::min(bs, n - b0);
-                MXLU_TRY(trsm_lunn_f64((int)bb, nr, &MXLU_AT(LU, b0, b0, lda), lda, Y + b0, ldy, s));
+                if (nr == 1)
+                    MXLU_TRY(trsv_block_f64((int)bb, false, &MXLU_AT(LU, b0, b0, lda), lda, Y + b0, s));
+                else
+                    MXLU_TRY(trsm_lunn_f64((int)bb, nr, &MXLU_AT(LU, b0, b0, lda), lda, Y + b0, ldy,
+                                           s));
                 if (b0 > 0)
                     MXLU_TRY(gemm_f64_sub(b0, nr, bb, &MXLU_AT(LU, 0, b0, lda), lda, Y + b0, ldy, Y,
                                      ldy, s));

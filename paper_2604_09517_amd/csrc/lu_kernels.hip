@@ -927,6 +927,77 @@ __global__ __launch_bounds__(256) void perm_from_ipiv_kernel(int64_t n,
         for (int64_t t = threadIdx.x; t < n; t += 256) perm[t] = sperm[t];
 }
 
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// One right-hand side through a triangular diagonal block of order bb <= 256
+// (one workgroup): the block is solved 64 rows at a time; wave 0 holds the
+// 64 x 64 diagonal sub-block, one row per lane, in registers and solves it
+// with each finished value broadcast by readlane; then all threads apply the
+// sub-block's values to the rows still to be solved (one row per thread,
+// coalesced column loads).  LOWER: unit lower, forward; else upper with its
+// diagonal, backward.  y (bb values) is read once and written once.
+template <bool LOWER>
+__global__ __launch_bounds__(256) void trsv_block_f64_kernel(int bb, const double *__restrict__ T,
+                                                             int64_t ldt, double *__restrict__ y) {
+    __shared__ double ys[256];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid < bb) ys[tid] = y[tid];
+    const int nsb = (bb + 63) / 64;
+    for (int k = 0; k < nsb; ++k) {
+        const int sb = LOWER ? k : nsb - 1 - k;
+        const int c0 = 64 * sb;
+        __syncthreads();
+        if (wave == 0) {
+            const int r = c0 + lane;
+            const bool ok = r < bb;
+            double a[64];
+#pragma unroll
+            for (int j = 0; j < 64; ++j)
+                a[j] = (ok && c0 + j < bb) ? T[(size_t)r + (size_t)(c0 + j) * ldt] : 0.0;
+            double x = ok ? ys[r] : 0.0;
+            if (LOWER) {
+#pragma unroll
+                for (int j = 0; j < 64; ++j) {
+                    const double xj = readlane_f64(x, j);   // final
+                    if (lane > j) x = fma(-a[j], xj, x);
+                }
+            } else {
+#pragma unroll
+                for (int j = 63; j >= 0; --j) {
+                    if (lane == j && ok) x = x / a[j];
+                    const double xj = readlane_f64(x, j);
+                    if (lane < j) x = fma(-a[j], xj, x);
+                }
+            }
+            if (ok) ys[r] = x;
+        }
+        __syncthreads();
+        // rows still to solve: below the sub-block (LOWER) or above it
+        const int r = LOWER ? c0 + 64 + tid : tid;
+        const bool todo = LOWER ? (r < bb) : (r < c0);
+        if (todo) {
+            // all 64 loads issued before the first use
+            const int jn = (bb - c0 < 64) ? bb - c0 : 64;
+            double t[64];
+#pragma unroll
+            for (int j = 0; j < 64; ++j)
+                t[j] = (j < jn) ? T[(size_t)r + (size_t)(c0 + j) * ldt] : 0.0;
+            double acc = ys[r];
+#pragma unroll
+            for (int j = 0; j < 64; ++j)
+                if (j < jn) acc = fma(-t[j], ys[c0 + j], acc);
+            ys[r] = acc;
+        }
+    }
+    __syncthreads();
+    if (tid < bb) y[tid] = ys[tid];
+}
+
 __global__ void gather_rows_kernel(int64_t n, int64_t nrhs, const int32_t *__restrict__ perm,
                                    const double *__restrict__ B, int64_t ldb,
                                    double *__restrict__ Y, int64_t ldy) {
@@ -1161,6 +1232,19 @@ int trsm_llnu_f64(int kb, int64_t ncols, const double *L, int64_t ldl, double *B
 int trsm_lunn_f64(int kb, int64_t ncols, const double *U, int64_t ldu, double *B, int64_t ldb,
                   hipStream_t s) {
     return trsm_launch<false, false, false>(kb, ncols, U, ldu, B, ldb, s);
+}
+int trsv_block_f64(int bb, bool lower, const double *T, int64_t ldt, double *y, hipStream_t s) {
+    if (bb <= 0) return 0;
+    if (bb > 256) {
+        set_error_msg("trsv_block_f64: block larger than 256");
+        return MXLU_E_NOMEM;
+    }
+    if (lower)
+        hipLaunchKernelGGL(trsv_block_f64_kernel<true>, dim3(1), dim3(256), 0, s, bb, T, ldt, y);
+    else
+        hipLaunchKernelGGL(trsv_block_f64_kernel<false>, dim3(1), dim3(256), 0, s, bb, T, ldt, y);
+    MXLU_LAUNCH_CHECK();
+    return 0;
 }
 int trsm_lutn_f64(int kb, int64_t ncols, const double *U, int64_t ldu, double *B, int64_t ldb,
                   hipStream_t s) {
