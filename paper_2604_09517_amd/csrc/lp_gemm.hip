@@ -66,9 +66,10 @@ __device__ __forceinline__ v4f mfma16(uint4 a, uint4 b, v4f c) {
 // stages with 16-byte direct global->LDS loads (no register staging): each
 // wave issues 4 + 2 loads of 1 KB per chunk, so up to kNs16 - 1 chunks are in
 // flight while the matrix cores work on the current one, and one workgroup
-// barrier per chunk orders the ring.  A is negated when read from LDS.  C is
-// read and written 8 bytes (4 rows of one column) per lane, the accumulator
-// layout.
+// barrier per chunk orders the ring.  A is negated when read from LDS.  The
+// A rows of each pair of MFMA blocks are interleaved so that a lane's
+// accumulators cover 8 consecutive rows of a column: C is read and written
+// 16 bytes per lane.
 constexpr int BK16 = kLpKc;
 constexpr int kNs16 = 3;
 static_assert(TM == kLpTileM && TN == kLpTileN, "tile and packing must agree");
@@ -99,35 +100,46 @@ __global__ __launch_bounds__(256, 2) void lp_schur16_kernel(
     const int wm = wave & 1, wn = wave >> 1;
     const int li = lane & 15, lg = lane >> 4;
 
-    // accumulators <- C (rows r .. r+3 of column c per lane); interior tiles
-    // (uniform branch) issue all their loads back to back without checks
-    const bool full = row0 + TM <= M && col0 + TN <= N;
+    // Row mapping: the A operand of MFMA block bi = 2p + h supplies, in lane
+    // li, tile row 32p + 2 li + h, so accumulator register r of lane (li, lg)
+    // of blocks 2p and 2p + 1 holds the 8 consecutive rows 32p + 8 lg + 2r + h
+    // of column c: C moves 16 bytes per lane (rows row8 .. row8 + 7).
+    // Interior tiles with 16-byte aligned columns (uniform branch) issue all
+    // their loads back to back without checks.
+    const bool full = row0 + TM <= M && col0 + TN <= N && (ldc & 7) == 0 &&
+                      ((uintptr_t)C & 15) == 0;
+    auto row_of = [&](int bi, int r) -> int64_t {
+        return row0 + wm * 128 + 32 * (bi >> 1) + 2 * (4 * lg + r) + (bi & 1);
+    };
     v4f acc[8][4];
     if (full) {
 #pragma unroll
-        for (int bi = 0; bi < 8; ++bi)
+        for (int pr = 0; pr < 4; ++pr)
 #pragma unroll
             for (int bj = 0; bj < 4; ++bj) {
-                const int64_t r = row0 + wm * 128 + bi * 16 + 4 * lg;
+                const int64_t r8 = row0 + wm * 128 + 32 * pr + 8 * lg;
                 const int64_t c = col0 + wn * 64 + bj * 16 + li;
-                const uint2 v = *reinterpret_cast<const uint2 *>(&C[(size_t)r + (size_t)c * ldc]);
-                acc[bi][bj][0] = lp_to_f32<FMT>((uint16_t)v.x);
-                acc[bi][bj][1] = lp_to_f32<FMT>((uint16_t)(v.x >> 16));
-                acc[bi][bj][2] = lp_to_f32<FMT>((uint16_t)v.y);
-                acc[bi][bj][3] = lp_to_f32<FMT>((uint16_t)(v.y >> 16));
+                const uint4 v = *reinterpret_cast<const uint4 *>(&C[(size_t)r8 + (size_t)c * ldc]);
+                const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    acc[2 * pr][bj][r] = lp_to_f32<FMT>((uint16_t)w4[r]);
+                    acc[2 * pr + 1][bj][r] = lp_to_f32<FMT>((uint16_t)(w4[r] >> 16));
+                }
             }
     } else {
 #pragma unroll
         for (int bi = 0; bi < 8; ++bi)
 #pragma unroll
             for (int bj = 0; bj < 4; ++bj) {
-                const int64_t r = row0 + wm * 128 + bi * 16 + 4 * lg;
                 const int64_t c = col0 + wn * 64 + bj * 16 + li;
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    acc[bi][bj][e] = (r + e < M && c < N)
-                                         ? lp_to_f32<FMT>(C[(size_t)(r + e) + (size_t)c * ldc])
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t row = row_of(bi, r);
+                    acc[bi][bj][r] = (row < M && c < N)
+                                         ? lp_to_f32<FMT>(C[(size_t)row + (size_t)c * ldc])
                                          : 0.0f;
+                }
             }
     }
 
@@ -170,7 +182,7 @@ __global__ __launch_bounds__(256, 2) void lp_schur16_kernel(
 #pragma unroll
         for (int bi = 0; bi < 8; ++bi)
             a[bi] = neg16(*reinterpret_cast<const uint4 *>(
-                &as[(wm * 128 + bi * 16 + li) * BK16 + lg * 8]));
+                &as[(wm * 128 + 32 * (bi >> 1) + 2 * li + (bi & 1)) * BK16 + lg * 8]));
 #pragma unroll
         for (int bj = 0; bj < 4; ++bj)
             b[bj] = *reinterpret_cast<const uint4 *>(&bs[(wn * 64 + bj * 16 + li) * BK16 + lg * 8]);
@@ -180,26 +192,35 @@ __global__ __launch_bounds__(256, 2) void lp_schur16_kernel(
             for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = mfma16<FMT>(a[bi], b[bj], acc[bi][bj]);
     }
 
+    if (full) {
 #pragma unroll
-    for (int bi = 0; bi < 8; ++bi)
+        for (int pr = 0; pr < 4; ++pr)
 #pragma unroll
-        for (int bj = 0; bj < 4; ++bj) {
-            const int64_t r = row0 + wm * 128 + bi * 16 + 4 * lg;
-            const int64_t c = col0 + wn * 64 + bj * 16 + li;
-            if (full) {
-                uint2 v;
-                v.x = (uint32_t)f32_to_lp<FMT>(acc[bi][bj][0]) |
-                      ((uint32_t)f32_to_lp<FMT>(acc[bi][bj][1]) << 16);
-                v.y = (uint32_t)f32_to_lp<FMT>(acc[bi][bj][2]) |
-                      ((uint32_t)f32_to_lp<FMT>(acc[bi][bj][3]) << 16);
-                *reinterpret_cast<uint2 *>(&C[(size_t)r + (size_t)c * ldc]) = v;
-            } else {
+            for (int bj = 0; bj < 4; ++bj) {
+                const int64_t r8 = row0 + wm * 128 + 32 * pr + 8 * lg;
+                const int64_t c = col0 + wn * 64 + bj * 16 + li;
+                uint32_t w4[4];
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    if (r + e < M && c < N)
-                        C[(size_t)(r + e) + (size_t)c * ldc] = f32_to_lp<FMT>(acc[bi][bj][e]);
+                for (int r = 0; r < 4; ++r)
+                    w4[r] = (uint32_t)f32_to_lp<FMT>(acc[2 * pr][bj][r]) |
+                            ((uint32_t)f32_to_lp<FMT>(acc[2 * pr + 1][bj][r]) << 16);
+                *reinterpret_cast<uint4 *>(&C[(size_t)r8 + (size_t)c * ldc]) =
+                    make_uint4(w4[0], w4[1], w4[2], w4[3]);
             }
-        }
+    } else {
+#pragma unroll
+        for (int bi = 0; bi < 8; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj) {
+                const int64_t c = col0 + wn * 64 + bj * 16 + li;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t row = row_of(bi, r);
+                    if (row < M && c < N)
+                        C[(size_t)row + (size_t)c * ldc] = f32_to_lp<FMT>(acc[bi][bj][r]);
+                }
+            }
+    }
 }
 
 // ------------------------------------------------------------ FP8 form
