@@ -230,7 +230,8 @@ __global__ __launch_bounds__(256, 2) void lp_schur16_kernel(
 // 16-byte direct global->LDS loads (8 loads of 1 KB per wave and chunk).
 // The accumulators start at -C / (sL sU) (exact: power-of-two scales) and
 // take +Lq Uq, so that -acc sL sU = C - (Lq Uq) sL sU needs no operand
-// negation; C is read and written 8 bytes (4 rows) per lane.
+// negation; C is read and written 16 bytes (8 rows) per lane, the A rows of
+// each pair of MFMA blocks being interleaved as in the 16-bit form.
 constexpr int kTm8 = 128, kTn8 = 128;
 constexpr int BK8 = kLp8Kc;
 constexpr int kNs8 = 2;
@@ -259,38 +260,50 @@ __global__ __launch_bounds__(256, 2) void lp_schur8_kernel(
     const int wm = wave & 1, wn = wave >> 1;
     const int li = lane & 15, lg = lane >> 4;
 
-    // accumulators <- -C / (sL sU); interior tiles (uniform branch) issue all
-    // their loads back to back without checks
-    const bool full = row0 + kTm8 <= M && col0 + kTn8 <= N;
+    // accumulators <- -C / (sL sU).  Rows as in the 16-bit form: the A operand
+    // of MFMA block bi = 2p + h supplies tile row 32p + 2 li + h in lane li, so
+    // a lane's accumulators of blocks 2p, 2p + 1 cover 8 consecutive rows of
+    // one column (16 bytes of C; rows 0-3 and 4-7 each share a scale tile,
+    // tiles being multiples of 4).  Interior tiles with 16-byte aligned columns
+    // (uniform branch) issue all their loads back to back without checks.
+    const bool full = row0 + kTm8 <= M && col0 + kTn8 <= N && (ldc & 7) == 0 &&
+                      ((uintptr_t)C & 15) == 0;
+    auto row_of = [&](int bi, int r) -> int64_t {
+        return row0 + wm * 64 + 32 * (bi >> 1) + 2 * (4 * lg + r) + (bi & 1);
+    };
     v4f acc[4][4];
     if (full) {
 #pragma unroll
-        for (int bi = 0; bi < 4; ++bi)
+        for (int pr = 0; pr < 2; ++pr)
 #pragma unroll
             for (int bj = 0; bj < 4; ++bj) {
-                const int64_t r = row0 + wm * 64 + bi * 16 + 4 * lg;
+                const int64_t r8 = row0 + wm * 64 + 32 * pr + 8 * lg;
                 const int64_t c = col0 + wn * 64 + bj * 16 + li;
-                const uint2 v = *reinterpret_cast<const uint2 *>(&C[(size_t)r + (size_t)c * ldc]);
-                const float inv = 1.0f / (sL[tix(r)] * sU[tix(c)]);   // rows r..r+3 share a tile
-                acc[bi][bj][0] = -lp_to_f32<FMT>((uint16_t)v.x) * inv;
-                acc[bi][bj][1] = -lp_to_f32<FMT>((uint16_t)(v.x >> 16)) * inv;
-                acc[bi][bj][2] = -lp_to_f32<FMT>((uint16_t)v.y) * inv;
-                acc[bi][bj][3] = -lp_to_f32<FMT>((uint16_t)(v.y >> 16)) * inv;
+                const uint4 v = *reinterpret_cast<const uint4 *>(&C[(size_t)r8 + (size_t)c * ldc]);
+                const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+                const float su = sU[tix(c)];
+                const float inv_lo = 1.0f / (sL[tix(r8)] * su), inv_hi = 1.0f / (sL[tix(r8 + 4)] * su);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const float inv = r < 2 ? inv_lo : inv_hi;
+                    acc[2 * pr][bj][r] = -lp_to_f32<FMT>((uint16_t)w4[r]) * inv;
+                    acc[2 * pr + 1][bj][r] = -lp_to_f32<FMT>((uint16_t)(w4[r] >> 16)) * inv;
+                }
             }
     } else {
 #pragma unroll
         for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
             for (int bj = 0; bj < 4; ++bj) {
-                const int64_t r = row0 + wm * 64 + bi * 16 + 4 * lg;
                 const int64_t c = col0 + wn * 64 + bj * 16 + li;
-                const bool in = r < M && c < N;
-                const float inv = in ? 1.0f / (sL[tix(r)] * sU[tix(c)]) : 0.0f;
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    acc[bi][bj][e] = (in && r + e < M)
-                                         ? -lp_to_f32<FMT>(C[(size_t)(r + e) + (size_t)c * ldc]) * inv
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t row = row_of(bi, r);
+                    acc[bi][bj][r] = (row < M && c < N)
+                                         ? -lp_to_f32<FMT>(C[(size_t)row + (size_t)c * ldc]) /
+                                               (sL[tix(row)] * sU[tix(c)])
                                          : 0.0f;
+                }
             }
     }
 
@@ -327,7 +340,8 @@ __global__ __launch_bounds__(256, 2) void lp_schur8_kernel(
         const uint8_t *bs = &ring[kt % kNs8][SA];
         v8i a[4], b[4];
 #pragma unroll
-        for (int bi = 0; bi < 4; ++bi) a[bi] = frag(&as[(wm * 64 + bi * 16 + li) * BK8 + lg * 32]);
+        for (int bi = 0; bi < 4; ++bi)
+            a[bi] = frag(&as[(wm * 64 + 32 * (bi >> 1) + 2 * li + (bi & 1)) * BK8 + lg * 32]);
 #pragma unroll
         for (int bj = 0; bj < 4; ++bj) b[bj] = frag(&bs[(wn * 64 + bj * 16 + li) * BK8 + lg * 32]);
 #pragma unroll
@@ -338,28 +352,40 @@ __global__ __launch_bounds__(256, 2) void lp_schur8_kernel(
                     a[bi], b[bj], acc[bi][bj], 0, 0, 0, 127, 0, 127);
     }
 
+    if (full) {
 #pragma unroll
-    for (int bi = 0; bi < 4; ++bi)
+        for (int pr = 0; pr < 2; ++pr)
 #pragma unroll
-        for (int bj = 0; bj < 4; ++bj) {
-            const int64_t r = row0 + wm * 64 + bi * 16 + 4 * lg;
-            const int64_t c = col0 + wn * 64 + bj * 16 + li;
-            if (full) {
-                const float sc = sL[tix(r)] * sU[tix(c)];
-                uint2 v;
-                v.x = (uint32_t)f32_to_lp<FMT>(-acc[bi][bj][0] * sc) |
-                      ((uint32_t)f32_to_lp<FMT>(-acc[bi][bj][1] * sc) << 16);
-                v.y = (uint32_t)f32_to_lp<FMT>(-acc[bi][bj][2] * sc) |
-                      ((uint32_t)f32_to_lp<FMT>(-acc[bi][bj][3] * sc) << 16);
-                *reinterpret_cast<uint2 *>(&C[(size_t)r + (size_t)c * ldc]) = v;
-            } else if (r < M && c < N) {
-                const float sc = sL[tix(r)] * sU[tix(c)];
+            for (int bj = 0; bj < 4; ++bj) {
+                const int64_t r8 = row0 + wm * 64 + 32 * pr + 8 * lg;
+                const int64_t c = col0 + wn * 64 + bj * 16 + li;
+                const float su = sU[tix(c)];
+                const float sc_lo = sL[tix(r8)] * su, sc_hi = sL[tix(r8 + 4)] * su;
+                uint32_t w4[4];
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    if (r + e < M)
-                        C[(size_t)(r + e) + (size_t)c * ldc] = f32_to_lp<FMT>(-acc[bi][bj][e] * sc);
+                for (int r = 0; r < 4; ++r) {
+                    const float sc = r < 2 ? sc_lo : sc_hi;
+                    w4[r] = (uint32_t)f32_to_lp<FMT>(-acc[2 * pr][bj][r] * sc) |
+                            ((uint32_t)f32_to_lp<FMT>(-acc[2 * pr + 1][bj][r] * sc) << 16);
+                }
+                *reinterpret_cast<uint4 *>(&C[(size_t)r8 + (size_t)c * ldc]) =
+                    make_uint4(w4[0], w4[1], w4[2], w4[3]);
             }
-        }
+    } else {
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj) {
+                const int64_t c = col0 + wn * 64 + bj * 16 + li;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t row = row_of(bi, r);
+                    if (row < M && c < N)
+                        C[(size_t)row + (size_t)c * ldc] =
+                            f32_to_lp<FMT>(-acc[bi][bj][r] * (sL[tix(row)] * sU[tix(c)]));
+                }
+            }
+    }
 }
 
 }  // namespace

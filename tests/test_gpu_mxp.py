@@ -83,7 +83,7 @@ def run_mxp(api, A_h, b_h, **kw):
 
 
 @pytest.mark.parametrize("prec,n,nb", [("bf16", 256, 64), ("fp16", 300, 64), ("bf16", 640, 128),
-                                       ("fp8", 512, 128)])
+                                       ("fp8", 512, 128), ("fp8", 700, 128)])
 def test_lp_factors_against_oracle(api, prec, n, nb):
     note(f"lp factors prec={prec} n={n} nb={nb}")
     A = inputs.diag_dominant_matrix(31 + n, 0, n)
