@@ -165,7 +165,15 @@ const OverlapStreams *overlap_streams() {
             cus = 0;
         if (cus >= 128 && cus <= 1024) {
             uint32_t pm[32] = {}, um[32] = {};
+            // np is kept a multiple of 32 (8 XCDs x 4 shader engines), so that
+            // every shader engine gets the same number of panel CUs; only this
+            // even split is used (a run with an uneven 48-CU split ended in a
+            // device fault)
             const int np = cus / 4;
+            if (np % 32 != 0) {
+                per_dev[dev] = {};
+                return nullptr;
+            }
             for (int i = 0; i < cus; ++i) (i < np ? pm : um)[i / 32] |= 1u << (i % 32);
             const uint32_t words = (uint32_t)((cus + 31) / 32);
             hipStream_t a = nullptr, b = nullptr;

@@ -346,7 +346,8 @@ __global__ __launch_bounds__(256) void panel_leaf_kernel(
 //   * wave reductions use DPP row operations and readlane instead of LDS
 //     permutes.
 // The exchange words are the slots and rows of panel_leaf_kernel, so the two
-// forms can follow each other within one factorization.
+// forms can follow each other within one factorization.  Full leaves only
+// (w = 32): the column loops carry no width checks.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double words_double(const uint32_t *q) {
     return __longlong_as_double((long long)(((uint64_t)q[1] << 32) | q[0]));
@@ -450,7 +451,7 @@ __device__ __forceinline__ void reg_leaf_candidate(RegLeafState<RPT> &st, const 
 template <int RPT, int J>
 __device__ __forceinline__ void reg_leaf_publish_rows(RegLeafState<RPT> &st, const RegLeafArgs &a,
                                                       RegLeafShared &sh) {
-    const int w = a.w;
+    constexpr int w = mxlu::kLeafW;
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
         const int r = a.tid + 256 * q;
@@ -458,7 +459,7 @@ __device__ __forceinline__ void reg_leaf_publish_rows(RegLeafState<RPT> &st, con
         if (st.idx != INT_MAX && rr == st.idx) {
 #pragma unroll
             for (int c = 0; c < mxlu::kLeafW; ++c)
-                if (c < w) {
+                {
                     const uint64_t xb = (uint64_t)__double_as_longlong(st.x[q][c]);
                     sh.crow[2 * c] = (uint32_t)xb;
                     sh.crow[2 * c + 1] = (uint32_t)(xb >> 32);
@@ -467,7 +468,7 @@ __device__ __forceinline__ void reg_leaf_publish_rows(RegLeafState<RPT> &st, con
         if (r < a.rows && rr == J) {
 #pragma unroll
             for (int c = 0; c < mxlu::kLeafW; ++c)
-                if (c < w) {
+                {
                     const uint64_t xb = (uint64_t)__double_as_longlong(st.x[q][c]);
                     sh.jrow[2 * c] = (uint32_t)xb;
                     sh.jrow[2 * c + 1] = (uint32_t)(xb >> 32);
@@ -494,7 +495,7 @@ __device__ __forceinline__ void reg_leaf_update(RegLeafState<RPT> &st, const Reg
         if (r < a.rows && a.rb + r > JP) {
 #pragma unroll
             for (int c = JP + 1; c < mxlu::kLeafW; ++c)
-                if (c >= c0 && c < c1 && c < a.w)
+                if (c >= c0 && c < c1)
                     st.x[q][c] = fma(-st.l[q], words_double(&prow[2 * c]), st.x[q][c]);
         }
     }
@@ -508,7 +509,8 @@ __device__ __forceinline__ const uint32_t *reg_leaf_column(RegLeafState<RPT> &st
                                                            const RegLeafArgs &a,
                                                            RegLeafShared &sh) {
     constexpr int R = 256 * RPT;
-    const int tid = a.tid, lane = a.lane, wave = a.wave, w = a.w, G = a.G;
+    const int tid = a.tid, lane = a.lane, wave = a.wave, G = a.G;
+    constexpr int w = mxlu::kLeafW;
     const uint32_t seq = (uint32_t)(a.r0 + J + 1);
     uint64_t *gs = a.slots + (size_t)(J & 1) * mxlu::kMaxGroups * kSlotWords;
     uint64_t *grj = a.rowj + (J & 1) * kRowWords;
@@ -599,11 +601,11 @@ __device__ __forceinline__ const uint32_t *reg_leaf_column(RegLeafState<RPT> &st
         if (swap && rr == J) {
 #pragma unroll
             for (int c = 0; c < mxlu::kLeafW; ++c)
-                if (c < w) st.x[q][c] = words_double(&prow[2 * c]);
+                st.x[q][c] = words_double(&prow[2 * c]);
         } else if (swap && rr == p) {
 #pragma unroll
             for (int c = 0; c < mxlu::kLeafW; ++c)
-                if (c < w) st.x[q][c] = words_double(&sh.rowj[2 * c]);
+                st.x[q][c] = words_double(&sh.rowj[2 * c]);
         }
         st.l[q] = 0.0;
         if (r < a.rows && rr > J) {
@@ -622,9 +624,9 @@ template <int RPT, int J>
 struct RegLeafSteps {
     static __device__ __forceinline__ void run(RegLeafState<RPT> &st, const RegLeafArgs &a,
                                                RegLeafShared &sh) {
-        if (J < a.w) {
+        {
             const uint32_t *prow = reg_leaf_column<RPT, J>(st, a, sh);
-            if (J + 1 < a.w) {
+            if (J + 1 < mxlu::kLeafW) {
                 constexpr int JN = (J + 1 < mxlu::kLeafW) ? J + 1 : J;
                 reg_leaf_update<RPT, J>(st, a, prow, J + 1, J + 2);
                 reg_leaf_candidate<RPT, JN>(st, a, sh);
@@ -669,7 +671,7 @@ __global__ __launch_bounds__(256) void panel_leaf_reg_kernel(int m, int w, doubl
 #pragma unroll
         for (int c = 0; c < mxlu::kLeafW; ++c) {
             const int r = a.tid + 256 * q;
-            st.x[q][c] = (r < a.rows && c < w) ? P[(size_t)(a.rb + r) + (size_t)c * lda] : 0.0;
+            st.x[q][c] = (r < a.rows) ? P[(size_t)(a.rb + r) + (size_t)c * lda] : 0.0;
         }
     reg_leaf_candidate<RPT, 0>(st, a, sh);
     reg_leaf_publish_rows<RPT, 0>(st, a, sh);
@@ -679,7 +681,7 @@ __global__ __launch_bounds__(256) void panel_leaf_reg_kernel(int m, int w, doubl
 #pragma unroll
         for (int c = 0; c < mxlu::kLeafW; ++c) {
             const int r = a.tid + 256 * q;
-            if (r < a.rows && c < w) P[(size_t)(a.rb + r) + (size_t)c * lda] = st.x[q][c];
+            if (r < a.rows) P[(size_t)(a.rb + r) + (size_t)c * lda] = st.x[q][c];
         }
 }
 
@@ -1132,7 +1134,7 @@ int panel_leaf(int64_t m, int w, T *P, int64_t ldp, int64_t r0, int32_t *ipiv,
         set_error_msg("panel_leaf: bad shape");
         return MXLU_E_NOMEM;
     }
-    if (sizeof(T) == 8) {
+    if (sizeof(T) == 8 && w == kLeafW) {
         int64_t Gr = 0;
         const int rpt = reg_leaf_plan(m, ex.group_cap, &Gr);
         if (rpt) {
