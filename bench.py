@@ -219,7 +219,7 @@ def run_mxp(args, cfg, name):
     b = torch.from_numpy(inputs.uniform_matrix(seed, inputs.STREAM_B, n, 1)[:, 0]).cuda()
     X = torch.empty(n, dtype=torch.float64, device="cuda")
     opts = api.mxp_options(prec=prec, nb=nb, refine="gmres", scale_tile=128)
-    work = torch.empty(api.mxp_workspace_bytes(n, opts), dtype=torch.uint8, device="cuda")
+    work = torch.empty(api.mxp_workspace_bytes(n, opts, n), dtype=torch.uint8, device="cuda")
     torch.cuda.synchronize()
     for w in range(args.warmup):
         _, rep, _, _ = api.mxp_solve(A, b, X=X, work=work, opts=opts)

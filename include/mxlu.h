@@ -78,6 +78,36 @@ int lu_factor(int64_t n, int64_t nb, double *A, int64_t lda, int32_t *ipiv,
 int mxlu_set_lookahead(int depth);
 
 /*
+ * mxlu_release -- destroys what the library keeps between calls: the two
+ * CU-masked streams of the look-ahead (per device) and the pooled timing
+ * events.  They are created again on demand.  Call it only while no library
+ * work is in flight; it also runs at process exit (registered when the
+ * streams are first created, so before the HIP runtime's own teardown).
+ * Returns 0.
+ *
+ * Residency.  The panel kernels' workgroups exchange pivot candidates while
+ * running, so all of them must be resident at once: the planner sizes them
+ * to the CUs they may use (all CUs on the caller's stream; a quarter of the
+ * CUs, capped at 7/8 of those, on the look-ahead's panel stream).  Kernels of
+ * other processes or other streams that hold those CUs can delay the panel;
+ * its waits are bounded, and when one expires lu_factor returns
+ * MXLU_E_TIMEOUT (the factors are then invalid, but every access stays
+ * inside A and ipiv).  Look-ahead factorizations of one process are
+ * serialised (they share the masked streams).
+ */
+int mxlu_release(void);
+
+/*
+ * mxlu_debug_expire_waits -- test hook, process-wide (0 = off, the default):
+ * when on, every panel factorization starts as if one of its bounded waits
+ * had already expired, so each wait gives up at its first check and every
+ * kernel runs to completion; the call then returns MXLU_E_TIMEOUT.  Lets
+ * tests exercise that path without delaying any kernel.  Returns 0, or -1
+ * for a value other than 0 or 1.
+ */
+int mxlu_debug_expire_waits(int on);
+
+/*
  * lu_solve -- triangular solves with the factors of lu_factor (Sec. III-A.1).
  *   trans = 0: solves A X = B  (apply P, L y = P b, U x = y)
  *   trans = 1: solves A^T X = B (U^T y = b, L^T z = y, x = P^T z)
@@ -87,6 +117,19 @@ int mxlu_set_lookahead(int depth);
 int lu_solve(int64_t n, int64_t nrhs, const double *LU, int64_t lda,
              const int32_t *ipiv, double *B, int64_t ldb, int trans,
              void *stream);
+
+/*
+ * mxlu_panel_factor_f64 -- the PFACT phase on its own (Sec. III-A.1: the
+ * panel factorization with partial pivoting): GEPP of the m x nb panel P
+ * (FP64, column-major, leading dimension ldp, m >= nb, nb <= 1024) in place,
+ * with the pivot rules of lu_factor.  ipiv (nb int32, device) receives the
+ * interchange sequence, 0-based rows of the panel; every interchange is
+ * applied to the whole panel row.  Returns 0, the 1-based first exactly-zero
+ * pivot column, -k for an invalid argument, or MXLU_E_*.  Synchronises
+ * `stream` once at the end.
+ */
+int mxlu_panel_factor_f64(int64_t m, int64_t nb, double *P, int64_t ldp, int32_t *ipiv,
+                          void *stream);
 
 /*
  * mxlu_schur_update_f64 -- the DGEMM phase on its own (Sec. III-A.1: update
@@ -130,6 +173,10 @@ typedef struct {
                                 with the same A, n, opts: skip conversion and LU */
     int32_t trans;           /* 0: solve A X = B; 1: solve A^T X = B */
     int32_t x_init;          /* 0: x0 = M b; 1: X holds the initial guess */
+    int32_t factor_steps;    /* > 0: stop the factorization after this many panel
+                                steps, leaving the trailing block updated but
+                                unfactored (a partial LU whose trailing block is
+                                the Schur complement); 0: factor completely */
 } mxp_opts;
 
 typedef struct {
@@ -142,15 +189,17 @@ typedef struct {
 } mxp_report;
 
 /* Fill *opts with the defaults: BF16, no pivoting, nb 512, GMRES, restart 30,
- * max_outer 20, max_inner_total 300, inner_tol 1e-6, threshold 16, tile 128. */
+ * max_outer 20, max_inner_total 300, inner_tol 1e-6, threshold 16, tile 128,
+ * complete factorization. */
 void mxp_default_opts(mxp_opts *opts);
 
-/* Bytes of caller workspace mxp_solve needs for order n, or 0 when the size
- * overflows.  The workspace starts with the low-precision factors: an n x n
+/* Bytes of caller workspace mxp_solve needs for order n with the FP64 matrix
+ * at leading dimension lda (>= n), or 0 when an argument is invalid or the
+ * size overflows.  The workspace starts with the low-precision factors: an n x n
  * column-major array of 16-bit words (bf16 for MXLU_PREC_BF16, fp16 for the
  * other two precisions) with leading dimension mxp_factor_ld(n), holding L
  * (unit lower, below the diagonal) and U (upper), as lu_factor does in FP64. */
-size_t mxp_workspace_bytes(int64_t n, const mxp_opts *opts);
+size_t mxp_workspace_bytes(int64_t n, int64_t lda, const mxp_opts *opts);
 int64_t mxp_factor_ld(int64_t n);
 
 /*
@@ -221,6 +270,32 @@ int mxlu_scaled_residual(int64_t n, int64_t nrhs, const double *A, int64_t lda,
 int mxlu_profile_enable(int on);
 int mxlu_profile_reset(void);
 int mxlu_profile_read(double *ms, double *work, int64_t *count, int nphase);
+
+/*
+ * Planning helpers: host arithmetic only (no device access), the rules the
+ * library applies with the current device's facts; exposed for tests.
+ *   mxlu_plan_panel_cus: CUs given to the look-ahead's panel stream on a
+ *     device with `cus` CUs: cus / 4 when that is a multiple of 32 (an equal
+ *     number in every shader engine of an 8-XCD, 4-engine-per-XCD part),
+ *     else 0 (no look-ahead).
+ *   mxlu_plan_panel_leaf: form of the panel leaf for m rows when at most
+ *     `cap` CUs may hold it (0: all `cus`), with occ_reg1 / occ_reg2
+ *     workgroups per CU for the register forms (0: not available),
+ *     lds_budget bytes of dynamic LDS for the LDS form and elements of
+ *     elem_bytes (4 or 8; the register forms are FP64 only).  Returns
+ *     1 or 2 (register form, rows per thread), 3 (LDS form), 0 (no form
+ *     fits: the call would fail with MXLU_E_NOMEM), -1 (bad argument);
+ *     *rows_per_group and *groups receive the geometry.
+ *   mxlu_plan_lookahead: CUs of the panel stream when lu_factor(n, nb) runs
+ *     look-ahead depth 1 on such a device (given 16-byte aligned A and even
+ *     lda), else 0.
+ */
+int mxlu_plan_panel_cus(int cus);
+int mxlu_plan_panel_leaf(int64_t m, int cap, int cus, int occ_reg1, int occ_reg2,
+                         int64_t lds_budget, int elem_bytes, int64_t *rows_per_group,
+                         int64_t *groups);
+int mxlu_plan_lookahead(int64_t n, int64_t nb, int cus, int occ_reg1, int occ_reg2,
+                        int64_t lds_budget);
 
 /* Static description of a status code. */
 const char *mxlu_status_string(int status);

@@ -79,6 +79,8 @@ def _bind(L):
     i64, i32, dp = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p
     L.oracle_getrf_steps.argtypes = [i64, i64, dp, i64, dp, i64]
     L.oracle_getrf_steps.restype = i32
+    L.oracle_getrf_gaps.argtypes = [i64, i64, dp, i64, dp, dp]
+    L.oracle_getrf_gaps.restype = i32
     L.oracle_threads.argtypes = []
     L.oracle_threads.restype = i32
     L.oracle_panel_getf2.argtypes = [i64, i64, dp, i64, dp]
@@ -93,6 +95,8 @@ def _bind(L):
     L.oracle_fp8_scale.restype = ctypes.c_double
     L.oracle_lp_getrf.argtypes = [i64, i64, i32, i32, i64, dp, i64, dp]
     L.oracle_lp_getrf.restype = i32
+    L.oracle_lp_getrf_steps.argtypes = [i64, i64, i32, i32, i64, dp, i64, dp, i64]
+    L.oracle_lp_getrf_steps.restype = i32
     L.oracle_lp_precond.argtypes = [i64, dp, i64, dp, dp, dp, i32]
     L.oracle_lp_precond.restype = i32
     return L
@@ -137,6 +141,20 @@ def getrf(A, nb, max_steps=-1):
     return LU, ipiv, info
 
 
+def getrf_gaps_inplace(A, nb):
+    """getrf in place on a Fortran-ordered FP64 array, also returning the
+    relative gap between the two largest candidates of every pivot search.
+    Returns (ipiv, gaps, info)."""
+    assert A.dtype == np.float64 and A.flags["F_CONTIGUOUS"]
+    n = A.shape[0]
+    ipiv = np.arange(n, dtype=np.int32)
+    gaps = np.zeros(n, dtype=np.float64)
+    info = lib().oracle_getrf_gaps(n, int(nb), _ptr(A), max(n, 1), _ptr(ipiv), _ptr(gaps))
+    if info < 0:
+        raise ValueError(f"oracle_getrf_gaps: bad argument ({info})")
+    return ipiv, gaps, info
+
+
 def panel_getrf(P):
     """GEPP of an m x kb panel (the first PFACT step).  Returns (LU, ipiv, info)."""
     LU = _fortran(P)
@@ -176,15 +194,18 @@ def fp8_scale(amax):
     return lib().oracle_fp8_scale(float(amax))
 
 
-def lp_getrf(A, nb, prec, pivot=False, tile=128):
+def lp_getrf(A, nb, prec, pivot=False, tile=128, max_steps=-1):
     """Low-precision blocked LU (Sec. III-A.2).  prec: 0 bf16, 1 fp16, 2 fp8
     updates with fp16 storage.  Returns (F, ipiv or None, info) where F holds
-    the stored factor values as FP64 numbers."""
+    the stored factor values as FP64 numbers.  max_steps >= 0 stops after that
+    many panel steps (the trailing block then holds the updated, unfactored
+    Schur complement in storage precision)."""
     F = _fortran(A)
     n = F.shape[0]
     ipiv = np.arange(n, dtype=np.int32)
-    info = lib().oracle_lp_getrf(n, int(nb), int(prec), 1 if pivot else 0,
-                                 int(tile), _ptr(F), max(n, 1), _ptr(ipiv))
+    info = lib().oracle_lp_getrf_steps(n, int(nb), int(prec), 1 if pivot else 0,
+                                       int(tile), _ptr(F), max(n, 1), _ptr(ipiv),
+                                       int(max_steps))
     if info < 0:
         raise ValueError(f"oracle_lp_getrf failed ({info})")
     return F, (ipiv if pivot else None), info

@@ -10,16 +10,19 @@
  * fma()/fmaf() so that the rounding is a stated property of the code, and the
  * file is compiled with -ffp-contract=off so the compiler adds no others.
  *
- * What is computed (Sec. III-A.1 of the paper: "LU factorization with partial
- * pivoting, followed by triangular solves"; the five phases PFACT, SWAP, DTRSM,
- * DGEMM of the right-looking blocked algorithm; Sec. III-A.2 for the
+ * What is computed (Sec. III-A.1 of the paper: Gaussian elimination with
+ * row partial pivoting, then the two triangular solves with the factors; the
+ * phases PFACT, SWAP, DTRSM, DGEMM of the right-looking blocked algorithm;
+ * Sec. III-A.2 for the
  * mixed-precision variant: low-precision factorization and trailing updates,
  * no pivoting, FP64 residuals and corrections):
  *
  *   oracle_getrf      blocked right-looking GEPP, panel width nb
+ *   oracle_getrf_gaps the same, with the relative gap of every pivot search
  *   oracle_getrs      solve with the factors, A x = b or A^T x = b
  *   oracle_round      round an FP64 value to bf16 / fp16 / e4m3fn (RNE)
  *   oracle_lp_getrf   low-precision blocked LU (storage in bf16 or fp16,
+ *                     all steps, or the first max_steps: oracle_lp_getrf_steps,
  *                     FP32 panel/TRSM, BF16/FP16 or FP8-with-tile-scales
  *                     trailing update), with or without partial pivoting
  *   oracle_lp_precond apply M = U^-1 L^-1 P (or its transpose) in FP32
@@ -61,7 +64,7 @@ static void swap_rows(double *A, int64_t lda, int64_t r1, int64_t r2,
  * An exactly zero pivot column is left unscaled and recorded in *info.
  */
 static void panel_getf2(int64_t n, int64_t k0, int64_t kb, double *A,
-                        int64_t lda, int32_t *ipiv, int *info)
+                        int64_t lda, int32_t *ipiv, int *info, double *gaps)
 {
     for (int64_t j = k0; j < k0 + kb; ++j) {
         int64_t p = j;
@@ -69,6 +72,15 @@ static void panel_getf2(int64_t n, int64_t k0, int64_t kb, double *A,
         for (int64_t i = j + 1; i < n; ++i) {
             double v = fabs(A[IDX(i, j, lda)]);
             if (v > best) { best = v; p = i; }
+        }
+        if (gaps) {   /* relative gap to the runner-up candidate */
+            double second = -1.0;
+            for (int64_t i = j; i < n; ++i) {
+                double v = fabs(A[IDX(i, j, lda)]);
+                if (i != p && v > second) second = v;
+            }
+            gaps[j] = (second < 0.0) ? 1.0
+                    : (best > 0.0 ? (best - second) / best : 0.0);
         }
         ipiv[j] = (int32_t)p;
         if (A[IDX(p, j, lda)] != 0.0) {
@@ -94,11 +106,12 @@ static void panel_getf2(int64_t n, int64_t k0, int64_t kb, double *A,
  * width kb: PFACT, SWAP on the columns outside the panel, DTRSM for the block
  * row U12 = L11^-1 A12 (forward substitution, unit lower), and the trailing
  * DGEMM A22 -= L21 U12 with the k index summed in ascending order.
+ * gaps (optional) receives the pivot searches' relative gaps (panel_getf2).
  */
 static void getrf_step(int64_t n, int64_t k0, int64_t kb, double *A,
-                       int64_t lda, int32_t *ipiv, int *info)
+                       int64_t lda, int32_t *ipiv, int *info, double *gaps)
 {
-    panel_getf2(n, k0, kb, A, lda, ipiv, info);
+    panel_getf2(n, k0, kb, A, lda, ipiv, info, gaps);
 
     /* SWAP: apply this panel's interchanges, in order, to the other columns */
     #pragma omp parallel for schedule(static)
@@ -141,8 +154,8 @@ static void getrf_step(int64_t n, int64_t k0, int64_t kb, double *A,
  * `max_steps` panel steps only when max_steps >= 0 (used to time a bounded
  * sample of a large factorization); max_steps < 0 runs them all.
  */
-int oracle_getrf_steps(int64_t n, int64_t nb, double *A, int64_t lda,
-                       int32_t *ipiv, int64_t max_steps)
+static int getrf_blocked(int64_t n, int64_t nb, double *A, int64_t lda,
+                         int32_t *ipiv, int64_t max_steps, double *gaps)
 {
     if (n < 0 || nb < 1 || lda < (n > 1 ? n : 1)) return -1;
     int info = 0;
@@ -150,9 +163,30 @@ int oracle_getrf_steps(int64_t n, int64_t nb, double *A, int64_t lda,
     for (int64_t k0 = 0; k0 < n; k0 += nb, ++step) {
         if (max_steps >= 0 && step >= max_steps) break;
         int64_t kb = (n - k0 < nb) ? (n - k0) : nb;
-        getrf_step(n, k0, kb, A, lda, ipiv, &info);
+        getrf_step(n, k0, kb, A, lda, ipiv, &info, gaps);
     }
     return info;
+}
+
+int oracle_getrf_steps(int64_t n, int64_t nb, double *A, int64_t lda,
+                       int32_t *ipiv, int64_t max_steps)
+{
+    return getrf_blocked(n, nb, A, lda, ipiv, max_steps, NULL);
+}
+
+/*
+ * The same factorization, also reporting for every column j the relative gap
+ * between the two largest candidate magnitudes of its pivot search,
+ * gaps[j] = (|a_pj| - max_{i >= j, i != p} |a_ij|) / |a_pj| (1 for a single
+ * candidate, 0 for a zero column).  A tiny gap marks a column where another
+ * rounding order may legally pick the other row; the pivot comparison uses it
+ * at sizes where re-running the oracle per mismatch is too slow.
+ */
+int oracle_getrf_gaps(int64_t n, int64_t nb, double *A, int64_t lda,
+                      int32_t *ipiv, double *gaps)
+{
+    if (!gaps) return -6;
+    return getrf_blocked(n, nb, A, lda, ipiv, -1, gaps);
 }
 
 /* Threads the OpenMP loops of this file use. */
@@ -172,7 +206,7 @@ int oracle_panel_getf2(int64_t m, int64_t kb, double *A, int64_t lda, int32_t *i
 {
     if (m < 0 || kb < 0 || kb > m || lda < (m > 1 ? m : 1)) return -1;
     int info = 0;
-    panel_getf2(m, 0, kb, A, lda, ipiv, &info);
+    panel_getf2(m, 0, kb, A, lda, ipiv, &info, NULL);
     return info;
 }
 
@@ -317,8 +351,8 @@ double oracle_fp8_scale(double amax)
  */
 static float to_f32(double v) { return (float)v; }   /* exact for stored values */
 
-int oracle_lp_getrf(int64_t n, int64_t nb, int prec, int pivot, int64_t tile,
-                    double *S, int64_t lds, int32_t *ipiv)
+int oracle_lp_getrf_steps(int64_t n, int64_t nb, int prec, int pivot, int64_t tile,
+                          double *S, int64_t lds, int32_t *ipiv, int64_t max_steps)
 {
     if (n < 0 || nb < 1 || lds < (n > 1 ? n : 1)) return -1;
     if (prec < 0 || prec > 2 || tile < 1) return -3;
@@ -344,7 +378,9 @@ int oracle_lp_getrf(int64_t n, int64_t nb, int prec, int pivot, int64_t tile,
         return -1000;
     }
 
-    for (int64_t k0 = 0; k0 < n; k0 += nb) {
+    int64_t step = 0;
+    for (int64_t k0 = 0; k0 < n; k0 += nb, ++step) {
+        if (max_steps >= 0 && step >= max_steps) break;
         int64_t kb = (n - k0 < nb) ? (n - k0) : nb;
         int64_t m = n - k0;
         /* PFACT in FP32; P is the m x kb panel, leading dimension m */
@@ -474,6 +510,13 @@ int oracle_lp_getrf(int64_t n, int64_t nb, int prec, int pivot, int64_t tile,
     }
     free(P); free(Lq); free(Uq); free(sL); free(sU);
     return info;
+}
+
+/* The complete low-precision factorization (all panel steps). */
+int oracle_lp_getrf(int64_t n, int64_t nb, int prec, int pivot, int64_t tile,
+                    double *S, int64_t lds, int32_t *ipiv)
+{
+    return oracle_lp_getrf_steps(n, nb, prec, pivot, tile, S, lds, ipiv, -1);
 }
 
 /*

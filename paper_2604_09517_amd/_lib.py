@@ -26,6 +26,7 @@ class MxpOpts(ctypes.Structure):
         ("restart", _i32), ("max_outer", _i32), ("max_inner_total", _i32),
         ("inner_tol", _dbl), ("resid_threshold", _dbl), ("scale_tile", _i32),
         ("reuse_factors", _i32), ("trans", _i32), ("x_init", _i32),
+        ("factor_steps", _i32),
     ]
 
 
@@ -41,12 +42,19 @@ class MxpReport(ctypes.Structure):
 SIGNATURES = {
     "lu_factor": (_int, [_i64, _i64, _vp, _i64, _vp, _vp]),
     "mxlu_set_lookahead": (_int, [_int]),
+    "mxlu_release": (_int, []),
+    "mxlu_debug_expire_waits": (_int, [_int]),
+    "mxlu_panel_factor_f64": (_int, [_i64, _i64, _vp, _i64, _vp, _vp]),
+    "mxlu_plan_panel_cus": (_int, [_int]),
+    "mxlu_plan_panel_leaf": (_int, [_i64, _int, _int, _int, _int, _i64, _int,
+                                    ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
+    "mxlu_plan_lookahead": (_int, [_i64, _i64, _int, _int, _int, _i64]),
     "lu_solve": (_int, [_i64, _i64, _vp, _i64, _vp, _vp, _i64, _int, _vp]),
     "mxlu_schur_update_f64": (_int, [_i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp]),
     "mxlu_outer_update_f64": (_int, [_i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _int,
                                      _vp]),
     "mxp_default_opts": (None, [ctypes.POINTER(MxpOpts)]),
-    "mxp_workspace_bytes": (_sz, [_i64, ctypes.POINTER(MxpOpts)]),
+    "mxp_workspace_bytes": (_sz, [_i64, _i64, ctypes.POINTER(MxpOpts)]),
     "mxp_factor_ld": (_i64, [_i64]),
     "mxp_convert": (_int, [_i32, _i64, _i64, _vp, _i64, _vp, _i64, _vp]),
     "mxp_solve": (_int, [_i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _sz, _vp,

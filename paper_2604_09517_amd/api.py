@@ -72,6 +72,28 @@ def lu_factor(A, nb=256, ipiv=None):
     return A, ipiv, info
 
 
+def panel_factor(P, ipiv=None):
+    """In-place GEPP of an m x nb FP64 panel (the PFACT phase alone).
+    Returns (P, ipiv with 0-based panel rows, info)."""
+    pp, m, nb, ldp = _mat(P, "P")
+    if ipiv is None:
+        ipiv = torch.empty(nb, dtype=torch.int32, device=P.device)
+    pi, _, _, _ = _mat(ipiv, "ipiv", torch.int32)
+    rc = lib().mxlu_panel_factor_f64(m, nb, pp, ldp, pi, _stream())
+    info = check("mxlu_panel_factor_f64", rc, positive_ok=True)
+    return P, ipiv, info
+
+
+def release():
+    """Destroy the library's cached streams and events (no work in flight)."""
+    check("mxlu_release", lib().mxlu_release())
+
+
+def debug_expire_waits(on):
+    """Test hook: panel factorizations start with their waits expired."""
+    check("mxlu_debug_expire_waits", lib().mxlu_debug_expire_waits(1 if on else 0))
+
+
 def lu_solve(LU, ipiv, B, trans=False):
     """In-place solve A X = B (or A^T X = B) with the factors of lu_factor."""
     pl, n, _, lda = _mat(LU, "LU")
@@ -142,7 +164,7 @@ REFINE = {"classical": 0, "gmres": 1}
 
 def mxp_options(prec="bf16", pivot=False, nb=512, refine="gmres", restart=30, max_outer=20,
                 max_inner_total=300, inner_tol=1e-6, resid_threshold=16.0, scale_tile=128,
-                reuse_factors=False, trans=False, x_init=False):
+                reuse_factors=False, trans=False, x_init=False, factor_steps=0):
     o = MxpOpts()
     lib().mxp_default_opts(ctypes.byref(o))
     o.prec = PREC[prec] if isinstance(prec, str) else int(prec)
@@ -158,11 +180,13 @@ def mxp_options(prec="bf16", pivot=False, nb=512, refine="gmres", restart=30, ma
     o.reuse_factors = 1 if reuse_factors else 0
     o.trans = 1 if trans else 0
     o.x_init = 1 if x_init else 0
+    o.factor_steps = int(factor_steps)
     return o
 
 
-def mxp_workspace_bytes(n, opts):
-    return int(lib().mxp_workspace_bytes(int(n), ctypes.byref(opts)))
+def mxp_workspace_bytes(n, opts, lda=None):
+    lda = max(1, int(n)) if lda is None else int(lda)
+    return int(lib().mxp_workspace_bytes(int(n), lda, ctypes.byref(opts)))
 
 
 def mxp_factor_ld(n):
@@ -200,7 +224,7 @@ def mxp_solve(A, B, X=None, work=None, ipiv=None, opts=None, allow_notconv=False
         X = fortran_empty(n, nrhs, device=A.device) if B.dim() == 2 else torch.empty(
             n, dtype=torch.float64, device=A.device)
     px, _, _, ldx = _mat(X, "X")
-    need = mxp_workspace_bytes(n, opts)
+    need = mxp_workspace_bytes(n, opts, lda)
     if work is None:
         work = torch.empty(max(1, need), dtype=torch.uint8, device=A.device)
     if opts.pivot and ipiv is None:

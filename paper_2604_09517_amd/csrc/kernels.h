@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 
 namespace mxlu {
@@ -49,14 +50,30 @@ constexpr int kMaxGroups = 256;   // workgroups of one leaf kernel (<= CUs)
 // (they must all be resident at once), or -1 when no geometry fits.
 template <typename T> int panel_leaf_groups(int64_t m, int cap);
 
+// Inputs of the leaf planner: the CUs the leaf may use (cap > 0: that many,
+// else all `cus`), workgroups of the register form per CU (0: form not
+// available), dynamic LDS per workgroup of the LDS form, element size.
+struct LeafDevice {
+    int cap, cus, occ_reg1, occ_reg2, elem_bytes;
+    int64_t lds_budget;
+};
+enum { kLeafNone = 0, kLeafReg1 = 1, kLeafReg2 = 2, kLeafLds = 3 };
+// Form (kLeaf*) and geometry (rows per group R, groups G) of an m-row leaf;
+// host arithmetic only.
+int leaf_plan(int64_t m, const LeafDevice &d, int64_t *R, int64_t *G);
+// The current device's facts for the FP64 leaf with group cap `cap`.
+int leaf_device_f64(int cap, LeafDevice *d);
+
 template <typename T>
 int panel_leaf(int64_t m, int w, T *P, int64_t ldp, int64_t r0, int32_t *ipiv,
                const PanelExchange &ex, hipStream_t s);
 
-// Interchanges ipiv[j0 .. j0+cnt) (rows >= j0, cnt <= 1024) composed into a
-// list of row moves, then applied to the columns c_begin + q (q < ncols,
-// skipping [skip_begin, skip_begin + skip_len)) of a matrix of T.
-int swap_compose(const int32_t *ipiv, int64_t j0, int cnt, int *moves, hipStream_t s);
+// Interchanges ipiv[j0 .. j0+cnt) (rows >= j0, cnt <= 1024, of a matrix with
+// nrows rows) composed into a list of row moves, then applied to the columns
+// c_begin + q (q < ncols, skipping [skip_begin, skip_begin + skip_len)) of a
+// matrix of T.  An interchange row outside [j0 + t, nrows) counts as none.
+int swap_compose(const int32_t *ipiv, int64_t j0, int cnt, int64_t nrows, int *moves,
+                 hipStream_t s);
 template <typename T>
 int swap_apply(T *A, int64_t lda, int64_t j0, const int *moves, int64_t c_begin, int64_t ncols,
                int64_t skip_begin, int64_t skip_len, hipStream_t s);
@@ -65,7 +82,7 @@ int swap_apply(T *A, int64_t lda, int64_t j0, const int *moves, int64_t c_begin,
 // the columns c_begin + q (q < ncols, skipping [skip_begin, skip_begin +
 // skip_len)).  `moves` is a device buffer of kSwapMovesInts ints.
 constexpr int kSwapMovesInts = 1 + 4 * 1024;
-int laswp_f64(double *A, int64_t lda, const int32_t *ipiv, int64_t j0, int cnt,
+int laswp_f64(double *A, int64_t lda, int64_t nrows, const int32_t *ipiv, int64_t j0, int cnt,
               int64_t c_begin, int64_t ncols, int64_t skip_begin, int64_t skip_len,
               int *moves, hipStream_t s);
 
@@ -85,6 +102,7 @@ int trsm_lltu_f64(int kb, int64_t ncols, const double *L, int64_t ldl, double *B
                   int64_t ldb, hipStream_t s);
 
 class Scratch;
+extern std::atomic<int> g_expire_waits;
 // Zeroed exchange area of the panel kernels for a matrix of order n.
 int alloc_panel_exchange(Scratch &scratch, int64_t n, PanelExchange *ex, hipStream_t s);
 // GEPP of the m x kb panel P (recursive; leaves are panel_leaf<T>); element

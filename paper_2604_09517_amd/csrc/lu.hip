@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cstdlib>
 #include <mutex>
 
 #include "common.h"
@@ -76,7 +77,7 @@ int panel_rec(const PanelCtx<T> &f, int64_t c, int64_t w) {
         MXLU_TRY(panel_leaf<T>(f.m - c, (int)w, P + (size_t)c + (size_t)c * ldp, ldp, f.ibase + c,
                           f.ipiv, f.ex, f.s));
         if (f.kb > w) {
-            MXLU_TRY(swap_compose(f.ipiv, f.ibase + c, (int)w, f.moves, f.s));
+            MXLU_TRY(swap_compose(f.ipiv, f.ibase + c, (int)w, f.ibase + f.m, f.moves, f.s));
             MXLU_TRY(swap_apply<T>(P, ldp, c, f.moves, 0, f.kb - w, c, w, f.s));
         }
         return 0;
@@ -109,6 +110,9 @@ template int panel_factor<double>(double *, int64_t, int64_t, int64_t, int64_t, 
 template int panel_factor<float>(float *, int64_t, int64_t, int64_t, int64_t, int32_t *,
                                  const PanelExchange &, int *, hipStream_t);
 
+// Test hook (mxlu_debug_expire_waits): panel exchanges start expired.
+std::atomic<int> g_expire_waits{0};
+
 int alloc_panel_exchange(Scratch &scratch, int64_t n, PanelExchange *ex, hipStream_t s) {
     const size_t slot_words = (size_t)2 * kMaxGroups * (2 * kLeafW + 4);
     const size_t rowj_words = (size_t)2 * 2 * kLeafW;
@@ -122,6 +126,8 @@ int alloc_panel_exchange(Scratch &scratch, int64_t n, PanelExchange *ex, hipStre
     MXLU_HIP_TRY(hipMemsetAsync(ex->slots, 0, sizeof(uint64_t) * slot_words, s));
     MXLU_HIP_TRY(hipMemsetAsync(ex->rowj, 0, sizeof(uint64_t) * rowj_words, s));
     MXLU_HIP_TRY(hipMemsetAsync(ex->flags, 0, sizeof(int) * 4, s));
+    if (g_expire_waits.load())   // as if a wait had already expired
+        MXLU_HIP_TRY(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(ex->flags + 1), 1, 1, s));
     return 0;
 }
 }  // namespace mxlu
@@ -140,54 +146,70 @@ std::atomic<int> g_lookahead{1};
 // each, so these are the first two CUs of every shader engine (present
 // however the engines are harvested); a driver that numbers the bits
 // XCD-major would give it two whole XCDs instead, also cus/4 CUs.  Created
-// once per device with the default priority; kept for the life of the
-// process.
+// once per device with the default priority; released by mxlu_release (also
+// run at process exit, before the HIP runtime's own teardown).
 struct OverlapStreams {
     hipStream_t panel = nullptr, update = nullptr;
     int panel_cus = 0, update_cus = 0;
 };
 
+constexpr int kMaxDev = 64;
+std::mutex g_streams_mu;
+OverlapStreams g_streams[kMaxDev];
+bool g_streams_tried[kMaxDev] = {};
+bool g_atexit_registered = false;
+
+// One look-ahead factorization at a time per process: the masked streams and
+// their CUs are shared by every call.
+std::mutex g_lookahead_mu;
+
+void release_streams() {
+    std::lock_guard<std::mutex> lk(g_streams_mu);
+    for (int d = 0; d < kMaxDev; ++d) {
+        if (g_streams[d].panel) (void)hipStreamDestroy(g_streams[d].panel);
+        if (g_streams[d].update) (void)hipStreamDestroy(g_streams[d].update);
+        g_streams[d] = {};
+        g_streams_tried[d] = false;
+    }
+    (void)hipGetLastError();
+}
+
+void release_at_exit() { (void)mxlu_release(); }
+
 const OverlapStreams *overlap_streams() {
-    constexpr int kMaxDev = 64;
-    static std::mutex mu;
-    static OverlapStreams per_dev[kMaxDev];
-    static bool tried[kMaxDev] = {};
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev) {
         (void)hipGetLastError();
         return nullptr;
     }
-    std::lock_guard<std::mutex> lk(mu);
-    if (!tried[dev]) {
-        tried[dev] = true;
+    std::lock_guard<std::mutex> lk(g_streams_mu);
+    if (!g_streams_tried[dev]) {
+        g_streams_tried[dev] = true;
         int cus = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             cus = 0;
-        if (cus >= 128 && cus <= 1024) {
+        const int np = mxlu_plan_panel_cus(cus);
+        if (np > 0) {
             uint32_t pm[32] = {}, um[32] = {};
-            // np is kept a multiple of 32 (8 XCDs x 4 shader engines), so that
-            // every shader engine gets the same number of panel CUs; only this
-            // even split is used (a run with an uneven 48-CU split ended in a
-            // device fault)
-            const int np = cus / 4;
-            if (np % 32 != 0) {
-                per_dev[dev] = {};
-                return nullptr;
-            }
             for (int i = 0; i < cus; ++i) (i < np ? pm : um)[i / 32] |= 1u << (i % 32);
             const uint32_t words = (uint32_t)((cus + 31) / 32);
             hipStream_t a = nullptr, b = nullptr;
             if (hipExtStreamCreateWithCUMask(&a, words, pm) == hipSuccess &&
                 hipExtStreamCreateWithCUMask(&b, words, um) == hipSuccess) {
-                per_dev[dev] = {a, b, np, cus - np};
+                g_streams[dev] = {a, b, np, cus - np};
+                if (!g_atexit_registered) {
+                    // registered after the HIP runtime started, so it runs
+                    // before the runtime's own exit-time teardown
+                    g_atexit_registered = std::atexit(release_at_exit) == 0;
+                }
             } else {
                 if (a) (void)hipStreamDestroy(a);
-                per_dev[dev] = {};
+                g_streams[dev] = {};
             }
         }
         (void)hipGetLastError();
     }
-    return per_dev[dev].panel ? &per_dev[dev] : nullptr;
+    return g_streams[dev].panel ? &g_streams[dev] : nullptr;
 }
 
 // Joins the look-ahead streams back into the factorization stream when it
@@ -239,19 +261,31 @@ class ForkJoin {
 
 // Leaf workgroups allowed on the panel stream: 7/8 of its CUs, so that a
 // leaf still fits when a few of them are unavailable.
-int lookahead_group_cap(const OverlapStreams *ov) { return ov->panel_cus * 7 / 8; }
+int lookahead_group_cap(int panel_cus) { return panel_cus * 7 / 8; }
 
 // Depth-1 look-ahead applies when every trailing update can be split at the
-// next panel's columns into direct-kernel updates (sizes multiples of 128) and
-// the tallest panel's leaf fits on the panel stream's CUs.
+// next panel's columns into direct-kernel updates (sizes multiples of 128),
+// the first panel's leaf fits on all CUs (it runs on the caller's stream)
+// and every later panel's leaf -- at most n - nb rows -- fits within the
+// group cap of the panel stream.  Host arithmetic only.
+bool lookahead_plan(int64_t n, int64_t nb, const LeafDevice &all, int panel_cus) {
+    if (panel_cus <= 0 || nb % 128 != 0 || n % 128 != 0 || n <= nb) return false;
+    LeafDevice capped = all;
+    capped.cap = lookahead_group_cap(panel_cus);
+    int64_t R = 0, G = 0;
+    return leaf_plan(n, all, &R, &G) != kLeafNone && leaf_plan(n - nb, capped, &R, &G) != kLeafNone;
+}
+
 bool lookahead_fits(int64_t n, int64_t nb, const double *A, int64_t lda,
                     const OverlapStreams *ov) {
-    if (!ov || nb % 128 != 0 || n % 128 != 0 || n <= nb) return false;
-    if (!gemm_f64_update_ok(n - nb, n - nb, nb, A, lda)) return false;
-    const int g = panel_leaf_groups<double>(n - nb, lookahead_group_cap(ov));
-    (void)hipGetLastError();
-    clear_error();
-    return g > 0;
+    if (!ov || n <= nb || !gemm_f64_update_ok(n - nb, n - nb, nb, A, lda)) return false;
+    LeafDevice all;
+    if (leaf_device_f64(0, &all)) {
+        (void)hipGetLastError();
+        clear_error();
+        return false;
+    }
+    return lookahead_plan(n, nb, all, ov->panel_cus);
 }
 
 // Columns of the remaining update given to the update stream while the next
@@ -284,10 +318,15 @@ int factor_impl(int64_t n, int64_t nb, double *A, int64_t lda, int32_t *ipiv, hi
     const OverlapStreams *ov =
         g_lookahead.load() > 0 ? overlap_streams() : nullptr;
     const bool la = lookahead_fits(n, nb, A, lda, ov);
+    std::unique_lock<std::mutex> la_lock(g_lookahead_mu, std::defer_lock);
+    if (la) la_lock.lock();   // held until the factorization has completed
     ForkJoin fj(s, ov);
+    // panels factored on the panel stream may use only its CUs; those on the
+    // caller's stream (the first one, and every one at depth 0) use all
+    PanelExchange ex_ahead = ex;
     if (la) {
         MXLU_TRY(fj.create());
-        ex.group_cap = lookahead_group_cap(ov);
+        ex_ahead.group_cap = lookahead_group_cap(ov->panel_cus);
     }
 
     bool ahead = false;  // the current panel was factored during the previous update
@@ -302,7 +341,7 @@ int factor_impl(int64_t n, int64_t nb, double *A, int64_t lda, int32_t *ipiv, hi
         ahead = false;
         {   // SWAP on the columns left and right of the panel
             PhaseScope ph(kPhaseSwap, s, 32.0 * kb * (double)(n - kb));
-            MXLU_TRY(laswp_f64(A, lda, ipiv, k0, (int)kb, 0, n - kb, k0, kb, moves, s));
+            MXLU_TRY(laswp_f64(A, lda, n, ipiv, k0, (int)kb, 0, n - kb, k0, kb, moves, s));
         }
         if (c1 >= n) continue;
         const int64_t nt = n - c1;
@@ -337,8 +376,8 @@ int factor_impl(int64_t n, int64_t nb, double *A, int64_t lda, int32_t *ipiv, hi
         MXLU_TRY(fj.fork());
         {
             PhaseScope ph(kPhasePfact, ov->panel, (double)nt * kb1 * 8.0);
-            MXLU_TRY(panel_factor<double>(&MXLU_AT(A, c1, c1, lda), lda, nt, kb1, c1, ipiv, ex,
-                                     moves, ov->panel));
+            MXLU_TRY(panel_factor<double>(&MXLU_AT(A, c1, c1, lda), lda, nt, kb1, c1, ipiv,
+                                          ex_ahead, moves, ov->panel));
         }
         const int64_t n1 = nt > kb1 ? lookahead_split(nt, kb, kb1, ov) : 0;
         if (n1 > 0) {
@@ -373,6 +412,73 @@ extern "C" int mxlu_set_lookahead(int depth) {
     if (depth < 0 || depth > 1) return -1;
     g_lookahead.store(depth);
     return 0;
+}
+
+extern "C" int mxlu_debug_expire_waits(int on) {
+    if (on != 0 && on != 1) return -1;
+    mxlu::g_expire_waits.store(on);
+    return 0;
+}
+
+extern "C" int mxlu_panel_factor_f64(int64_t m, int64_t nb, double *P, int64_t ldp,
+                                     int32_t *ipiv, void *stream) {
+    if (m < 0) return -1;
+    if (nb < 0 || nb > m || nb > 1024) return -2;
+    if (m > 0 && nb > 0 && !P) return -3;
+    if (ldp < std::max<int64_t>(1, m)) return -4;
+    if (nb > 0 && !ipiv) return -5;
+    if (m > 0x7fffffff) return -1;
+    if (m == 0 || nb == 0) return 0;
+    if (int rc = check_device()) return rc;
+    clear_error();
+    hipStream_t s = (hipStream_t)stream;
+    Scratch scratch(s);
+    PanelExchange ex;
+    MXLU_TRY(alloc_panel_exchange(scratch, m, &ex, s));
+    int *moves = scratch.alloc_n<int>(kSwapMovesInts);
+    if (!moves) return MXLU_E_NOMEM;
+    {
+        PhaseScope ph(kPhasePfact, s, (double)m * nb * 8.0);
+        MXLU_TRY(panel_factor<double>(P, ldp, m, nb, 0, ipiv, ex, moves, s));
+    }
+    int flags[4] = {0, 0, 0, 0};
+    MXLU_HIP_TRY(hipMemcpyAsync(flags, ex.flags, sizeof(flags), hipMemcpyDeviceToHost, s));
+    MXLU_HIP_TRY(hipStreamSynchronize(s));
+    if (flags[1]) {
+        set_error_msg("mxlu_panel_factor_f64: panel grid barrier wait expired");
+        return MXLU_E_TIMEOUT;
+    }
+    return flags[0];
+}
+
+extern "C" int mxlu_release(void) {
+    release_streams();
+    return mxlu::profile_release();
+}
+
+extern "C" int mxlu_plan_panel_cus(int cus) {
+    if (cus < 128 || cus > 1024) return 0;
+    const int np = cus / 4;
+    return np % 32 == 0 ? np : 0;
+}
+
+extern "C" int mxlu_plan_panel_leaf(int64_t m, int cap, int cus, int occ_reg1, int occ_reg2,
+                                    int64_t lds_budget, int elem_bytes, int64_t *rows_per_group,
+                                    int64_t *groups) {
+    if (cus <= 0 || cap < 0 || (elem_bytes != 4 && elem_bytes != 8)) return -1;
+    LeafDevice d{cap, cus, occ_reg1, occ_reg2, elem_bytes, lds_budget};
+    int64_t R = 0, G = 0;
+    const int form = leaf_plan(m, d, &R, &G);
+    if (rows_per_group) *rows_per_group = R;
+    if (groups) *groups = G;
+    return form;
+}
+
+extern "C" int mxlu_plan_lookahead(int64_t n, int64_t nb, int cus, int occ_reg1, int occ_reg2,
+                                   int64_t lds_budget) {
+    const int np = mxlu_plan_panel_cus(cus);
+    LeafDevice all{0, cus, occ_reg1, occ_reg2, 8, lds_budget};
+    return lookahead_plan(n, nb, all, np) ? np : 0;
 }
 
 extern "C" int lu_factor(int64_t n, int64_t nb, double *A, int64_t lda, int32_t *ipiv,

@@ -254,6 +254,7 @@ __global__ __launch_bounds__(256) void panel_leaf_kernel(
                 argmax_merge(gv, gi, word_double(&s_words[t * kSlotWords]),
                              (int)s_words[t * kSlotWords + 2]);
             wave_argmax(gv, gi);
+            if (gi < j || gi >= m) gi = j;   // expired wait only (see below)
             prow = &s_words[(gi / R) * kSlotWords + 4];
             swap = (gv != 0.0) && gi != j;
         } else {
@@ -281,6 +282,7 @@ __global__ __launch_bounds__(256) void panel_leaf_kernel(
             for (int t = lane; t < G; t += 64)
                 argmax_merge(gv, gi, word_double(&s_words[3 * t]), (int)s_words[3 * t + 2]);
             wave_argmax(gv, gi);
+            if (gi < j || gi >= m) gi = j;   // expired wait only (see below)
             swap = (gv != 0.0) && gi != j;
             if (tid < 2 * w) {
                 const uint64_t *src = gs + (size_t)(gi / R) * kSlotWords + 4 + tid;
@@ -292,7 +294,9 @@ __global__ __launch_bounds__(256) void panel_leaf_kernel(
             __syncthreads();
             prow = s_prow;
         }
-        // gi is a valid row >= j (the group holding row j has a candidate)
+        // gi is a valid row >= j (the group holding row j has a candidate);
+        // only after an expired wait (stale words) could it have left [j, m),
+        // and it was then replaced by j above, so no index leaves the panel
         const int p = gi;
         const bool nonzero = (gv != 0.0);
         if (g == 0 && tid == 0) {
@@ -394,7 +398,7 @@ struct RegLeafShared {
 };
 
 struct RegLeafArgs {
-    int w, G, rows, rb, g, tid, lane, wave;
+    int m, w, G, rows, rb, g, tid, lane, wave;
     int64_t r0;
     int32_t *ipiv;
     uint64_t *slots, *rowj;
@@ -542,6 +546,7 @@ __device__ __forceinline__ const uint32_t *reg_leaf_column(RegLeafState<RPT> &st
             argmax_merge(gv, gi, words_double(&sh.words[t * kSlotWords]),
                          (int)sh.words[t * kSlotWords + 2]);
         wave_argmax_dpp(gv, gi);
+        if (gi < J || gi >= a.m) gi = J;   // expired wait only (see below)
         prow = &sh.words[(gi / R) * kSlotWords + 4];
         swap = (gv != 0.0) && gi != J;
         if (swap && gi >= a.rb && gi < a.rb + a.rows && tid >= 64 && tid < 64 + 2 * w) {
@@ -575,6 +580,7 @@ __device__ __forceinline__ const uint32_t *reg_leaf_column(RegLeafState<RPT> &st
         for (int t = lane; t < G; t += 64)
             argmax_merge(gv, gi, words_double(&sh.words[3 * t]), (int)sh.words[3 * t + 2]);
         wave_argmax_dpp(gv, gi);
+        if (gi < J || gi >= a.m) gi = J;   // expired wait only (see below)
         swap = (gv != 0.0) && gi != J;
         if (tid < 2 * w) {
             const uint64_t *src = gs + (size_t)(gi / R) * kSlotWords + 4 + tid;
@@ -586,7 +592,9 @@ __device__ __forceinline__ const uint32_t *reg_leaf_column(RegLeafState<RPT> &st
         __syncthreads();
         prow = sh.prow;
     }
-    // gi is a valid row >= J (the group holding row J has a candidate)
+    // gi is a valid row >= J (the group holding row J has a candidate); only
+    // after an expired wait (stale words) could it have left [J, m), and it
+    // was then replaced by J above, so no index leaves the panel
     const int p = gi;
     const bool nonzero = (gv != 0.0);
     if (a.g == 0 && tid == 0) {
@@ -652,6 +660,7 @@ __global__ __launch_bounds__(256) void panel_leaf_reg_kernel(int m, int w, doubl
     constexpr int R = 256 * RPT;
     __shared__ RegLeafShared sh;
     RegLeafArgs a;
+    a.m = m;
     a.w = w;
     a.G = G;
     a.g = blockIdx.x;
@@ -700,13 +709,19 @@ __global__ __launch_bounds__(256) void panel_leaf_reg_kernel(int m, int w, doubl
 constexpr int kMaxSwaps = 1024;
 
 __global__ __launch_bounds__(256) void swap_compose_kernel(const int32_t *__restrict__ ipiv,
-                                                           int64_t j0, int cnt,
+                                                           int64_t j0, int cnt, int64_t nrows,
                                                            int *__restrict__ moves) {
     __shared__ int s_piv[kMaxSwaps];
     __shared__ int s_wsum[4];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
-    for (int t = tid; t < cnt; t += 256) s_piv[t] = (int)(ipiv[j0 + t] - j0);  // relative
+    // relative pivot rows; an entry outside [t, nrows - j0) (possible only in
+    // a sequence left by an expired wait) is taken as no interchange, so the
+    // moves never address a row outside the matrix
+    for (int t = tid; t < cnt; t += 256) {
+        const int64_t q = (int64_t)ipiv[j0 + t] - j0;
+        s_piv[t] = (q >= t && q < nrows - j0) ? (int)q : t;
+    }
     __syncthreads();
     // candidate t < cnt is row t; candidate cnt + u is the pivot row of
     // interchange u when it lies beyond the block and appears there first
@@ -1049,44 +1064,21 @@ static int max_dynamic_lds() {
     return cached;
 }
 
-// Rows per workgroup (R) and workgroups (G) of the leaf kernel for an m-row
-// leaf, and the dynamic LDS budget.  The dynamic LDS holds the group's rows of
-// the leaf (the static part holds the gathered words): about `cap` groups
-// (64 when cap is 0) of at least 256 rows, more groups when LDS is short.
-// Returns 0, or MXLU_E_NOMEM when the panel cannot be held by co-resident
-// workgroups (at most `cap` of them when cap > 0, else at most one per CU).
+// Dynamic LDS left to the LDS form of the leaf (the static part holds the
+// gathered words).
 template <typename T>
-static int leaf_geometry(int64_t m, int cap, int64_t *R_out, int64_t *G_out,
-                         int64_t *budget_out) {
+static int leaf_lds_budget(int64_t *budget) {
     static int64_t static_lds = -1;
     if (static_lds < 0) {
         hipFuncAttributes fa;
         MXLU_HIP_TRY(hipFuncGetAttributes(&fa, (const void *)panel_leaf_kernel<T>));
         static_lds = (int64_t)fa.sharedSizeBytes;
     }
-    const int64_t budget = max_dynamic_lds() - static_lds;
-    const int64_t target = cap > 0 ? cap : 64;
-    int64_t R = std::max<int64_t>(256, (m + target - 1) / target);
-    int64_t G = (m + R - 1) / R;
-    auto need = [&](int64_t r) { return (int64_t)sizeof(T) * kLeafW * r; };
-    while (need(R) > budget && G < kMaxGroups) {
-        R = std::max<int64_t>(64, (R * 7) / 8);
-        G = (m + R - 1) / R;
-    }
-    if (G > kMaxGroups || G > compute_units() || (cap > 0 && G > cap) || need(R) > budget) {
-        set_error_msg("panel_leaf: panel too tall for the LDS of the device");
-        return MXLU_E_NOMEM;
-    }
-    *R_out = R;
-    *G_out = G;
-    *budget_out = budget;
+    *budget = max_dynamic_lds() - static_lds;
     return 0;
 }
 
-// Register form of the FP64 leaf: rows per thread (1 or 2) and workgroups,
-// or 0 when it does not apply.  All G workgroups must be resident at once:
-// G stays within the workgroups per CU the kernel's resources allow times the
-// CUs available (`cap` CUs when cap > 0, else all of them).
+// Workgroups of the register form of the FP64 leaf that one CU can hold.
 static int reg_leaf_occupancy(int rpt) {
     static int occ[3] = {-1, -1, -1};
     if (occ[rpt] < 0) {
@@ -1102,26 +1094,62 @@ static int reg_leaf_occupancy(int rpt) {
     return occ[rpt];
 }
 
-static int reg_leaf_plan(int64_t m, int cap, int64_t *G_out) {
-    const int64_t cus = cap > 0 ? cap : compute_units();
-    for (int rpt = 1; rpt <= 2; ++rpt) {
-        const int64_t G = (m + 256 * rpt - 1) / (256 * rpt);
-        if (G <= mxlu::kMaxGroups && G <= (int64_t)reg_leaf_occupancy(rpt) * cus) {
-            *G_out = G;
-            return rpt;
+// Device facts the leaf planner needs, for the caller's group cap.
+template <typename T>
+static int leaf_device(int cap, mxlu::LeafDevice *d) {
+    d->cap = cap;
+    d->cus = compute_units();
+    d->occ_reg1 = sizeof(T) == 8 ? reg_leaf_occupancy(1) : 0;
+    d->occ_reg2 = sizeof(T) == 8 ? reg_leaf_occupancy(2) : 0;
+    d->elem_bytes = (int)sizeof(T);
+    return leaf_lds_budget<T>(&d->lds_budget);
+}
+
+// The leaf planner (host arithmetic only).  All G workgroups of a leaf must
+// be resident at once, so G stays within what the CUs the leaf may use can
+// hold: `cap` CUs when cap > 0, else every CU.
+//   register form (FP64 only): R = 256 RPT rows per group, RPT = 1 or 2, the
+//     first with G <= kMaxGroups and G <= occupancy x CUs;
+//   LDS form: about `cap` groups (64 when cap is 0) of at least 256 rows,
+//     more groups when the group's rows do not fit in its LDS; at most one
+//     group per usable CU.
+int leaf_plan(int64_t m, const LeafDevice &d, int64_t *R_out, int64_t *G_out) {
+    if (m <= 0 || m > 0x7fffffff) return kLeafNone;
+    const int64_t cus = d.cap > 0 ? std::min<int64_t>(d.cap, d.cus) : d.cus;
+    if (d.elem_bytes == 8) {
+        for (int rpt = 1; rpt <= 2; ++rpt) {
+            const int occ = rpt == 1 ? d.occ_reg1 : d.occ_reg2;
+            const int64_t G = (m + 256 * rpt - 1) / (256 * rpt);
+            if (occ > 0 && G <= kMaxGroups && G <= (int64_t)occ * cus) {
+                *R_out = 256 * rpt;
+                *G_out = G;
+                return rpt == 1 ? kLeafReg1 : kLeafReg2;
+            }
         }
     }
-    return 0;
+    const int64_t target = d.cap > 0 ? d.cap : 64;
+    int64_t R = std::max<int64_t>(256, (m + target - 1) / target);
+    int64_t G = (m + R - 1) / R;
+    auto need = [&](int64_t r) { return (int64_t)d.elem_bytes * kLeafW * r; };
+    while (need(R) > d.lds_budget && G < kMaxGroups) {
+        R = std::max<int64_t>(64, (R * 7) / 8);
+        G = (m + R - 1) / R;
+    }
+    if (G > kMaxGroups || G > cus || need(R) > d.lds_budget) return kLeafNone;
+    *R_out = R;
+    *G_out = G;
+    return kLeafLds;
 }
+
+int leaf_device_f64(int cap, LeafDevice *d) { return leaf_device<double>(cap, d); }
 
 template <typename T>
 int panel_leaf_groups(int64_t m, int cap) {
-    int64_t R = 0, G = 0, budget = 0;
     if (m <= 0) return 0;
-    if (m > 0x7fffffff) return -1;
-    if (sizeof(T) == 8 && reg_leaf_plan(m, cap, &G)) return (int)G;
-    if (leaf_geometry<T>(m, cap, &R, &G, &budget)) return -1;
-    return (int)G;
+    LeafDevice d;
+    if (leaf_device<T>(cap, &d)) return -1;
+    int64_t R = 0, G = 0;
+    return leaf_plan(m, d, &R, &G) == kLeafNone ? -1 : (int)G;
 }
 template int panel_leaf_groups<double>(int64_t, int);
 template int panel_leaf_groups<float>(int64_t, int);
@@ -1134,12 +1162,20 @@ int panel_leaf(int64_t m, int w, T *P, int64_t ldp, int64_t r0, int32_t *ipiv,
         set_error_msg("panel_leaf: bad shape");
         return MXLU_E_NOMEM;
     }
-    if (sizeof(T) == 8 && w == kLeafW) {
-        int64_t Gr = 0;
-        const int rpt = reg_leaf_plan(m, ex.group_cap, &Gr);
-        if (rpt) {
+    LeafDevice dev;
+    MXLU_TRY(leaf_device<T>(ex.group_cap, &dev));
+    if (w != kLeafW) dev.occ_reg1 = dev.occ_reg2 = 0;   // the register form takes full leaves
+    int64_t R = 0, G = 0;
+    const int form = leaf_plan(m, dev, &R, &G);
+    if (form == kLeafNone) {
+        set_error_msg("panel_leaf: panel too tall for the LDS of the device");
+        return MXLU_E_NOMEM;
+    }
+    if (form == kLeafReg1 || form == kLeafReg2) {
+        const int64_t Gr = G;
+        {
             double *Pd = reinterpret_cast<double *>(P);
-            if (rpt == 1)
+            if (form == kLeafReg1)
                 hipLaunchKernelGGL(panel_leaf_reg_kernel<1>, dim3((unsigned)Gr), dim3(256), 0, s,
                                    (int)m, w, Pd, ldp, (int)Gr, r0, ipiv + r0, ex.slots, ex.rowj,
                                    ex.flags);
@@ -1151,14 +1187,12 @@ int panel_leaf(int64_t m, int w, T *P, int64_t ldp, int64_t r0, int32_t *ipiv,
             return 0;
         }
     }
-    int64_t R = 0, G = 0, budget = 0;
-    MXLU_TRY(leaf_geometry<T>(m, ex.group_cap, &R, &G, &budget));
     const size_t lds = (size_t)sizeof(T) * kLeafW * R;
     static bool attr_set = false;
     if (!attr_set) {
         MXLU_HIP_TRY(hipFuncSetAttribute((const void *)panel_leaf_kernel<T>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         (int)budget));
+                                         (int)dev.lds_budget));
         attr_set = true;
     }
     hipLaunchKernelGGL(panel_leaf_kernel<T>, dim3((unsigned)G), dim3(256), lds, s, (int)m, w, P,
@@ -1171,13 +1205,15 @@ template int panel_leaf<double>(int64_t, int, double *, int64_t, int64_t, int32_
 template int panel_leaf<float>(int64_t, int, float *, int64_t, int64_t, int32_t *,
                                const PanelExchange &, hipStream_t);
 
-int swap_compose(const int32_t *ipiv, int64_t j0, int cnt, int *moves, hipStream_t s) {
+int swap_compose(const int32_t *ipiv, int64_t j0, int cnt, int64_t nrows, int *moves,
+                 hipStream_t s) {
     if (cnt <= 0) return 0;
-    if (cnt > kMaxSwaps || !moves) {
-        set_error_msg("laswp: too many interchanges or no move buffer");
+    if (cnt > kMaxSwaps || !moves || nrows - j0 > INT_MAX) {
+        set_error_msg("laswp: too many interchanges, rows or no move buffer");
         return MXLU_E_NOMEM;
     }
-    hipLaunchKernelGGL(swap_compose_kernel, dim3(1), dim3(256), 0, s, ipiv, j0, cnt, moves);
+    hipLaunchKernelGGL(swap_compose_kernel, dim3(1), dim3(256), 0, s, ipiv, j0, cnt, nrows,
+                       moves);
     MXLU_LAUNCH_CHECK();
     return 0;
 }
@@ -1199,11 +1235,11 @@ template int swap_apply<float>(float *, int64_t, int64_t, const int *, int64_t, 
 template int swap_apply<uint16_t>(uint16_t *, int64_t, int64_t, const int *, int64_t, int64_t,
                                   int64_t, int64_t, hipStream_t);
 
-int laswp_f64(double *A, int64_t lda, const int32_t *ipiv, int64_t j0, int cnt,
+int laswp_f64(double *A, int64_t lda, int64_t nrows, const int32_t *ipiv, int64_t j0, int cnt,
               int64_t c_begin, int64_t ncols, int64_t skip_begin, int64_t skip_len,
               int *moves, hipStream_t s) {
     if (cnt <= 0 || ncols <= 0) return 0;
-    MXLU_TRY(swap_compose(ipiv, j0, cnt, moves, s));
+    MXLU_TRY(swap_compose(ipiv, j0, cnt, nrows, moves, s));
     return swap_apply<double>(A, lda, j0, moves, c_begin, ncols, skip_begin, skip_len, s);
 }
 

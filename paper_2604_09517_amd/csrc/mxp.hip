@@ -110,7 +110,9 @@ int lp_factorize(const mxp_opts &o, int64_t n, const double *A, int64_t lda, uin
     tf.start();
     {
         PhaseScope ph(kPhaseLpFactor, s, (2.0 / 3.0) * (double)n * n * n);
-        for (int64_t k0 = 0; k0 < n; k0 += nb) {
+        int64_t step = 0;
+        for (int64_t k0 = 0; k0 < n; k0 += nb, ++step) {
+            if (o.factor_steps > 0 && step >= o.factor_steps) break;
             const int64_t kb = std::min(nb, n - k0), m = n - k0, c1 = k0 + kb;
             uint16_t *Fk = F + (size_t)k0 + (size_t)k0 * ldf;
             MXLU_TRY(lp_load_f32(fmt, m, kb, Fk, ldf, P32, m, s));
@@ -121,7 +123,7 @@ int lp_factorize(const mxp_opts &o, int64_t n, const double *A, int64_t lda, uin
             const bool need_lt = !fp8 && c1 < n;
             MXLU_TRY(lp_panel_store(fmt, m, (int)kb, P32, m, Fk, ldf, need_lt ? LTp : nullptr, Mp, s));
             if (o.pivot && n > kb) {   // the panel's interchanges on the other stored columns
-                MXLU_TRY(swap_compose(ipiv, k0, (int)kb, moves, s));
+                MXLU_TRY(swap_compose(ipiv, k0, (int)kb, n, moves, s));
                 MXLU_TRY(swap_apply<uint16_t>(F, ldf, k0, moves, 0, n - kb, k0, kb, s));
             }
             if (c1 >= n) continue;
@@ -335,10 +337,11 @@ extern "C" void mxp_default_opts(mxp_opts *o) {
     o->reuse_factors = 0;
     o->trans = 0;
     o->x_init = 0;
+    o->factor_steps = 0;
 }
 
-extern "C" size_t mxp_workspace_bytes(int64_t n, const mxp_opts *o) {
-    if (n < 0 || !o) return 0;
+extern "C" size_t mxp_workspace_bytes(int64_t n, int64_t lda, const mxp_opts *o) {
+    if (n < 0 || lda < std::max<int64_t>(1, n) || !o) return 0;
     const int64_t ldf = factor_ld(n);
     const double bytes = (double)ldf * (double)n * 2.0 + 256.0;
     if (bytes > 9.0e18) return 0;
@@ -382,10 +385,10 @@ extern "C" int mxp_solve(int64_t n, int64_t nrhs, const double *A, int64_t lda, 
                                                        o.scale_tile > 256 || o.scale_tile % 4)) ||
         (o.refine != MXLU_IR_CLASSICAL && o.refine != MXLU_IR_GMRES) || o.restart < 1 ||
         o.restart > 255 || o.max_outer < 0 || o.max_inner_total < 0 || o.trans < 0 ||
-        o.trans > 1)
+        o.trans > 1 || o.factor_steps < 0)
         return -12;
     if (o.pivot && !ipiv) return -11;
-    if (n > 0 && work_bytes < mxp_workspace_bytes(n, opts)) return MXLU_E_WORKSPACE;
+    if (n > 0 && work_bytes < mxp_workspace_bytes(n, lda, opts)) return MXLU_E_WORKSPACE;
     if (report) std::memset(report, 0, sizeof(*report));
     if (n == 0 || nrhs == 0) {
         if (report) report->converged = 1;

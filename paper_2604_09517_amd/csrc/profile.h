@@ -20,6 +20,8 @@ enum {
 };
 
 bool profiling_enabled();
+// Destroys the pooled timing events (pending intervals are dropped).
+int profile_release();
 
 class PhaseScope {
   public:

@@ -46,6 +46,20 @@ hipEvent_t get_event() {
 
 bool profiling_enabled() { return g_enabled; }
 
+int profile_release() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto &p : g_pending) {
+        (void)hipEventSynchronize(p.stop);
+        g_free.push_back(p.start);
+        g_free.push_back(p.stop);
+    }
+    g_pending.clear();
+    for (hipEvent_t e : g_free) (void)hipEventDestroy(e);
+    g_free.clear();
+    (void)hipGetLastError();
+    return 0;
+}
+
 PhaseScope::PhaseScope(int phase, hipStream_t s, double work) : s_(s) {
     if (!g_enabled) return;
     std::lock_guard<std::mutex> lk(g_mu);

@@ -79,8 +79,11 @@ def test_mxp_options_and_workspace(L):
     assert o.resid_threshold == 16.0 and o.scale_tile == 128
     ldf = L.mxp_factor_ld(1000)
     assert ldf >= 1000 and ldf % 64 == 0
-    assert L.mxp_workspace_bytes(1000, ctypes.byref(o)) >= 2 * ldf * 1000
-    assert L.mxp_workspace_bytes(-1, ctypes.byref(o)) == 0
+    assert o.factor_steps == 0
+    assert L.mxp_workspace_bytes(1000, 1000, ctypes.byref(o)) >= 2 * ldf * 1000
+    assert L.mxp_workspace_bytes(1000, 1004, ctypes.byref(o)) >= 2 * ldf * 1000
+    assert L.mxp_workspace_bytes(-1, 1, ctypes.byref(o)) == 0
+    assert L.mxp_workspace_bytes(1000, 999, ctypes.byref(o)) == 0     # lda < n
     p = ctypes.c_void_p(16)
     rep = _lib.MxpReport()
     bad = _lib.MxpOpts()
@@ -96,7 +99,11 @@ def test_mxp_options_and_workspace(L):
     bad.pivot = 1                                  # pivoting needs ipiv
     assert L.mxp_solve(64, 1, p, 64, p, 64, p, 64, p, 1 << 20, None, ctypes.byref(bad),
                        ctypes.byref(rep), None) == -11
-    bad.pivot = 0                                  # workspace too small
+    bad.pivot = 0
+    bad.factor_steps = -1                          # negative step count
+    assert L.mxp_solve(64, 1, p, 64, p, 64, p, 64, p, 1 << 20, None, ctypes.byref(bad),
+                       ctypes.byref(rep), None) == -12
+    bad.factor_steps = 0                           # workspace too small
     assert L.mxp_solve(64, 1, p, 64, p, 64, p, 64, p, 16, None, ctypes.byref(bad),
                        ctypes.byref(rep), None) == -1006
 
@@ -124,3 +131,75 @@ def test_python_layer_rejects_bad_tensors():
         api._mat(torch.zeros(4, 4, dtype=torch.float32), "A")
     with pytest.raises(ValueError):
         api._mat(torch.zeros(4, 4, dtype=torch.float64), "A")   # on the CPU
+
+
+# ------------------------------------------------------- planning (host only)
+LDS_BUDGET = 160 * 1024 - 4096     # dynamic LDS of the LDS-form leaf, about
+
+
+def plan_leaf(L, m, cap, cus=256, occ1=2, occ2=2, budget=LDS_BUDGET, elem=8):
+    R, G = ctypes.c_int64(0), ctypes.c_int64(0)
+    form = L.mxlu_plan_panel_leaf(m, cap, cus, occ1, occ2, budget, elem, ctypes.byref(R),
+                                  ctypes.byref(G))
+    return form, R.value, G.value
+
+
+def test_panel_cus_even_split_only(L):
+    """The look-ahead's panel stream gets a quarter of the CUs only when that
+    is an equal number per shader engine (a multiple of 32 on an 8-XCD,
+    4-engine-per-XCD part): 256 CUs -> 64; the uneven 48-of-192 and 76-of-304
+    splits are refused (no look-ahead)."""
+    assert L.mxlu_plan_panel_cus(256) == 64
+    assert L.mxlu_plan_panel_cus(128) == 32
+    for cus in (192, 304, 240, 100, 0, -1, 2048):
+        assert L.mxlu_plan_panel_cus(cus) == 0, cus
+
+
+def test_leaf_planner_forms_and_residency(L):
+    # register form, one row per thread, while groups fit two per CU
+    assert plan_leaf(L, 32768, 0) == (1, 256, 128)
+    assert plan_leaf(L, 65536, 0) == (1, 256, 256)
+    # beyond kMaxGroups (256) groups: two rows per thread
+    assert plan_leaf(L, 65537, 0)[:2] == (2, 512)
+    # a cap of 56 CUs (7/8 of the 64 panel CUs) holds 112 groups
+    assert plan_leaf(L, 28672, 56) == (1, 256, 112)
+    assert plan_leaf(L, 28673, 56)[:2] == (2, 512)
+    assert plan_leaf(L, 57344, 56) == (2, 512, 112)
+    # one row more: neither register form fits in 56 CUs, and the LDS form
+    # (one group per CU, rows in LDS) needs more LDS than a CU has
+    assert plan_leaf(L, 57345, 56)[0] == 0
+    # FP32 panels take the LDS form
+    form, R, G = plan_leaf(L, 40000, 0, elem=4)
+    assert form == 3 and G <= 256 and R * G >= 40000 and 4 * 32 * R <= LDS_BUDGET
+    # every form keeps all groups resident: G <= CUs x groups per CU
+    for m in (1, 255, 257, 5000, 30000, 60000, 100000, 131072):
+        for cap in (0, 56):
+            form, R, G = plan_leaf(L, m, cap)
+            if form:
+                cus = cap or 256
+                assert R * G >= m and G <= (2 if form < 3 else 1) * cus
+
+
+def test_lookahead_plan_boundary(L):
+    """The first panel (n rows) runs on the caller's stream with every CU, so
+    only the later panels (at most n - nb rows) are bound by the panel
+    stream's cap: n = 57472 with nb = 128 (first panel 57472 rows, next
+    57344) takes look-ahead; n = 57600 does not (next panel 57472 rows)."""
+    args = (256, 2, 2, LDS_BUDGET)
+    assert L.mxlu_plan_lookahead(32768, 256, *args) == 64
+    assert L.mxlu_plan_lookahead(57472, 128, *args) == 64
+    assert L.mxlu_plan_lookahead(57600, 128, *args) == 0
+    assert L.mxlu_plan_lookahead(57600, 256, *args) == 64
+    assert L.mxlu_plan_lookahead(32768, 64, *args) == 0        # nb % 128
+    assert L.mxlu_plan_lookahead(32704, 256, *args) == 0       # n % 128
+    assert L.mxlu_plan_lookahead(256, 256, *args) == 0         # a single panel
+    assert L.mxlu_plan_lookahead(32768, 256, 304, 2, 2, LDS_BUDGET) == 0   # uneven split
+
+
+def test_debug_and_release_hooks_validate(L):
+    assert L.mxlu_debug_expire_waits(2) == -1
+    assert L.mxlu_debug_expire_waits(0) == 0
+    p = ctypes.c_void_p(16)
+    assert L.mxlu_panel_factor_f64(10, 11, p, 10, p, None) == -2     # nb > m
+    assert L.mxlu_panel_factor_f64(10, 4, p, 9, p, None) == -4
+    assert L.mxlu_panel_factor_f64(10, 4, p, 10, None, None) == -5

@@ -5,10 +5,13 @@ against the CPU oracle, through the C ABI.
 What is compared, and how:
   * conversion FP64 -> bf16/fp16: bit for bit;
   * factors: the first panel step (panel and U12 block row, FP32 arithmetic in
-    the same operation order) bit for bit; the rest within a bound, since
-    the MFMA trailing update sums products in its own order; the backward
-    error ||LU - A|| / ||A|| of the GPU factors within 4 u (u = 2^-8 bf16,
-    2^-11 fp16, 2^-4 for the FP8 update);
+    the same operation order) bit for bit; after one panel step every entry
+    of the updated trailing block within one storage ulp (same operands, only
+    the FP32 summation order differs); the whole factorization within a
+    componentwise bound of two summation orders, and the backward error
+    ||LU - A|| / ||A|| within 4 u (u = 2^-8 bf16, 2^-11 fp16, 2^-4 for the
+    FP8 update); FP8 at nb 128, 256 and 1024 (1, 2 and 8 K chunks in the
+    update kernel) and on inputs whose scale tiles all differ;
   * preconditioner M b on identical (oracle) factors: bit for bit;
   * solves: the HPL scaled residual < 16 (the acceptance threshold), the
     forward error against the FP64 oracle solution within the bound that
@@ -82,24 +85,137 @@ def run_mxp(api, A_h, b_h, **kw):
     return X.cpu().numpy(), rep, work, dA
 
 
-@pytest.mark.parametrize("prec,n,nb", [("bf16", 256, 64), ("fp16", 300, 64), ("bf16", 640, 128),
-                                       ("fp8", 512, 128), ("fp8", 700, 128)])
-def test_lp_factors_against_oracle(api, prec, n, nb):
-    note(f"lp factors prec={prec} n={n} nb={nb}")
-    A = inputs.diag_dominant_matrix(31 + n, 0, n)
+def tile_scaled(A, tile):
+    """D_r A D_c with power-of-two factors constant on each tile of `tile`
+    rows (columns) and different between neighbouring tiles.  The no-pivot
+    LU of the result is D_r L D_r^-1 times D_r U D_c (exact scalings), so the
+    factorization is as stable as A's, while the FP8 tile scales of L21 rows
+    and U12 columns differ from tile to tile."""
+    n = A.shape[0]
+    kr = np.array([(i // tile) % 5 - 2 for i in range(n)], dtype=np.float64)
+    kc = np.array([2 - (j // tile) % 5 for j in range(n)], dtype=np.float64)
+    return (2.0 ** kr)[:, None] * A * (2.0 ** kc)[None, :]
+
+
+def lp_input(kind, n, seed, tile=128, l21_boost=0, nb=0):
+    A = inputs.diag_dominant_matrix(seed, 0, n)
+    if l21_boost:
+        # larger multipliers below the first panel (a power of two, exact):
+        # the first trailing update then moves A22 by much more than a
+        # storage ulp, so a dropped or misplaced term shows at once
+        A[nb:, :nb] *= 2.0 ** l21_boost
+    if kind == "scaled":
+        A = tile_scaled(A, tile)
+    return A
+
+
+def ordered_bits(F, prec):
+    """Storage words of F (FP64 holding storage values) as integers ordered
+    like the values: adjacent representable numbers differ by 1."""
+    dt = torch.bfloat16 if prec == "bf16" else torch.float16
+    w = torch.from_numpy(np.ascontiguousarray(F)).to(dt).view(torch.int16).numpy()
+    w = w.astype(np.int64) & 0xFFFF
+    mag = w & 0x7FFF
+    return np.where(w & 0x8000, -mag, mag)
+
+
+def componentwise_bound(A, F_ref, nb, prec):
+    """Bound on |F - F_ref| for two executions of the same blocked algorithm
+    that differ only in the FP32 summation order of the trailing updates.
+    Each update step can move a stored Schur-complement entry by one storage
+    rounding (u_s |value|), and a changed stored operand changes later update
+    terms l_ik u_kj by a relative u_s -- by one e4m3 step (2^-3) when the FP8
+    quantisation of the changed operand flips.  Summed over the steps that
+    touch entry (i, j):
+      |dF_ij| <= 4 s_ij (u_s (|F_ij| + |A_ij|) + u_q (|L||U|)'_ij)
+    with s_ij = min(i, j) // nb + 1 and (|L||U|)' the sum over k < min(i, j)
+    of |l_ik| |u_kj| (the update terms)."""
+    n = A.shape[0]
+    L, U = checks.unpack_lu(F_ref)
+    aL, aU = np.abs(L), np.abs(U)
+    full = aL @ aU
+    last = np.where(np.tri(n, dtype=bool), aL * np.diag(aU)[None, :], aU)
+    upd = full - last
+    us = U_LP["bf16"] if prec == "bf16" else U_LP["fp16"]
+    uq = 2.0 ** -3 if prec == "fp8" else us
+    steps = np.minimum.outer(np.arange(n), np.arange(n)) // nb + 1
+    return 4 * steps * (us * (np.abs(F_ref) + np.abs(A)) + uq * upd)
+
+
+@pytest.mark.parametrize("prec,n,nb,kind,tile", [
+    ("bf16", 256, 64, "dominant", 64), ("fp16", 300, 64, "dominant", 64),
+    ("bf16", 640, 128, "dominant", 64), ("fp8", 512, 128, "dominant", 64),
+    ("fp8", 700, 128, "dominant", 64), ("fp8", 680, 256, "dominant", 128),
+    ("fp8", 2216, 1024, "dominant", 128), ("fp8", 500, 128, "scaled", 12),
+    ("fp8", 680, 256, "scaled", 128), ("bf16", 680, 256, "scaled", 128)])
+def test_lp_factors_against_oracle(api, prec, n, nb, kind, tile):
+    """Whole factorization: first panel and block row bit for bit, every
+    other entry within the componentwise bound of two summation orders."""
+    note(f"lp factors prec={prec} n={n} nb={nb} input={kind} tile={tile}")
+    A = lp_input(kind, n, 31 + n, tile)
     b = inputs.uniform_matrix(31 + n, 1, n, 1)[:, 0]
-    _, rep, work, _ = run_mxp(api, A, b, prec=prec, nb=nb, max_outer=0, scale_tile=64)
+    _, rep, work, _ = run_mxp(api, A, b, prec=prec, nb=nb, max_outer=0, scale_tile=tile)
     F = factors_to_host(api, work, n, prec)
-    F_ref, _, info = oracle.lp_getrf(A, nb, PREC_ID[prec], pivot=False, tile=64)
+    F_ref, _, info = oracle.lp_getrf(A, nb, PREC_ID[prec], pivot=False, tile=tile)
     assert rep["info"] == info == 0
     # first panel and first block row: FP32 arithmetic in the same order
     assert np.array_equal(F[:, :nb], F_ref[:, :nb])
     assert np.array_equal(F[:nb, :], F_ref[:nb, :])
+    d = np.abs(F - F_ref)
+    bound = componentwise_bound(A, F_ref, nb, prec)
+    worst = np.unravel_index(np.argmax(d / np.maximum(bound, 1e-300)), d.shape)
+    note(f"  entries differing {(d > 0).sum()}, max |dF| {d.max():.3e}, "
+         f"worst ratio to bound {d[worst] / bound[worst]:.3f} at {worst}")
+    assert np.all(d <= bound)
     u = U_LP[prec]
-    assert np.abs(F - F_ref).max() <= 4 * u * np.abs(F_ref).max()
     L, U = checks.unpack_lu(F)
     err = np.abs(L @ U - A).sum(1).max() / np.abs(A).sum(1).max()
     assert err <= 4 * u
+
+
+@pytest.mark.parametrize("prec,n,nb,kind,tile", [
+    ("bf16", 680, 256, "dominant", 128), ("fp16", 700, 128, "dominant", 64),
+    ("bf16", 2216, 512, "dominant", 128),
+    ("fp8", 700, 128, "dominant", 64), ("fp8", 680, 256, "dominant", 128),
+    ("fp8", 2216, 1024, "dominant", 128), ("fp8", 500, 128, "scaled", 12),
+    ("fp8", 1064, 256, "scaled", 128), ("fp8", 1064, 256, "scaled", 36)])
+def test_lp_one_update_within_one_ulp(api, prec, n, nb, kind, tile):
+    """One panel step (partial factorization): the panel and U12 bit for bit,
+    and every updated entry of the trailing block within one storage ulp of
+    the oracle's -- the operands are identical, so only the FP32 summation
+    order differs, and with FP8 operands the products and their partial sums
+    are mostly exact in FP32.  nb 256 and 1024 run the FP8 update's K loop
+    over 2 and 8 chunks; the scaled inputs give every scale tile its own
+    power-of-two scale (tile 12: rows of one lane's 8-row group fall into two
+    scale tiles)."""
+    note(f"one update prec={prec} n={n} nb={nb} input={kind} tile={tile}")
+    A = lp_input(kind, n, 57 + n, tile, l21_boost=4, nb=nb)
+    b = inputs.uniform_matrix(57 + n, 1, n, 1)[:, 0]
+    _, rep, work, _ = run_mxp(api, A, b, prec=prec, nb=nb, max_outer=0, scale_tile=tile,
+                              factor_steps=1)
+    F = factors_to_host(api, work, n, prec)
+    F_ref, _, info = oracle.lp_getrf(A, nb, PREC_ID[prec], pivot=False, tile=tile, max_steps=1)
+    assert rep["info"] == info == 0
+    assert np.array_equal(F[:, :nb], F_ref[:, :nb])
+    assert np.array_equal(F[:nb, :], F_ref[:nb, :])
+    A22, R22 = F[nb:, nb:], F_ref[nb:, nb:]
+    diff = np.abs(ordered_bits(A22, prec) - ordered_bits(R22, prec))
+    # the update is not trivially small: it moved most entries by many ulps
+    sfmt = oracle.BF16 if prec == "bf16" else oracle.FP16
+    S22 = oracle.round_lp(A[nb:, nb:], sfmt)
+    moved = np.abs(ordered_bits(R22, prec) - ordered_bits(S22, prec))
+    # where the update cancels to a result far below its terms, two FP32
+    # summation orders may differ by more than one storage ulp: there the
+    # difference stays within the FP32 dot-product bound 2 gamma_K T,
+    # T = |a_ij| + sum_k |l_ik u_kj|, gamma_K = K 2^-24 (plus one ulp)
+    T = np.abs(S22) + np.abs(F_ref[nb:, :nb]) @ np.abs(F_ref[:nb, nb:])
+    ulp = np.abs(R22) * (2.0 ** -7 if prec == "bf16" else 2.0 ** -10) + 2.0 ** -24
+    cancel_ok = np.abs(A22 - R22) <= 2 * nb * 2.0 ** -24 * T + ulp
+    note(f"  entries off by one ulp {(diff == 1).sum()}, by more (cancellation) "
+         f"{(diff > 1).sum()} of {diff.size}; median ulps moved by the update "
+         f"{np.median(moved):.0f}")
+    assert np.median(moved) >= 4
+    assert np.all((diff <= 1) | cancel_ok)
 
 
 @pytest.mark.parametrize("prec,trans", [("bf16", 0), ("fp16", 0), ("bf16", 1)])
@@ -110,7 +226,7 @@ def test_preconditioner_bitwise_on_oracle_factors(api, prec, trans):
     F_ref, _, _ = oracle.lp_getrf(A, nb, PREC_ID[prec], pivot=False)
     dA, db = to_dev(A), to_dev(b)
     opts = api.mxp_options(prec=prec, nb=nb, max_outer=0, reuse_factors=True, trans=bool(trans))
-    work = torch.zeros(api.mxp_workspace_bytes(n, opts), dtype=torch.uint8, device="cuda")
+    work = torch.zeros(api.mxp_workspace_bytes(n, opts, n), dtype=torch.uint8, device="cuda")
     api.mxp_factors(work, n, prec).copy_(torch.from_numpy(F_ref).to(
         torch.bfloat16 if prec == "bf16" else torch.float16))
     X, rep, _, _ = api.mxp_solve(dA, db, work=work, opts=opts, allow_notconv=True)
@@ -139,14 +255,36 @@ def test_mxp_solve_matches_oracle(api, prec, method, n, nb):
     F_ref, _, _ = oracle.lp_getrf(A, nb, PREC_ID[prec], pivot=False, tile=128)
     out = refine.refine(A, b, F_ref, None, method=method)
     assert out["converged"]
-    assert abs(rep["outer_iters"] - out["outer_iters"]) <= 1
     LU, ipiv, _ = oracle.getrf(A, nb)
     x64 = oracle.getrs(LU, ipiv, b)
     kappa = np.linalg.cond(A, np.inf)
     fe = checks.forward_error(x, x64)
     note(f"  outer {rep['outer_iters']} (oracle {out['outer_iters']}), inner "
          f"{rep['inner_iters']} (oracle {out['inner_iters']}), rho {rho:.2f}, fwd err {fe:.2e}")
+    assert abs(rep["outer_iters"] - out["outer_iters"]) <= 1
+    # GMRES: each cycle may end one Arnoldi step earlier or later (its stopping
+    # test compares a rounding-sensitive estimate with inner_tol * beta)
+    assert abs(rep["inner_iters"] - out["inner_iters"]) <= out["outer_iters"] + 1
     assert fe < 4 * 16 * n * EPS * kappa
+
+
+@pytest.mark.parametrize("prec,n,nb,tile", [("fp8", 896, 128, 12), ("bf16", 1000, 256, 128)])
+def test_mxp_solve_tile_scaled_matrix(api, prec, n, nb, tile):
+    """A harder system for the refinement: the tile-scaled matrix has
+    condition number about 2^8 times that of the dominant matrix, and its
+    FP8 factors carry a different scale on every tile."""
+    seed = 71 + n
+    A = lp_input("scaled", n, seed, tile)
+    b = inputs.uniform_matrix(seed, 1, n, 1)[:, 0]
+    x, rep, _, _ = run_mxp(api, A, b, prec=prec, nb=nb, refine="gmres", scale_tile=tile)
+    F_ref, _, _ = oracle.lp_getrf(A, nb, PREC_ID[prec], pivot=False, tile=tile)
+    out = refine.refine(A, b, F_ref, None, method="gmres")
+    rho = checks.scaled_residual(A, x, b)
+    note(f"tile-scaled {prec} n={n}: outer {rep['outer_iters']} (oracle {out['outer_iters']}), "
+         f"inner {rep['inner_iters']} (oracle {out['inner_iters']}), rho {rho:.2f}")
+    assert out["converged"] and rep["converged"] == 1 and rho < 16
+    assert abs(rep["outer_iters"] - out["outer_iters"]) <= 1
+    assert abs(rep["inner_iters"] - out["inner_iters"]) <= out["outer_iters"] + 1
 
 
 def test_mxp_transposed_and_multiple_rhs(api):

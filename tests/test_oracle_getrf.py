@@ -228,3 +228,24 @@ def test_panel_alone_equals_first_step(oracle_lib):
     P, pp, _ = oracle.panel_getrf(A[:, :nb])
     assert np.array_equal(pp, ipiv[:nb])
     assert np.array_equal(P, LU[:, :nb])
+
+
+@pytest.mark.parametrize("n,seed", [(n, s) for n in (3, 5, 8) for s in range(3)])
+def test_pivot_gaps_match_exact_rational(oracle_lib, n, seed):
+    """The gap report of the gap-recording factorization equals the exact
+    rational runner-up gap of textbook GEPP, and its factors and pivots are
+    those of the plain factorization."""
+    A = inputs.uniform_matrix(100 + seed, 0, n, n)
+    _, piv, gaps_exact = exact_gepp(A)
+    Ag = np.asfortranarray(A.copy())
+    ipiv_g, gaps, info = oracle.getrf_gaps_inplace(Ag, 3)
+    LU, ipiv, _ = oracle.getrf(A, 3)
+    assert np.array_equal(ipiv_g, ipiv) and np.array_equal(Ag, LU)
+    for j in range(n):
+        assert abs(gaps[j] - float(gaps_exact[j])) <= 1e-9, (j, gaps[j], gaps_exact[j])
+    # a planted exact tie in the first column has gap 0
+    B = A.copy()
+    B[1, 0] = -B[np.argmax(np.abs(B[:, 0])), 0] if np.argmax(np.abs(B[:, 0])) != 1 else B[1, 0]
+    Bg = np.asfortranarray(B)
+    _, gb, _ = oracle.getrf_gaps_inplace(Bg, 3)
+    assert gb[0] == 0.0 or np.argmax(np.abs(B[:, 0])) == 1

@@ -141,6 +141,46 @@ def test_lp_lu_fp8_update_exact_on_representable_operands(oracle_lib):
     assert np.array_equal(np.triu(F), U)
 
 
+def _tile_scaled_exact_lu(n, tile, seed):
+    """Exact factors as in _exact_lu_pair, with rows and columns scaled by
+    powers of two that are constant on each tile of `tile` rows (columns) and
+    differ between neighbouring tiles: L' = Dr L Dr^-1, U' = Dr U Dc, so the
+    rows of L21 and the columns of U12 fall into tiles whose largest entries
+    differ by powers of two.  Every value stays a short dyadic number."""
+    rng = np.random.default_rng(seed)
+    L, U = _exact_lu_pair(n, rng)
+    dr = 2.0 ** np.array([(i // tile) % 3 - 1 for i in range(n)], dtype=np.float64)
+    dc = 2.0 ** np.array([1 - (j // tile) % 3 for j in range(n)], dtype=np.float64)
+    L2 = (dr[:, None] * L) / dr[None, :]
+    U2 = dr[:, None] * U * dc[None, :]
+    return L2 @ U2, L2, U2
+
+
+@pytest.mark.parametrize("n,nb,tile", [(24, 8, 4), (40, 16, 8), (36, 12, 12)])
+def test_lp_lu_fp8_distinct_tile_scales_exact(oracle_lib, n, nb, tile):
+    """FP8 update with one power-of-two scale per tile (Sec. III-A.2 reduced-
+    precision trailing update; e4m3fn operands with per-tile scales): on
+    factors whose tiles have different magnitudes every quantised operand is
+    an e4m3 number times its own tile's scale, so the update is exact and the
+    factors come back exactly -- but only when each row (column) is
+    dequantised with the scale of its own tile."""
+    A, L2, U2 = _tile_scaled_exact_lu(n, tile, seed=n + tile)
+    assert np.array_equal(oracle.round_lp(A, oracle.FP16), A)
+    # the tiles really carry different scales: the L21 row tiles of the first
+    # step, and the U12 column tiles
+    l21 = np.abs(np.tril(L2, -1)[nb:, :nb])
+    amax_l = [l21[t:t + tile].max() for t in range(0, n - nb, tile)]
+    u12 = np.abs(U2[:nb, nb:])
+    amax_u = [u12[:, t:t + tile].max() for t in range(0, n - nb, tile)]
+    assert len({oracle.fp8_scale(a) for a in amax_l}) > 1
+    assert len({oracle.fp8_scale(a) for a in amax_u}) > 1
+    assert any(oracle.fp8_scale(a) != oracle.fp8_scale(b) for a, b in zip(amax_l, amax_l[1:]))
+    F, _, info = oracle.lp_getrf(A, nb=nb, prec=2, pivot=False, tile=tile)
+    assert info == 0
+    assert np.array_equal(np.tril(F, -1), np.tril(L2, -1))
+    assert np.array_equal(np.triu(F), U2)
+
+
 def test_lp_lu_pivoted_recovers_permutation(oracle_lib):
     rng = np.random.default_rng(13)
     n = 10
@@ -277,6 +317,23 @@ def test_refine_reaches_fp64_accuracy_on_dominant_matrix(oracle_lib, method, pre
     assert checks.forward_error(out["x"], x64) < 4 * 16 * n * checks.EPS * kappa
     # the residual history goes down
     assert out["history"][-1] < out["history"][0]
+
+
+@pytest.mark.parametrize("method", ["classical", "gmres"])
+def test_refine_stopping_measure_is_the_hpl_residual(oracle_lib, method):
+    """The refinement's own stopping measure at every iterate equals the HPL
+    scaled residual of the acceptance checks at that iterate."""
+    n = 96
+    A = inputs.diag_dominant_matrix(43, 0, n)
+    b = inputs.uniform_matrix(43, 1, n, 1)[:, 0]
+    F, _, _ = oracle.lp_getrf(A, nb=32, prec=0)
+    full = refine.refine(A, b, F, None, method=method, threshold=0.0, max_outer=3)
+    for k in range(4):
+        out = refine.refine(A, b, F, None, method=method, threshold=0.0, max_outer=k)
+        assert out["outer_iters"] == k
+        rho = checks.scaled_residual(A, out["x"], b)
+        assert abs(out["history"][-1] - rho) <= 1e-12 * rho
+        assert abs(full["history"][k] - rho) <= 1e-12 * rho
 
 
 def test_refine_transposed(oracle_lib):

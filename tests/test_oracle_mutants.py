@@ -45,6 +45,10 @@ MUTANTS = [
     ("lp_update_sign", "acc = fmaf(-to_f32(S[IDX(i, k0 + k, lds)]),",
      "acc = fmaf(to_f32(S[IDX(i, k0 + k, lds)]),", 0),
     ("lp_fp8_missing_u_scale", "upd = (float)((double)upd * su);", "upd = upd;", 0),
+    ("lp_fp8_neighbour_row_tile_scale", "double sl = sL[(i - c1) / tile];",
+     "double sl = sL[(i - c1) / tile > 0 ? (i - c1) / tile - 1 : 1];", 0),
+    ("lp_fp8_first_column_tile_scale", "double su = sU[(c - c1) / tile];",
+     "double su = sU[0];", 0),
     ("lp_trsm_wrong_factor", "uu[i] = fmaf(-P[IDX(i, k, m)], uu[k], uu[i]);",
      "uu[i] = fmaf(-P[IDX(k, i, m)], uu[k], uu[i]);", 0),
     ("precond_no_forward_solve",
@@ -69,6 +73,8 @@ PINS = [
     lambda: P.test_fp8_scale_is_minimal_power_of_two(None),
     lambda: [P.test_lp_lu_reproduces_exact_factors(None, p) for p in (0, 1)],
     lambda: P.test_lp_lu_fp8_update_exact_on_representable_operands(None),
+    lambda: [P.test_lp_lu_fp8_distinct_tile_scales_exact(None, n, nb, t)
+             for n, nb, t in ((24, 8, 4), (40, 16, 8), (36, 12, 12))],
     lambda: P.test_lp_lu_pivoted_recovers_permutation(None),
     lambda: P.test_preconditioner_solves_with_factors_and_adjoint(None),
     lambda: P.test_preconditioner_with_pivots_and_exact_factors(None),
