@@ -270,6 +270,15 @@ int mxlu_scaled_residual(int64_t n, int64_t nrhs, const double *A, int64_t lda,
 int mxlu_profile_enable(int on);
 int mxlu_profile_reset(void);
 int mxlu_profile_read(double *ms, double *work, int64_t *count, int nphase);
+/*
+ * mxlu_profile_intervals -- the individual intervals of one phase since the
+ * last reset, in recording order: step[k] is the panel step the interval
+ * belongs to (k0 / nb of the factorization; -1 outside a factorization),
+ * ms[k] its GPU time, work[k] its nominal work.  Fills at most `cap` entries
+ * of the HOST arrays (any may be NULL) and returns the number of intervals,
+ * or < 0 on error.  Synchronises on the recorded events.
+ */
+int64_t mxlu_profile_intervals(int phase, int64_t *step, double *ms, double *work, int64_t cap);
 
 /*
  * Planning helpers: host arithmetic only (no device access), the rules the

@@ -67,6 +67,8 @@ SIGNATURES = {
     "mxlu_profile_reset": (_int, []),
     "mxlu_profile_read": (_int, [ctypes.POINTER(_dbl), ctypes.POINTER(_dbl),
                                  ctypes.POINTER(_i64), _int]),
+    "mxlu_profile_intervals": (_i64, [_int, ctypes.POINTER(_i64), ctypes.POINTER(_dbl),
+                                      ctypes.POINTER(_dbl), _i64]),
     "mxlu_status_string": (ctypes.c_char_p, [_int]),
     "mxlu_last_error": (ctypes.c_char_p, []),
 }

@@ -265,3 +265,16 @@ def profile_read():
     cnt = (ctypes.c_int64 * n)()
     check("mxlu_profile_read", lib().mxlu_profile_read(ms, work, cnt, n))
     return {p: (ms[i], work[i], cnt[i]) for i, p in enumerate(PHASES)}
+
+
+def profile_intervals(phase):
+    """[(step, ms, work), ...] of one phase (a name of PHASES) since the last reset."""
+    k = PHASES.index(phase)
+    n = int(lib().mxlu_profile_intervals(k, None, None, None, 0))
+    if n < 0:
+        raise RuntimeError(f"mxlu_profile_intervals failed ({n})")
+    step = (ctypes.c_int64 * max(1, n))()
+    ms = (ctypes.c_double * max(1, n))()
+    work = (ctypes.c_double * max(1, n))()
+    lib().mxlu_profile_intervals(k, step, ms, work, n)
+    return [(step[i], ms[i], work[i]) for i in range(n)]

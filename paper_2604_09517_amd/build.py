@@ -37,12 +37,24 @@ def _compile(src: str) -> str:
     return obj
 
 
-def _stale(src: str, headers: list[str]) -> bool:
+def _includes(path: str, seen: set[str]) -> set[str]:
+    """Local headers a source includes, transitively."""
+    import re
+    for name in re.findall(r'^\s*#include\s+"([^"]+)"', open(path).read(), flags=re.M):
+        for d in (CSRC, INCLUDE):
+            h = os.path.join(d, name)
+            if os.path.exists(h) and h not in seen:
+                seen.add(h)
+                _includes(h, seen)
+    return seen
+
+
+def _stale(src: str) -> bool:
     obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
     if not os.path.exists(obj):
         return True
     t = os.path.getmtime(obj)
-    return any(os.path.getmtime(f) > t for f in [src, *headers])
+    return any(os.path.getmtime(f) > t for f in [src, *_includes(src, set())])
 
 
 def build(jobs: int | None = None, verbose: bool = False, incremental: bool = False) -> str:
@@ -51,8 +63,7 @@ def build(jobs: int | None = None, verbose: bool = False, incremental: bool = Fa
     or than any header)."""
     os.makedirs(OBJDIR, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
-    headers = glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(INCLUDE, "*.h"))
-    todo = [s for s in srcs if not incremental or _stale(s, headers)]
+    todo = [s for s in srcs if not incremental or _stale(s)]
     jobs = jobs or min(8, os.cpu_count() or 1)
     with cf.ThreadPoolExecutor(jobs) as ex:
         list(ex.map(_compile, todo))

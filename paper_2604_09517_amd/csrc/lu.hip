@@ -333,6 +333,7 @@ int factor_impl(int64_t n, int64_t nb, double *A, int64_t lda, int32_t *ipiv, hi
     for (int64_t k0 = 0; k0 < n; k0 += nb) {
         const int64_t kb = std::min(nb, n - k0);
         const int64_t m = n - k0, c1 = k0 + kb;
+        profile_set_step(k0 / nb);
         if (!ahead) {   // PFACT
             PhaseScope ph(kPhasePfact, s, (double)m * kb * 8.0);
             MXLU_TRY(panel_factor<double>(&MXLU_AT(A, k0, k0, lda), lda, m, kb, k0, ipiv, ex, moves,
@@ -375,10 +376,12 @@ int factor_impl(int64_t n, int64_t nb, double *A, int64_t lda, int32_t *ipiv, hi
         }
         MXLU_TRY(fj.fork());
         {
+            profile_set_step(k0 / nb + 1);   // the next step's panel
             PhaseScope ph(kPhasePfact, ov->panel, (double)nt * kb1 * 8.0);
             MXLU_TRY(panel_factor<double>(&MXLU_AT(A, c1, c1, lda), lda, nt, kb1, c1, ipiv,
                                           ex_ahead, moves, ov->panel));
         }
+        profile_set_step(k0 / nb);
         const int64_t n1 = nt > kb1 ? lookahead_split(nt, kb, kb1, ov) : 0;
         if (n1 > 0) {
             PhaseScope ph(kPhaseGemm, ov->update, 2.0 * (double)nt * (double)n1 * (double)kb);
@@ -395,6 +398,7 @@ int factor_impl(int64_t n, int64_t nb, double *A, int64_t lda, int32_t *ipiv, hi
         MXLU_TRY(fj.join_update());
         ahead = true;
     }
+    profile_set_step(-1);
     int flags[4] = {0, 0, 0, 0};
     MXLU_HIP_TRY(hipMemcpyAsync(flags, ex.flags, sizeof(flags), hipMemcpyDeviceToHost, s));
     MXLU_HIP_TRY(hipStreamSynchronize(s));
@@ -499,8 +503,10 @@ extern "C" int lu_factor(int64_t n, int64_t nb, double *A, int64_t lda, int32_t 
     return info;
 }
 
-extern "C" int lu_solve(int64_t n, int64_t nrhs, const double *LU, int64_t lda,
-                        const int32_t *ipiv, double *B, int64_t ldb, int trans, void *stream) {
+namespace {
+
+int solve_args(int64_t n, int64_t nrhs, const double *LU, int64_t lda, const int32_t *ipiv,
+               const double *B, int64_t ldb, int trans) {
     if (n < 0) return -1;
     if (nrhs < 0) return -2;
     if (n > 0 && !LU) return -3;
@@ -510,20 +516,17 @@ extern "C" int lu_solve(int64_t n, int64_t nrhs, const double *LU, int64_t lda,
     if (ldb < std::max<int64_t>(1, n)) return -7;
     if (trans != 0 && trans != 1) return -8;
     if (n > 0x7fffffff) return -1;
-    if (n == 0 || nrhs == 0) return 0;
-    if (int rc = check_device()) return rc;
-    clear_error();
-    hipStream_t s = (hipStream_t)stream;
-    Scratch scratch(s);
-    PhaseScope ph(kPhaseSolve, s, 8.0 * (double)n * (double)n);
-    int32_t *perm = scratch.alloc_n<int32_t>((size_t)n);
-    if (!perm) return MXLU_E_NOMEM;
-    MXLU_TRY(perm_from_ipiv(n, ipiv, perm, s));
+    return 0;
+}
 
+// The solves of lu_solve with caller-provided device scratch: perm (n int32)
+// and Y (n x min(16, nrhs) doubles, leading dimension n).
+int solve_impl(int64_t n, int64_t nrhs, const double *LU, int64_t lda, const int32_t *ipiv,
+               double *B, int64_t ldb, int trans, hipStream_t s, int32_t *perm, double *Y) {
+    PhaseScope ph(kPhaseSolve, s, 8.0 * (double)n * (double)n);
+    MXLU_TRY(perm_from_ipiv(n, ipiv, perm, s));
     // Work on strips of at most 16 right-hand sides.
     const int64_t bs = 256;
-    double *Y = scratch.alloc_n<double>((size_t)n * (size_t)std::min<int64_t>(16, nrhs));
-    if (!Y) return MXLU_E_NOMEM;
     const int64_t ldy = n;
     for (int64_t r0 = 0; r0 < nrhs; r0 += 16) {
         const int64_t nr = std::min<int64_t>(16, nrhs - r0);
@@ -583,6 +586,22 @@ extern "C" int lu_solve(int64_t n, int64_t nrhs, const double *LU, int64_t lda,
         }
     }
     return 0;
+}
+
+}  // namespace
+
+extern "C" int lu_solve(int64_t n, int64_t nrhs, const double *LU, int64_t lda,
+                        const int32_t *ipiv, double *B, int64_t ldb, int trans, void *stream) {
+    if (int rc = solve_args(n, nrhs, LU, lda, ipiv, B, ldb, trans)) return rc;
+    if (n == 0 || nrhs == 0) return 0;
+    if (int rc = check_device()) return rc;
+    clear_error();
+    hipStream_t s = (hipStream_t)stream;
+    Scratch scratch(s);
+    int32_t *perm = scratch.alloc_n<int32_t>((size_t)n);
+    double *Y = scratch.alloc_n<double>((size_t)n * (size_t)std::min<int64_t>(16, nrhs));
+    if (!perm || !Y) return MXLU_E_NOMEM;
+    return solve_impl(n, nrhs, LU, lda, ipiv, B, ldb, trans, s, perm, Y);
 }
 
 extern "C" int mxlu_schur_update_f64(int64_t M, int64_t N, int64_t K, const double *A,

@@ -113,25 +113,34 @@ int lp_factorize(const mxp_opts &o, int64_t n, const double *A, int64_t lda, uin
         int64_t step = 0;
         for (int64_t k0 = 0; k0 < n; k0 += nb, ++step) {
             if (o.factor_steps > 0 && step >= o.factor_steps) break;
+            profile_set_step(step);
             const int64_t kb = std::min(nb, n - k0), m = n - k0, c1 = k0 + kb;
             uint16_t *Fk = F + (size_t)k0 + (size_t)k0 * ldf;
-            MXLU_TRY(lp_load_f32(fmt, m, kb, Fk, ldf, P32, m, s));
-            if (o.pivot)   // partial pivoting on the FP32 values of the panel
-                MXLU_TRY(panel_factor<float>(P32, m, m, kb, k0, ipiv, ex, moves, s));
-            else
-                MXLU_TRY(lp_panel_factor_nopiv(m, (int)kb, P32, m, d_info, k0, s));
-            const bool need_lt = !fp8 && c1 < n;
-            MXLU_TRY(lp_panel_store(fmt, m, (int)kb, P32, m, Fk, ldf, need_lt ? LTp : nullptr, Mp, s));
+            {   // PFACT in FP32 (work: the panel's bytes in storage precision)
+                PhaseScope ph(kPhasePfact, s, 2.0 * (double)m * kb);
+                MXLU_TRY(lp_load_f32(fmt, m, kb, Fk, ldf, P32, m, s));
+                if (o.pivot)   // partial pivoting on the FP32 values of the panel
+                    MXLU_TRY(panel_factor<float>(P32, m, m, kb, k0, ipiv, ex, moves, s));
+                else
+                    MXLU_TRY(lp_panel_factor_nopiv(m, (int)kb, P32, m, d_info, k0, s));
+                const bool need_lt = !fp8 && c1 < n;
+                MXLU_TRY(lp_panel_store(fmt, m, (int)kb, P32, m, Fk, ldf, need_lt ? LTp : nullptr,
+                                        Mp, s));
+            }
             if (o.pivot && n > kb) {   // the panel's interchanges on the other stored columns
+                PhaseScope ph(kPhaseSwap, s, 8.0 * kb * (double)(n - kb));
                 MXLU_TRY(swap_compose(ipiv, k0, (int)kb, n, moves, s));
                 MXLU_TRY(swap_apply<uint16_t>(F, ldf, k0, moves, 0, n - kb, k0, kb, s));
             }
             if (c1 >= n) continue;
             const int64_t nt = n - c1;
             uint16_t *U12 = F + (size_t)k0 + (size_t)c1 * ldf;
-            MXLU_TRY(lp_load_f32(fmt, kb, nt, U12, ldf, T32, kb, s));
-            MXLU_TRY(trsm_f32_llnu(kb, nt, P32, m, T32, kb, s));
-            MXLU_TRY(lp_store_f32(fmt, kb, nt, T32, kb, U12, ldf, s));
+            {   // U12 = L11^-1 A12 in FP32
+                PhaseScope ph(kPhaseTrsm, s, (double)kb * (kb - 1) * (double)nt);
+                MXLU_TRY(lp_load_f32(fmt, kb, nt, U12, ldf, T32, kb, s));
+                MXLU_TRY(trsm_f32_llnu(kb, nt, P32, m, T32, kb, s));
+                MXLU_TRY(lp_store_f32(fmt, kb, nt, T32, kb, U12, ldf, s));
+            }
             uint16_t *A22 = F + (size_t)c1 + (size_t)c1 * ldf;
             // algorithmic bytes: A22 read and written in 16 bits, L21 and U12 read once
             const double ob = fp8 ? 1.0 : 2.0;
@@ -151,6 +160,7 @@ int lp_factorize(const mxp_opts &o, int64_t n, const double *A, int64_t lda, uin
             }
         }
     }
+    profile_set_step(-1);
     tf.stop();
     int hinfo[4] = {0, 0, 0, 0};
     MXLU_HIP_TRY(hipMemcpyAsync(hinfo, o.pivot ? ex.flags : d_info, sizeof(hinfo),

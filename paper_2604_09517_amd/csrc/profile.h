@@ -22,6 +22,9 @@ enum {
 bool profiling_enabled();
 // Destroys the pooled timing events (pending intervals are dropped).
 int profile_release();
+// Panel step index recorded with the intervals opened from now on by the
+// calling thread (-1: none).
+void profile_set_step(int64_t step);
 
 class PhaseScope {
   public:
@@ -34,6 +37,7 @@ class PhaseScope {
     hipStream_t s_;
     hipEvent_t start_ = nullptr;
     int phase_ = 0;
+    int64_t step_ = -1;
     double work_ = 0.0;
 };
 
