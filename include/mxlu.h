@@ -119,6 +119,23 @@ int lu_solve(int64_t n, int64_t nrhs, const double *LU, int64_t lda,
              void *stream);
 
 /*
+ * lu_solve_noalloc -- lu_solve for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that
+ * forbid allocation): the same solves, bit for bit, with no hipMalloc,
+ * hipFree or other allocating call.  Its scratch (the row permutation and a
+ * strip of up to 16 right-hand sides) lives in a library-owned device array
+ * of 8.25 MiB per device (held until the process ends), whose device address
+ * is looked up on the first call on each device.  Limit: n <= 65536 (larger
+ * n returns MXLU_E_WORKSPACE, nothing enqueued).  Every call on a device
+ * shares that device's array: calls that overlap on one device (on different
+ * streams or threads) race and must be serialised by the caller.  Arguments,
+ * other return values and stream behaviour as lu_solve.
+ */
+int lu_solve_noalloc(int64_t n, int64_t nrhs, const double *LU, int64_t lda,
+                     const int32_t *ipiv, double *B, int64_t ldb, int trans,
+                     void *stream);
+
+/*
  * mxlu_panel_factor_f64 -- the PFACT phase on its own (Sec. III-A.1: the
  * panel factorization with partial pivoting): GEPP of the m x nb panel P
  * (FP64, column-major, leading dimension ldp, m >= nb, nb <= 1024) in place,

@@ -50,6 +50,7 @@ SIGNATURES = {
                                     ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "mxlu_plan_lookahead": (_int, [_i64, _i64, _int, _int, _int, _i64]),
     "lu_solve": (_int, [_i64, _i64, _vp, _i64, _vp, _vp, _i64, _int, _vp]),
+    "lu_solve_noalloc": (_int, [_i64, _i64, _vp, _i64, _vp, _vp, _i64, _int, _vp]),
     "mxlu_schur_update_f64": (_int, [_i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp]),
     "mxlu_outer_update_f64": (_int, [_i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _int,
                                      _vp]),

@@ -72,6 +72,18 @@ def lu_factor(A, nb=256, ipiv=None):
     return A, ipiv, info
 
 
+def lu_solve_noalloc(LU, ipiv, B, trans=False):
+    """lu_solve without device allocation (library-owned scratch, n <= 65536)."""
+    pl, n, _, lda = _mat(LU, "LU")
+    pp, _, _, _ = _mat(ipiv, "ipiv", torch.int32)
+    pb, nb_rows, nrhs, ldb = _mat(B, "B")
+    if nb_rows != n:
+        raise ValueError("B must have n rows")
+    rc = lib().lu_solve_noalloc(n, nrhs, pl, lda, pp, pb, ldb, 1 if trans else 0, _stream())
+    check("lu_solve_noalloc", rc)
+    return B
+
+
 def panel_factor(P, ipiv=None):
     """In-place GEPP of an m x nb FP64 panel (the PFACT phase alone).
     Returns (P, ipiv with 0-based panel rows, info)."""

@@ -588,6 +588,35 @@ int solve_impl(int64_t n, int64_t nrhs, const double *LU, int64_t lda, const int
     return 0;
 }
 
+// Scratch of lu_solve_noalloc: Y (kNoAllocMaxN x 16 doubles) then perm
+// (kNoAllocMaxN int32), one copy per device, held until the process ends.
+constexpr int64_t kNoAllocMaxN = 65536;
+constexpr size_t kNoAllocYBytes = (size_t)kNoAllocMaxN * 16 * sizeof(double);
+constexpr size_t kNoAllocBytes = kNoAllocYBytes + (size_t)kNoAllocMaxN * sizeof(int32_t);
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[kMaxDev] = {};
+
+// Device address of this device's copy of `scratch`, looked up once per
+// device (the array's name is only a host-side stand-in).
+int noalloc_scratch(void **out) {
+    int dev = 0;
+    MXLU_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDev) {
+        set_error_msg("lu_solve_noalloc: device index out of range");
+        return MXLU_E_NODEV;
+    }
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void *p = nullptr;
+        MXLU_HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_noalloc_ptr[dev] = p;
+    }
+    *out = g_noalloc_ptr[dev];
+    return 0;
+}
+
 }  // namespace
 
 extern "C" int lu_solve(int64_t n, int64_t nrhs, const double *LU, int64_t lda,
@@ -602,6 +631,24 @@ extern "C" int lu_solve(int64_t n, int64_t nrhs, const double *LU, int64_t lda,
     double *Y = scratch.alloc_n<double>((size_t)n * (size_t)std::min<int64_t>(16, nrhs));
     if (!perm || !Y) return MXLU_E_NOMEM;
     return solve_impl(n, nrhs, LU, lda, ipiv, B, ldb, trans, s, perm, Y);
+}
+
+extern "C" int lu_solve_noalloc(int64_t n, int64_t nrhs, const double *LU, int64_t lda,
+                                const int32_t *ipiv, double *B, int64_t ldb, int trans,
+                                void *stream) {
+    if (int rc = solve_args(n, nrhs, LU, lda, ipiv, B, ldb, trans)) return rc;
+    if (n > kNoAllocMaxN) {
+        set_error_msg("lu_solve_noalloc: n exceeds the 65536 rows its static scratch holds");
+        return MXLU_E_WORKSPACE;
+    }
+    if (n == 0 || nrhs == 0) return 0;
+    if (int rc = check_device()) return rc;
+    clear_error();
+    void *base = nullptr;
+    MXLU_TRY(noalloc_scratch(&base));
+    double *Y = static_cast<double *>(base);
+    int32_t *perm = reinterpret_cast<int32_t *>(static_cast<unsigned char *>(base) + kNoAllocYBytes);
+    return solve_impl(n, nrhs, LU, lda, ipiv, B, ldb, trans, (hipStream_t)stream, perm, Y);
 }
 
 extern "C" int mxlu_schur_update_f64(int64_t M, int64_t N, int64_t K, const double *A,
