@@ -234,15 +234,23 @@ __global__ __launch_bounds__(256, 2) void lp_schur16_kernel(
 // each pair of MFMA blocks being interleaved as in the 16-bit form.
 constexpr int kTm8 = 128, kTn8 = 128;
 constexpr int BK8 = kLp8Kc;
-constexpr int kNs8 = 2;
 static_assert(kTm8 == kLp8Tile && kTn8 == kLp8Tile, "tile and packing must agree");
 
-template <int FMT>
-__global__ __launch_bounds__(256, 2) void lp_schur8_kernel(
+// vmcnt(n) for the waits of the rings below (gfx9 encoding: vmcnt bits [3:0]
+// and [15:14], expcnt and lgkmcnt left at their maxima)
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt(0x0F70 | (N & 15) | ((N >> 4) << 14));
+}
+
+template <int FMT, int NS>
+__global__ __launch_bounds__(256, NS <= 2 ? 2 : 1) void lp_schur8_kernel(
     int64_t M, int64_t N, int K, const uint8_t *__restrict__ Lq, int64_t Mp,
     const float *__restrict__ sL, const uint8_t *__restrict__ Uq, int64_t Np,
     const float *__restrict__ sU, int tile, uint16_t *__restrict__ C, int64_t ldc, int tiles_m,
     int tiles_n) {
+    constexpr int kNs8 = NS;
     constexpr int SA = kTm8 * BK8, SB = kTn8 * BK8;   // bytes per stage
     constexpr int NA = SA / 4 / 1024, NB = SB / 4 / 1024;
     __shared__ __attribute__((aligned(1024))) uint8_t ring[kNs8][SA + SB];
@@ -330,12 +338,19 @@ __global__ __launch_bounds__(256, 2) void lp_schur8_kernel(
     };
 
     const int nk = K / BK8;
-    static_assert(kNs8 == 2, "the wait below assumes two stages");
-    issue(0, 0);
+    constexpr int kLoads = NA + NB;   // loads per wave and chunk
+#pragma unroll
+    for (int c = 0; c < kNs8 - 1; ++c)
+        if (c < nk) issue(c, c);
     for (int kt = 0; kt < nk; ++kt) {
-        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): chunk kt (and the C loads) landed
-        __syncthreads();                      // every wave's part; stage (kt + 1) % 2 free
-        if (kt + 1 < nk) issue(kt + 1, (kt + 1) % kNs8);
+        // chunk kt (and the C loads, issued first) has landed once at most
+        // min(NS - 2, nk - 1 - kt) later chunks are outstanding
+        const int later = min(kNs8 - 2, nk - 1 - kt);
+        if (kNs8 >= 4 && later >= 2) wait_vmcnt<2 * kLoads>();
+        else if (kNs8 >= 3 && later >= 1) wait_vmcnt<kLoads>();
+        else wait_vmcnt<0>();
+        __syncthreads();   // every wave's part of chunk kt; stage (kt - 1) % NS free
+        if (kt + kNs8 - 1 < nk) issue(kt + kNs8 - 1, (kt + kNs8 - 1) % kNs8);
         const uint8_t *as = &ring[kt % kNs8][0];
         const uint8_t *bs = &ring[kt % kNs8][SA];
         v8i a[4], b[4];
@@ -424,12 +439,17 @@ int lp_schur_update_fp8(int fmt, int64_t M, int64_t N, int K, const uint8_t *Lq,
     }
     const int64_t tiles_m = (M + kTm8 - 1) / kTm8, tiles_n = (N + kTn8 - 1) / kTn8;
     const dim3 grid((unsigned)(tiles_m * tiles_n));
+    // two stages with two workgroups per CU: measured faster than three or
+    // four stages with one workgroup per CU (4.5 s against 3.2 s per solve at
+    // N = 131072), whose single wave per SIMD leaves the LDS reads and the
+    // epilogue exposed
+    constexpr int kStages = 2;
     if (fmt == kFmtBf16)
-        hipLaunchKernelGGL(lp_schur8_kernel<kFmtBf16>, grid, dim3(256), 0, s, M, N, K, Lq, Mp, sL,
-                           Uq, Np, sU, tile, C, ldc, (int)tiles_m, (int)tiles_n);
+        hipLaunchKernelGGL((lp_schur8_kernel<kFmtBf16, kStages>), grid, dim3(256), 0, s, M, N, K, Lq,
+                           Mp, sL, Uq, Np, sU, tile, C, ldc, (int)tiles_m, (int)tiles_n);
     else
-        hipLaunchKernelGGL(lp_schur8_kernel<kFmtFp16>, grid, dim3(256), 0, s, M, N, K, Lq, Mp, sL,
-                           Uq, Np, sU, tile, C, ldc, (int)tiles_m, (int)tiles_n);
+        hipLaunchKernelGGL((lp_schur8_kernel<kFmtFp16, kStages>), grid, dim3(256), 0, s, M, N, K, Lq,
+                           Mp, sL, Uq, Np, sU, tile, C, ldc, (int)tiles_m, (int)tiles_n);
     MXLU_LAUNCH_CHECK();
     return 0;
 }

@@ -64,33 +64,50 @@ __global__ void f32_to_lp_kernel(int64_t rows, int64_t cols, const float *__rest
 
 // ---------------------------------------------------------------- panel leaf
 // Inner block [c, c+ib) of the FP32 panel P (m x kb, leading dimension ldp).
-// Every workgroup factors the ib x ib diagonal block in LDS (no pivoting);
+// In every workgroup, wave 0 factors the ib x ib diagonal block in its
+// registers (no pivoting) and leaves it in LDS;
 // workgroups [0, nrow) then finish rows c+ib.. of the block columns (row
 // TRSM with U of the diagonal block), workgroups [nrow, nrow+ncol) finish
 // rows c..c+ib of the panel columns right of the block (unit-lower TRSM).
-__global__ __launch_bounds__(256) void lp_leaf_nopiv_kernel(int m, int kb, int c, int ib,
+// FULL: ib == kLpIb, the loops carry no width predicates (every loop is
+// unrolled at compile time, so the rows stay in registers).
+template <bool FULL>
+__global__ __launch_bounds__(256) void lp_leaf_nopiv_kernel(int m, int kb, int c, int ib_arg,
                                                             float *__restrict__ P, int64_t ldp,
                                                             int nrow, int *__restrict__ info,
                                                             int64_t col_base) {
     __shared__ float D[kLpIb][kLpIb + 1];
+    const int ib = FULL ? kLpIb : ib_arg;
     const int tid = threadIdx.x;
-    for (int t = tid; t < ib * ib; t += 256) {
-        const int i = t % ib, j = t / ib;
-        D[i][j] = P[(size_t)(c + i) + (size_t)(c + j) * ldp];
+    if (tid < 64) {
+        // wave 0 factors the diagonal block in registers: lane i holds row i;
+        // at step j the pivot row's values come from lane j by readlane (the
+        // lanes of one wave run in lockstep, so no barrier is needed), and
+        // every element takes its terms in the order of the column loop
+        float x[kLpIb];
+#pragma unroll
+        for (int k = 0; k < kLpIb; ++k)
+            x[k] = (tid < ib && k < ib) ? P[(size_t)(c + tid) + (size_t)(c + k) * ldp] : 0.0f;
+#pragma unroll
+        for (int j = 0; j < kLpIb; ++j) {
+            if (j < ib) {
+                const float piv = __builtin_bit_cast(
+                    float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x[j]), j));
+                // an exactly zero pivot leaves its column unscaled (it is reported)
+                if (tid > j && tid < ib && piv != 0.0f) x[j] = x[j] / piv;
+#pragma unroll
+                for (int col = j + 1; col < kLpIb; ++col) {
+                    const float u = __builtin_bit_cast(
+                        float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x[col]), j));
+                    if (tid > j && tid < ib && col < ib) x[col] = fmaf(-x[j], u, x[col]);
+                }
+            }
+        }
+        if (tid < ib)
+#pragma unroll
+            for (int k = 0; k < kLpIb; ++k) D[tid][k] = x[k];
     }
     __syncthreads();
-    for (int j = 0; j < ib; ++j) {
-        const float piv = D[j][j];
-        // an exactly zero pivot leaves its column unscaled (it is reported)
-        if (tid > j && tid < ib && piv != 0.0f) D[tid][j] = D[tid][j] / piv;
-        __syncthreads();
-        const int w = ib - j - 1;
-        for (int t = tid; t < w * w; t += 256) {
-            const int i = j + 1 + t % w, col = j + 1 + t / w;
-            D[i][col] = fmaf(-D[i][j], D[j][col], D[i][col]);
-        }
-        __syncthreads();
-    }
     if (blockIdx.x == 0) {
         for (int t = tid; t < ib * ib; t += 256) {
             const int i = t % ib, j = t / ib;
@@ -113,11 +130,13 @@ __global__ __launch_bounds__(256) void lp_leaf_nopiv_kernel(int m, int kb, int c
             x[k] = (k < ib) ? P[(size_t)r + (size_t)(c + k) * ldp] : 0.0f;
 #pragma unroll
         for (int k = 0; k < kLpIb; ++k) {
-            if (k >= ib) break;
-            if (D[k][k] != 0.0f) x[k] = x[k] / D[k][k];
+            if (k < ib) {
+                const float dkk = D[k][k];
+                if (dkk != 0.0f) x[k] = x[k] / dkk;
 #pragma unroll
-            for (int col = k + 1; col < kLpIb; ++col)
-                if (col < ib) x[col] = fmaf(-x[k], D[k][col], x[col]);
+                for (int col = k + 1; col < kLpIb; ++col)
+                    if (col < ib) x[col] = fmaf(-x[k], D[k][col], x[col]);
+            }
         }
 #pragma unroll
         for (int k = 0; k < kLpIb; ++k)
@@ -131,10 +150,11 @@ __global__ __launch_bounds__(256) void lp_leaf_nopiv_kernel(int m, int kb, int c
             y[k] = (k < ib) ? P[(size_t)(c + k) + (size_t)q * ldp] : 0.0f;
 #pragma unroll
         for (int k = 0; k < kLpIb; ++k) {
-            if (k >= ib) break;
+            if (k < ib) {
 #pragma unroll
-            for (int i = k + 1; i < kLpIb; ++i)
-                if (i < ib) y[i] = fmaf(-D[i][k], y[k], y[i]);
+                for (int i = k + 1; i < kLpIb; ++i)
+                    if (i < ib) y[i] = fmaf(-D[i][k], y[k], y[i]);
+            }
         }
 #pragma unroll
         for (int k = 0; k < kLpIb; ++k)
@@ -198,6 +218,89 @@ __global__ __launch_bounds__(256) void gemm_f32_sub_kernel(int64_t M, int64_t N,
         for (int b = 0; b < 4; ++b) {
             const int64_t r = row0 + tr + 16 * a, cc = col0 + tc + 16 * b;
             if (r < M && cc < N) C[(size_t)r + (size_t)cc * ldc] = acc[a][b];
+        }
+}
+
+// Large-tile form for the panel's big updates: 128 x 128 tiles, 256 threads,
+// 8 x 8 outputs per thread (rows 4 ty + {0..3} and 64 + 4 ty + {0..3},
+// columns 4 tx + {0..3} and 64 + 4 tx + {0..3}), K in chunks of 16 staged
+// through two LDS buffers; the next chunk's global loads are in flight in
+// registers while the current one is used.  The same order of terms as the
+// small-tile form: one fused multiply-add per term in ascending k from C.
+constexpr int kG32Tile = 128, kG32Kc = 16, kG32Ld = kG32Tile + 4;
+
+__global__ __launch_bounds__(256) void gemm_f32_sub_big_kernel(int64_t M, int64_t N, int64_t K,
+                                                               const float *__restrict__ A,
+                                                               int64_t lda,
+                                                               const float *__restrict__ B,
+                                                               int64_t ldb, float *__restrict__ C,
+                                                               int64_t ldc, int tiles_m) {
+    __shared__ __attribute__((aligned(16))) float As[2][kG32Kc][kG32Ld];
+    __shared__ __attribute__((aligned(16))) float Bs[2][kG32Kc][kG32Ld];
+    const int tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
+    const int64_t row0 = (int64_t)tm * kG32Tile, col0 = (int64_t)tn * kG32Tile;
+    const int tid = threadIdx.x;
+    const int tx = tid & 15, ty = tid >> 4;
+    // global load roles: A rows (tid % 128), k = tid / 128 + 2 q; B k = tid % 16,
+    // columns tid / 16 + 16 q (q < 8)
+    const int ar = tid & 127, ak = tid >> 7;
+    const int bk = tid & 15, bc = tid >> 4;
+    float ra[8], rb[8];
+    auto load = [&](int64_t k0) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t r = row0 + ar, kk = k0 + ak + 2 * q;
+            ra[q] = (r < M && kk < K) ? A[(size_t)r + (size_t)kk * lda] : 0.0f;
+            const int64_t cc = col0 + bc + 16 * q, kb = k0 + bk;
+            rb[q] = (cc < N && kb < K) ? B[(size_t)kb + (size_t)cc * ldb] : 0.0f;
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            As[buf][ak + 2 * q][ar] = ra[q];
+            Bs[buf][bk][bc + 16 * q] = rb[q];
+        }
+    };
+    float acc[8][8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int64_t r = row0 + (i < 4 ? 4 * ty + i : 64 + 4 * ty + i - 4);
+            const int64_t cc = col0 + (j < 4 ? 4 * tx + j : 64 + 4 * tx + j - 4);
+            acc[i][j] = (r < M && cc < N) ? C[(size_t)r + (size_t)cc * ldc] : 0.0f;
+        }
+    const int nk = (int)((K + kG32Kc - 1) / kG32Kc);
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int buf = kt & 1;
+        if (kt + 1 < nk) load((int64_t)(kt + 1) * kG32Kc);
+        const int kc = (int)((K - (int64_t)kt * kG32Kc < kG32Kc) ? K - (int64_t)kt * kG32Kc : kG32Kc);
+        for (int k = 0; k < kc; ++k) {
+            const float4 a0 = *reinterpret_cast<const float4 *>(&As[buf][k][4 * ty]);
+            const float4 a1 = *reinterpret_cast<const float4 *>(&As[buf][k][64 + 4 * ty]);
+            const float4 b0 = *reinterpret_cast<const float4 *>(&Bs[buf][k][4 * tx]);
+            const float4 b1 = *reinterpret_cast<const float4 *>(&Bs[buf][k][64 + 4 * tx]);
+            const float av[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+            const float bv[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+#pragma unroll
+                for (int j = 0; j < 8; ++j) acc[i][j] = fmaf(-av[i], bv[j], acc[i][j]);
+        }
+        if (kt + 1 < nk) store(buf ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int64_t r = row0 + (i < 4 ? 4 * ty + i : 64 + 4 * ty + i - 4);
+            const int64_t cc = col0 + (j < 4 ? 4 * tx + j : 64 + 4 * tx + j - 4);
+            if (r < M && cc < N) C[(size_t)r + (size_t)cc * ldc] = acc[i][j];
         }
 }
 
@@ -430,6 +533,15 @@ int lp_store_f32(int fmt, int64_t rows, int64_t cols, const float *P, int64_t ld
 int gemm_f32_sub(int64_t M, int64_t N, int64_t K, const float *A, int64_t lda, const float *B,
                  int64_t ldb, float *C, int64_t ldc, hipStream_t s) {
     if (M <= 0 || N <= 0 || K <= 0) return 0;
+    {   // large-tile form when it still gives every CU a few tiles
+        const int64_t tm = (M + kG32Tile - 1) / kG32Tile, tn = (N + kG32Tile - 1) / kG32Tile;
+        if (K >= 32 && M >= 96 && N >= 96 && tm * tn >= 512 && tm * tn <= 0x7fffffff) {
+            hipLaunchKernelGGL(gemm_f32_sub_big_kernel, dim3((unsigned)(tm * tn)), dim3(256), 0, s,
+                               M, N, K, A, lda, B, ldb, C, ldc, (int)tm);
+            MXLU_LAUNCH_CHECK();
+            return 0;
+        }
+    }
     const int64_t tm = (M + 63) / 64, tn = (N + 63) / 64;
     if (tm * tn > 0x7fffffff) {
         set_error_msg("gemm_f32_sub: grid too large");
@@ -451,8 +563,13 @@ static int panel_nopiv_rec(int64_t m, int64_t c0, int64_t w, float *P, int64_t l
     if (w <= kLpIb) {
         const int64_t rows_below = m - c0 - w;
         const int nrow = (int)((rows_below + 255) / 256);
-        hipLaunchKernelGGL(lp_leaf_nopiv_kernel, dim3((unsigned)(nrow > 0 ? nrow : 1)), dim3(256), 0,
-                           s, (int)m, (int)(c0 + w), (int)c0, (int)w, P, ldp, nrow, info, col_base);
+        const dim3 grid((unsigned)(nrow > 0 ? nrow : 1));
+        if (w == kLpIb)
+            hipLaunchKernelGGL(lp_leaf_nopiv_kernel<true>, grid, dim3(256), 0, s, (int)m,
+                               (int)(c0 + w), (int)c0, (int)w, P, ldp, nrow, info, col_base);
+        else
+            hipLaunchKernelGGL(lp_leaf_nopiv_kernel<false>, grid, dim3(256), 0, s, (int)m,
+                               (int)(c0 + w), (int)c0, (int)w, P, ldp, nrow, info, col_base);
         MXLU_LAUNCH_CHECK();
         return 0;
     }
