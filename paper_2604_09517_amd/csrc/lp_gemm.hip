@@ -228,9 +228,9 @@ __global__ __launch_bounds__(256, 2) void lp_schur16_kernel(
 // blocks); two workgroups per CU.  One K chunk is 128 values (one MFMA K
 // step): 16 KB of L21 and 16 KB of U12, copied into a two-stage LDS ring with
 // 16-byte direct global->LDS loads (8 loads of 1 KB per wave and chunk).
-// The accumulators start at -C / (sL sU) (exact: power-of-two scales) and
-// take +Lq Uq, so that -acc sL sU = C - (Lq Uq) sL sU needs no operand
-// negation; C is read and written 16 bytes (8 rows) per lane, the A rows of
+// The accumulators start at zero and take +Lq Uq; the epilogue forms
+// C - acc sL sU (the scalings exact: powers of two), the order of the
+// definition; C is read and written 16 bytes (8 rows) per lane, the A rows of
 // each pair of MFMA blocks being interleaved as in the 16-bit form.
 constexpr int kTm8 = 128, kTn8 = 128;
 constexpr int BK8 = kLp8Kc;
@@ -268,52 +268,26 @@ __global__ __launch_bounds__(256, NS <= 2 ? 2 : 1) void lp_schur8_kernel(
     const int wm = wave & 1, wn = wave >> 1;
     const int li = lane & 15, lg = lane >> 4;
 
-    // accumulators <- -C / (sL sU).  Rows as in the 16-bit form: the A operand
-    // of MFMA block bi = 2p + h supplies tile row 32p + 2 li + h in lane li, so
-    // a lane's accumulators of blocks 2p, 2p + 1 cover 8 consecutive rows of
-    // one column (16 bytes of C; rows 0-3 and 4-7 each share a scale tile,
-    // tiles being multiples of 4).  Interior tiles with 16-byte aligned columns
-    // (uniform branch) issue all their loads back to back without checks.
+    // Rows as in the 16-bit form: the A operand of MFMA block bi = 2p + h
+    // supplies tile row 32p + 2 li + h in lane li, so a lane's accumulators of
+    // blocks 2p, 2p + 1 cover 8 consecutive rows of one column (16 bytes of C;
+    // rows 0-3 and 4-7 each share a scale tile, tiles being multiples of 4).
+    // The accumulators start at zero and the epilogue forms C - acc sL sU (the
+    // scalings are exact: powers of two), so the C tile is needed only at the
+    // end: interior tiles with 16-byte aligned columns (uniform branch) load it
+    // right after the first operand chunk, and its latency overlaps that
+    // chunk's.
     const bool full = row0 + kTm8 <= M && col0 + kTn8 <= N && (ldc & 7) == 0 &&
                       ((uintptr_t)C & 15) == 0;
     auto row_of = [&](int bi, int r) -> int64_t {
         return row0 + wm * 64 + 32 * (bi >> 1) + 2 * (4 * lg + r) + (bi & 1);
     };
     v4f acc[4][4];
-    if (full) {
 #pragma unroll
-        for (int pr = 0; pr < 2; ++pr)
+    for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-            for (int bj = 0; bj < 4; ++bj) {
-                const int64_t r8 = row0 + wm * 64 + 32 * pr + 8 * lg;
-                const int64_t c = col0 + wn * 64 + bj * 16 + li;
-                const uint4 v = *reinterpret_cast<const uint4 *>(&C[(size_t)r8 + (size_t)c * ldc]);
-                const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
-                const float su = sU[tix(c)];
-                const float inv_lo = 1.0f / (sL[tix(r8)] * su), inv_hi = 1.0f / (sL[tix(r8 + 4)] * su);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const float inv = r < 2 ? inv_lo : inv_hi;
-                    acc[2 * pr][bj][r] = -lp_to_f32<FMT>((uint16_t)w4[r]) * inv;
-                    acc[2 * pr + 1][bj][r] = -lp_to_f32<FMT>((uint16_t)(w4[r] >> 16)) * inv;
-                }
-            }
-    } else {
-#pragma unroll
-        for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-            for (int bj = 0; bj < 4; ++bj) {
-                const int64_t c = col0 + wn * 64 + bj * 16 + li;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int64_t row = row_of(bi, r);
-                    acc[bi][bj][r] = (row < M && c < N)
-                                         ? -lp_to_f32<FMT>(C[(size_t)row + (size_t)c * ldc]) /
-                                               (sL[tix(row)] * sU[tix(c)])
-                                         : 0.0f;
-                }
-            }
-    }
+        for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+    uint4 cv[2][4];
 
     const char *gA = reinterpret_cast<const char *>(Lq + (size_t)row0 * BK8) + wave * (SA / 4) + lane * 16;
     const char *gB = reinterpret_cast<const char *>(Uq + (size_t)col0 * BK8) + wave * (SB / 4) + lane * 16;
@@ -342,9 +316,19 @@ __global__ __launch_bounds__(256, NS <= 2 ? 2 : 1) void lp_schur8_kernel(
 #pragma unroll
     for (int c = 0; c < kNs8 - 1; ++c)
         if (c < nk) issue(c, c);
+    if (full) {
+#pragma unroll
+        for (int pr = 0; pr < 2; ++pr)
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj) {
+                const int64_t r8 = row0 + wm * 64 + 32 * pr + 8 * lg;
+                const int64_t c = col0 + wn * 64 + bj * 16 + li;
+                cv[pr][bj] = *reinterpret_cast<const uint4 *>(&C[(size_t)r8 + (size_t)c * ldc]);
+            }
+    }
     for (int kt = 0; kt < nk; ++kt) {
-        // chunk kt (and the C loads, issued first) has landed once at most
-        // min(NS - 2, nk - 1 - kt) later chunks are outstanding
+        // chunk kt has landed once at most min(NS - 2, nk - 1 - kt) later
+        // chunks are outstanding (the C loads were issued before them)
         const int later = min(kNs8 - 2, nk - 1 - kt);
         if (kNs8 >= 4 && later >= 2) wait_vmcnt<2 * kLoads>();
         else if (kNs8 >= 3 && later >= 1) wait_vmcnt<kLoads>();
@@ -367,6 +351,7 @@ __global__ __launch_bounds__(256, NS <= 2 ? 2 : 1) void lp_schur8_kernel(
                     a[bi], b[bj], acc[bi][bj], 0, 0, 0, 127, 0, 127);
     }
 
+    // C <- round(fp32(C) - acc sL sU)
     if (full) {
 #pragma unroll
         for (int pr = 0; pr < 2; ++pr)
@@ -376,12 +361,15 @@ __global__ __launch_bounds__(256, NS <= 2 ? 2 : 1) void lp_schur8_kernel(
                 const int64_t c = col0 + wn * 64 + bj * 16 + li;
                 const float su = sU[tix(c)];
                 const float sc_lo = sL[tix(r8)] * su, sc_hi = sL[tix(r8 + 4)] * su;
+                const uint32_t c4[4] = {cv[pr][bj].x, cv[pr][bj].y, cv[pr][bj].z, cv[pr][bj].w};
                 uint32_t w4[4];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const float sc = r < 2 ? sc_lo : sc_hi;
-                    w4[r] = (uint32_t)f32_to_lp<FMT>(-acc[2 * pr][bj][r] * sc) |
-                            ((uint32_t)f32_to_lp<FMT>(-acc[2 * pr + 1][bj][r] * sc) << 16);
+                    const float lo = lp_to_f32<FMT>((uint16_t)c4[r]) - acc[2 * pr][bj][r] * sc;
+                    const float hi =
+                        lp_to_f32<FMT>((uint16_t)(c4[r] >> 16)) - acc[2 * pr + 1][bj][r] * sc;
+                    w4[r] = (uint32_t)f32_to_lp<FMT>(lo) | ((uint32_t)f32_to_lp<FMT>(hi) << 16);
                 }
                 *reinterpret_cast<uint4 *>(&C[(size_t)r8 + (size_t)c * ldc]) =
                     make_uint4(w4[0], w4[1], w4[2], w4[3]);
@@ -395,9 +383,11 @@ __global__ __launch_bounds__(256, NS <= 2 ? 2 : 1) void lp_schur8_kernel(
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int64_t row = row_of(bi, r);
-                    if (row < M && c < N)
-                        C[(size_t)row + (size_t)c * ldc] =
-                            f32_to_lp<FMT>(-acc[bi][bj][r] * (sL[tix(row)] * sU[tix(c)]));
+                    if (row < M && c < N) {
+                        uint16_t *cp = &C[(size_t)row + (size_t)c * ldc];
+                        *cp = f32_to_lp<FMT>(lp_to_f32<FMT>(*cp) -
+                                             acc[bi][bj][r] * (sL[tix(row)] * sU[tix(c)]));
+                    }
                 }
             }
     }

@@ -306,19 +306,21 @@ __global__ __launch_bounds__(256) void gemm_f32_sub_big_kernel(int64_t M, int64_
 
 // ---------------------------------------------------------------- FP32 TRSM
 // B (kb x ncols) <- L^-1 B, L unit lower kb x kb (kb <= 256), thread per row,
-// 16 columns per workgroup, one LDS barrier per step; each thread reads its
-// row of L 32 columns at a time into registers, the next 32 in flight.
+// NC columns per workgroup, one LDS barrier per step; each thread reads its
+// row of L 32 columns at a time into registers, the next 32 in flight.  More
+// columns per workgroup spread each barrier over more multiply-adds.
+template <int NC>
 __global__ __launch_bounds__(256) void trsm_f32_llnu_kernel(int kb, int64_t ncols,
                                                             const float *__restrict__ L,
                                                             int64_t ldl, float *__restrict__ B,
                                                             int64_t ldb) {
-    __shared__ float xs[2][16];
+    __shared__ float xs[2][NC];
     const int i = threadIdx.x;
-    const int64_t c0 = (int64_t)blockIdx.x * 16;
-    const int nc = (int)((ncols - c0 < 16) ? ncols - c0 : 16);
-    float b[16];
+    const int64_t c0 = (int64_t)blockIdx.x * NC;
+    const int nc = (int)((ncols - c0 < NC) ? ncols - c0 : NC);
+    float b[NC];
 #pragma unroll
-    for (int c = 0; c < 16; ++c)
+    for (int c = 0; c < NC; ++c)
         b[c] = (i < kb && c < nc) ? B[(size_t)i + (size_t)(c0 + c) * ldb] : 0.0f;
     // the thread's row of L in chunks of 32 columns, the next chunk in flight
     // while the current one is used
@@ -336,21 +338,22 @@ __global__ __launch_bounds__(256) void trsm_f32_llnu_kernel(int kb, int64_t ncol
 #pragma unroll
         for (int kk = 0; kk < 32; ++kk) {
             const int k = k0 + kk;
-            if (k >= kb) break;
-            if (i == k)
+            if (k < kb) {
+                if (i == k)
 #pragma unroll
-                for (int c = 0; c < 16; ++c) xs[k & 1][c] = b[c];
-            lds_barrier();
-            if (i > k && i < kb)
+                    for (int c = 0; c < NC; ++c) xs[k & 1][c] = b[c];
+                lds_barrier();
+                if (i > k && i < kb)
 #pragma unroll
-                for (int c = 0; c < 16; ++c) b[c] = fmaf(-lc[kk], xs[k & 1][c], b[c]);
+                    for (int c = 0; c < NC; ++c) b[c] = fmaf(-lc[kk], xs[k & 1][c], b[c]);
+            }
         }
 #pragma unroll
         for (int kk = 0; kk < 32; ++kk) lc[kk] = ln[kk];
     }
     if (i < kb)
 #pragma unroll
-        for (int c = 0; c < 16; ++c)
+        for (int c = 0; c < NC; ++c)
             if (c < nc) B[(size_t)i + (size_t)(c0 + c) * ldb] = b[c];
 }
 
@@ -594,8 +597,11 @@ int trsm_f32_llnu(int64_t kb, int64_t ncols, const float *L, int64_t ldl, float 
                   hipStream_t s) {
     for (int64_t b0 = 0; b0 < kb; b0 += 256) {
         const int bb = (int)((kb - b0 < 256) ? kb - b0 : 256);
-        hipLaunchKernelGGL(trsm_f32_llnu_kernel, dim3((unsigned)((ncols + 15) / 16)), dim3(256), 0,
-                           s, bb, ncols, L + (size_t)b0 + (size_t)b0 * ldl, ldl, B + b0, ldb);
+        // 16 columns per workgroup: measured faster than 64 (whose 183
+        // registers leave two waves per SIMD)
+        const float *Lb = L + (size_t)b0 + (size_t)b0 * ldl;
+        hipLaunchKernelGGL(trsm_f32_llnu_kernel<16>, dim3((unsigned)((ncols + 15) / 16)),
+                           dim3(256), 0, s, bb, ncols, Lb, ldl, B + b0, ldb);
         MXLU_LAUNCH_CHECK();
         if (b0 + bb < kb) {
             int rc = gemm_f32_sub(kb - b0 - bb, ncols, bb, L + (size_t)(b0 + bb) + (size_t)b0 * ldl,
