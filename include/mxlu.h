@@ -251,6 +251,27 @@ int mxp_solve(int64_t n, int64_t nrhs, const double *A, int64_t lda,
               const mxp_opts *opts, mxp_report *report, void *stream);
 
 /*
+ * mxp_solve_seeded -- mxp_solve for the seeded synthetic matrix, regenerated
+ * wherever it is needed instead of being stored (Sec. II-B names scalable
+ * generation of the input matrix among what HPL-MxP asks for): the
+ * conversion to the storage precision and every FP64 residual r = b - op(A) x
+ * compute a_ij from its counter, so no n x n FP64 array exists (at
+ * n = 131072 that is 128 GiB of HBM not needed).  The matrix is the one
+ * mxlu_fill_uniform(n, n, ., seed, stream_id) writes, and with dominant = 1
+ * the one mxlu_make_diag_dominant then makes (its diagonal, the sums of the
+ * rows' absolute off-diagonal values, is computed first by one pass over the
+ * regenerated entries into n doubles of internal scratch).  Arguments from
+ * nrhs on, results and the order of every floating-point operation are those
+ * of mxp_solve on that matrix (the two give the same bits); work_bytes as
+ * mxp_workspace_bytes(n, n, opts).  Returns as mxp_solve (-k for the k-th
+ * argument of this signature).
+ */
+int mxp_solve_seeded(int64_t n, uint64_t seed, uint64_t stream_id, int dominant, int64_t nrhs,
+                     const double *B, int64_t ldb, double *X, int64_t ldx, void *work,
+                     size_t work_bytes, int32_t *ipiv, const mxp_opts *opts, mxp_report *report,
+                     void *stream);
+
+/*
  * Seeded synthetic inputs (not part of the method).  Element (i, j) of a
  * rows x cols matrix is u(j*rows + i) with the counter-based generator
  *   mix(z) = SplitMix64 finaliser, key = mix(seed + G (stream_id + 1)),

@@ -60,6 +60,8 @@ SIGNATURES = {
     "mxp_convert": (_int, [_i32, _i64, _i64, _vp, _i64, _vp, _i64, _vp]),
     "mxp_solve": (_int, [_i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _sz, _vp,
                          ctypes.POINTER(MxpOpts), ctypes.POINTER(MxpReport), _vp]),
+    "mxp_solve_seeded": (_int, [_i64, _u64, _u64, _int, _i64, _vp, _i64, _vp, _i64, _vp, _sz,
+                                _vp, ctypes.POINTER(MxpOpts), ctypes.POINTER(MxpReport), _vp]),
     "mxlu_fill_uniform": (_int, [_i64, _i64, _vp, _i64, _u64, _u64, _vp]),
     "mxlu_make_diag_dominant": (_int, [_i64, _vp, _i64, _vp]),
     "mxlu_scaled_residual": (_int, [_i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _int,

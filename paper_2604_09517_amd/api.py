@@ -252,6 +252,35 @@ def mxp_solve(A, B, X=None, work=None, ipiv=None, opts=None, allow_notconv=False
     return X, report, work, ipiv
 
 
+def mxp_solve_seeded(n, seed, stream_id, B, dominant=True, X=None, work=None, ipiv=None,
+                     opts=None, allow_notconv=False, **kw):
+    """Mixed-precision solve of the seeded matrix regenerated on the fly (no
+    FP64 copy of A).  Returns (X, report dict, work, ipiv)."""
+    opts = opts if opts is not None else mxp_options(**kw)
+    pb, nb_rows, nrhs, ldb = _mat(B, "B")
+    if nb_rows != n:
+        raise ValueError("B must have n rows")
+    if X is None:
+        X = fortran_empty(n, nrhs, device=B.device) if B.dim() == 2 else torch.empty(
+            n, dtype=torch.float64, device=B.device)
+    px, _, _, ldx = _mat(X, "X")
+    need = mxp_workspace_bytes(n, opts, n)
+    if work is None:
+        work = torch.empty(max(1, need), dtype=torch.uint8, device=B.device)
+    if opts.pivot and ipiv is None:
+        ipiv = torch.empty(n, dtype=torch.int32, device=B.device)
+    pp = ipiv.data_ptr() if (opts.pivot and ipiv is not None) else None
+    rep = MxpReport()
+    rc = lib().mxp_solve_seeded(int(n), int(seed), int(stream_id), 1 if dominant else 0, nrhs, pb,
+                                ldb, px, ldx, work.data_ptr(), work.numel(), pp,
+                                ctypes.byref(opts), ctypes.byref(rep), _stream())
+    report = {f: getattr(rep, f) for f, _ in MxpReport._fields_}
+    if not (allow_notconv and rc == -1004):
+        check("mxp_solve_seeded", rc)
+    report["status"] = rc
+    return X, report, work, ipiv
+
+
 def exported_symbols():
     """Names the binding expects the library to export."""
     return list(_lib.SIGNATURES)

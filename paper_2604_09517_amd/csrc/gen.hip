@@ -8,17 +8,14 @@
 #include <cmath>
 #include <cstring>
 
+#include "asource.h"
 #include "common.h"
 
 namespace {
 
-constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
+constexpr uint64_t kGolden = mxlu::kGenGolden;
 
-__host__ __device__ inline uint64_t splitmix_finalise(uint64_t z) {
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
+__host__ __device__ inline uint64_t splitmix_finalise(uint64_t z) { return mxlu::gen_mix(z); }
 
 // One thread per element of a column strip; grid.y walks column blocks.
 __global__ void fill_uniform_kernel(int64_t rows, int64_t cols, double *A,
@@ -43,6 +40,20 @@ __global__ void diag_dominant_kernel(int64_t n, double *A, int64_t lda) {
     for (int64_t j = 0; j < n; ++j)
         if (j != i) s += fabs(MXLU_AT(A, i, j, lda));
     MXLU_AT(A, i, i, lda) = s;
+}
+
+// The diagonal of the seeded diagonally dominant matrix without storing the
+// matrix: diag[i] = sum over j != i of |u(j n + i)| (exact in any order, as
+// above), one thread per row.
+__global__ void gen_dominant_diag_kernel(int64_t n, uint64_t key, double *diag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t step = kGolden * (uint64_t)n;
+    uint64_t z = key + kGolden * ((uint64_t)i + 1ull);
+    double s = 0.0;
+    for (int64_t j = 0; j < n; ++j, z += step)
+        if (j != i) s += fabs(mxlu::gen_value(z));
+    diag[i] = s;
 }
 
 // Residual check: per row i and column c, r = b - sum_j op(A)_ij x_j and the
@@ -100,6 +111,16 @@ __global__ void absmax_kernel(int64_t n, const double *v, unsigned long long *ou
 }
 
 }  // namespace
+
+namespace mxlu {
+int gen_dominant_diag(int64_t n, uint64_t key, double *diag, hipStream_t s) {
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(gen_dominant_diag_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                       s, n, key, diag);
+    MXLU_LAUNCH_CHECK();
+    return 0;
+}
+}  // namespace mxlu
 
 extern "C" int mxlu_fill_uniform(int64_t rows, int64_t cols, double *A,
                                  int64_t lda, uint64_t seed, uint64_t stream_id,

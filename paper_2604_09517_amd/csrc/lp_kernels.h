@@ -5,6 +5,8 @@
 
 #include <cstdint>
 
+#include "asource.h"
+
 namespace mxlu {
 
 constexpr int kLpIb = 32;   // inner block width of the FP32 panel factorization
@@ -12,6 +14,11 @@ constexpr int kLpIb = 32;   // inner block width of the FP32 panel factorization
 // F (rows x cols, 16-bit) <- round-to-nearest-even of A (FP64).
 int lp_convert(int fmt, int64_t rows, int64_t cols, const double *A, int64_t lda, uint16_t *F,
                int64_t ldf, hipStream_t s);
+// The same for the n x n matrix of `src` (in memory, or regenerated from its
+// seed); gen_dominant_diag fills the diagonal of the seeded dominant matrix.
+int lp_convert_src(int fmt, int64_t n, const ASource &src, uint16_t *F, int64_t ldf,
+                   hipStream_t s);
+int gen_dominant_diag(int64_t n, uint64_t key, double *diag, hipStream_t s);
 // P (FP32) <- F (16-bit), exact; F <- round(P).
 int lp_load_f32(int fmt, int64_t rows, int64_t cols, const uint16_t *F, int64_t ldf, float *P,
                 int64_t ldp, hipStream_t s);

@@ -18,6 +18,7 @@
 
 #include <algorithm>
 
+#include "asource.h"
 #include "common.h"
 #include "lp_common.h"
 #include "lp_kernels.h"
@@ -42,6 +43,17 @@ __global__ void convert_kernel(int64_t rows, int64_t cols, const double *__restr
     if (i >= rows) return;
     for (int64_t j = blockIdx.y; j < cols; j += gridDim.y)
         F[(size_t)i + (size_t)j * (size_t)ldf] = f64_to_lp<FMT>(MXLU_AT(A, i, j, lda));
+}
+
+// The same rounding from the seeded generator's values (the FP64 matrix is
+// never stored): F[i, j] <- round(a_ij).
+template <int FMT>
+__global__ void convert_seeded_kernel(int64_t n, ASource src, uint16_t *__restrict__ F,
+                                      int64_t ldf) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int64_t j = blockIdx.y; j < n; j += gridDim.y)
+        F[(size_t)i + (size_t)j * (size_t)ldf] = f64_to_lp<FMT>(src.at(i, j));
 }
 
 template <int FMT>
@@ -503,6 +515,20 @@ int lp_convert(int fmt, int64_t rows, int64_t cols, const double *A, int64_t lda
     else
         hipLaunchKernelGGL(convert_kernel<kFmtFp16>, grid2(rows, cols), dim3(256), 0, s, rows, cols,
                            A, lda, F, ldf);
+    MXLU_LAUNCH_CHECK();
+    return 0;
+}
+
+int lp_convert_src(int fmt, int64_t n, const ASource &src, uint16_t *F, int64_t ldf,
+                   hipStream_t s) {
+    if (!src.seeded()) return lp_convert(fmt, n, n, src.A, src.lda, F, ldf, s);
+    if (n <= 0) return 0;
+    if (fmt == kFmtBf16)
+        hipLaunchKernelGGL(convert_seeded_kernel<kFmtBf16>, grid2(n, n), dim3(256), 0, s, n, src, F,
+                           ldf);
+    else
+        hipLaunchKernelGGL(convert_seeded_kernel<kFmtFp16>, grid2(n, n), dim3(256), 0, s, n, src, F,
+                           ldf);
     MXLU_LAUNCH_CHECK();
     return 0;
 }

@@ -63,7 +63,7 @@ struct Timer {
 };
 
 // ------------------------------------------------------------------ factor
-int lp_factorize(const mxp_opts &o, int64_t n, const double *A, int64_t lda, uint16_t *F,
+int lp_factorize(const mxp_opts &o, int64_t n, const ASource &src, uint16_t *F,
                  int64_t ldf, int32_t *ipiv, int *info_host, hipStream_t s, double *t_conv,
                  double *t_fact) {
     const int fmt = (o.prec == MXLU_PREC_BF16) ? kFmtBf16 : kFmtFp16;
@@ -104,7 +104,7 @@ int lp_factorize(const mxp_opts &o, int64_t n, const double *A, int64_t lda, uin
     tc.start();
     {
         PhaseScope ph(kPhaseConvert, s, 10.0 * (double)n * (double)n);
-        MXLU_TRY(lp_convert(fmt, n, n, A, lda, F, ldf, s));
+        MXLU_TRY(lp_convert_src(fmt, n, src, F, ldf, s));
     }
     tc.stop();
     tf.start();
@@ -179,8 +179,8 @@ int lp_factorize(const mxp_opts &o, int64_t n, const double *A, int64_t lda, uin
 // ------------------------------------------------------------------ refine
 struct RefineCtx {
     int fmt, trans;
-    int64_t n, lda, ldf;
-    const double *A;
+    int64_t n, ldf;
+    ASource src;   // the FP64 matrix: in memory or regenerated from its seed
     const uint16_t *F;
     const int32_t *perm;
     hipStream_t s;
@@ -203,7 +203,7 @@ int precond(RefineCtx &c, const double *r, double *d) {
 int residual(RefineCtx &c, const double *b, const double *x, double bnorm, double *rho) {
     MXLU_HIP_TRY(hipMemsetAsync(c.stats, 0, 3 * sizeof(unsigned long long), c.s));
     const bool need_anorm = c.anorm < 0.0;
-    MXLU_TRY(gemv_f64(c.trans, c.n, c.A, c.lda, x, b, c.r, c.part, need_anorm ? c.apart : nullptr,
+    MXLU_TRY(gemv_f64(c.trans, c.n, c.src, x, b, c.r, c.part, need_anorm ? c.apart : nullptr,
                       c.nsplit, c.stats, c.s));
     unsigned long long h[3];
     MXLU_HIP_TRY(hipMemcpyAsync(h, c.stats, sizeof(h), hipMemcpyDeviceToHost, c.s));
@@ -238,7 +238,7 @@ int gmres_cycle(RefineCtx &c, double *x, int mmax, int *steps) {
     for (int j = 0; j < mmax; ++j) {
         double *vj = c.V + (size_t)j * ldv;
         // w = op(A) v_j ; z = M w
-        MXLU_TRY(gemv_f64(c.trans, n, c.A, c.lda, vj, nullptr, c.w, c.part, nullptr, c.nsplit,
+        MXLU_TRY(gemv_f64(c.trans, n, c.src, vj, nullptr, c.w, c.part, nullptr, c.nsplit,
                           nullptr, c.s));
         MXLU_TRY(precond(c, c.w, c.z));
         // classical Gram-Schmidt, twice
@@ -376,13 +376,11 @@ extern "C" int mxp_convert(int32_t prec, int64_t rows, int64_t cols, const doubl
                       (hipStream_t)stream);
 }
 
-extern "C" int mxp_solve(int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *B,
-                         int64_t ldb, double *X, int64_t ldx, void *work, size_t work_bytes,
-                         int32_t *ipiv, const mxp_opts *opts, mxp_report *report, void *stream) {
-    if (n < 0 || n > 0x7fffffff) return -1;
-    if (nrhs < 0) return -2;
-    if (n > 0 && !A) return -3;
-    if (lda < std::max<int64_t>(1, n)) return -4;
+namespace {
+
+// Argument checks shared by both forms (all but the matrix's own arguments).
+int mxp_check(int64_t n, int64_t nrhs, const double *B, int64_t ldb, double *X, int64_t ldx,
+              void *work, int32_t *ipiv, const mxp_opts *opts) {
     if (n > 0 && nrhs > 0 && !B) return -5;
     if (ldb < std::max<int64_t>(1, n)) return -6;
     if (n > 0 && nrhs > 0 && !X) return -7;
@@ -398,15 +396,14 @@ extern "C" int mxp_solve(int64_t n, int64_t nrhs, const double *A, int64_t lda, 
         o.trans > 1 || o.factor_steps < 0)
         return -12;
     if (o.pivot && !ipiv) return -11;
-    if (n > 0 && work_bytes < mxp_workspace_bytes(n, lda, opts)) return MXLU_E_WORKSPACE;
-    if (report) std::memset(report, 0, sizeof(*report));
-    if (n == 0 || nrhs == 0) {
-        if (report) report->converged = 1;
-        return 0;
-    }
-    if (int rc = check_device()) return rc;
-    clear_error();
-    hipStream_t s = (hipStream_t)stream;
+    return 0;
+}
+
+int mxp_impl(int64_t n, int64_t nrhs, const ASource &src, const double *B, int64_t ldb,
+             double *X, int64_t ldx, void *work, size_t work_bytes, int32_t *ipiv,
+             const mxp_opts *opts, mxp_report *report, hipStream_t s) {
+    const mxp_opts &o = *opts;
+    (void)work_bytes;
     const int fmt = (o.prec == MXLU_PREC_BF16) ? kFmtBf16 : kFmtFp16;
     const int64_t ldf = factor_ld(n);
     uint16_t *F = reinterpret_cast<uint16_t *>(work);
@@ -414,16 +411,15 @@ extern "C" int mxp_solve(int64_t n, int64_t nrhs, const double *A, int64_t lda, 
     double t_conv = 0.0, t_fact = 0.0;
     int info = 0;
     if (!o.reuse_factors)
-        MXLU_TRY(lp_factorize(o, n, A, lda, F, ldf, ipiv, &info, s, &t_conv, &t_fact));
+        MXLU_TRY(lp_factorize(o, n, src, F, ldf, ipiv, &info, s, &t_conv, &t_fact));
 
     Scratch scratch(s);
     RefineCtx c;
     c.fmt = fmt;
     c.trans = o.trans;
     c.n = n;
-    c.lda = lda;
     c.ldf = ldf;
-    c.A = A;
+    c.src = src;
     c.F = F;
     c.perm = nullptr;
     if (o.pivot) {
@@ -496,4 +492,60 @@ extern "C" int mxp_solve(int64_t n, int64_t nrhs, const double *A, int64_t lda, 
         return MXLU_E_NOTCONV;
     }
     return 0;
+}
+
+}  // namespace
+
+extern "C" int mxp_solve(int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *B,
+                         int64_t ldb, double *X, int64_t ldx, void *work, size_t work_bytes,
+                         int32_t *ipiv, const mxp_opts *opts, mxp_report *report, void *stream) {
+    if (n < 0 || n > 0x7fffffff) return -1;
+    if (nrhs < 0) return -2;
+    if (n > 0 && !A) return -3;
+    if (lda < std::max<int64_t>(1, n)) return -4;
+    if (int rc = mxp_check(n, nrhs, B, ldb, X, ldx, work, ipiv, opts)) return rc;
+    if (n > 0 && work_bytes < mxp_workspace_bytes(n, lda, opts)) return MXLU_E_WORKSPACE;
+    if (report) std::memset(report, 0, sizeof(*report));
+    if (n == 0 || nrhs == 0) {
+        if (report) report->converged = 1;
+        return 0;
+    }
+    if (int rc = check_device()) return rc;
+    clear_error();
+    ASource src;
+    src.A = A;
+    src.lda = lda;
+    src.n = n;
+    return mxp_impl(n, nrhs, src, B, ldb, X, ldx, work, work_bytes, ipiv, opts, report,
+                    (hipStream_t)stream);
+}
+
+extern "C" int mxp_solve_seeded(int64_t n, uint64_t seed, uint64_t stream_id, int dominant,
+                                int64_t nrhs, const double *B, int64_t ldb, double *X,
+                                int64_t ldx, void *work, size_t work_bytes, int32_t *ipiv,
+                                const mxp_opts *opts, mxp_report *report, void *stream) {
+    if (n < 0 || n > 0x7fffffff) return -1;
+    if (dominant != 0 && dominant != 1) return -4;
+    if (nrhs < 0) return -5;
+    if (int rc = mxp_check(n, nrhs, B, ldb, X, ldx, work, ipiv, opts)) return rc - 1;
+    if (n > 0 && work_bytes < mxp_workspace_bytes(n, n, opts)) return MXLU_E_WORKSPACE;
+    if (report) std::memset(report, 0, sizeof(*report));
+    if (n == 0 || nrhs == 0) {
+        if (report) report->converged = 1;
+        return 0;
+    }
+    if (int rc = check_device()) return rc;
+    clear_error();
+    hipStream_t s = (hipStream_t)stream;
+    Scratch scratch(s);
+    ASource src;
+    src.n = n;
+    src.key = gen_key(seed, stream_id);
+    if (dominant) {
+        double *diag = scratch.alloc_n<double>((size_t)n);
+        if (!diag) return MXLU_E_NOMEM;
+        MXLU_TRY(gen_dominant_diag(n, src.key, diag, s));
+        src.diag = diag;
+    }
+    return mxp_impl(n, nrhs, src, B, ldb, X, ldx, work, work_bytes, ipiv, opts, report, s);
 }

@@ -5,15 +5,18 @@
 
 #include <cstdint>
 
+#include "asource.h"
+
 namespace mxlu {
 
 constexpr int kTrsvBs = 256;   // block rows of the FP32 triangular solves
 
-// y = A x (b == NULL) or y = b - A x; op(A) = A (trans 0) or A^T (trans 1).
+// y = A x (b == NULL) or y = b - A x; op(A) = A (trans 0) or A^T (trans 1),
+// A in memory or regenerated from its seed (ASource).
 // part, asum_part: nsplit * n doubles (asum_part optional: |op(A)| row sums).
 // stats (optional, zeroed by the caller): [0] max|y|, [1] max row sum, [2] max|x|
 // as bit patterns of non-negative doubles.
-int gemv_f64(int trans, int64_t n, const double *A, int64_t lda, const double *x,
+int gemv_f64(int trans, int64_t n, const ASource &src, const double *x,
              const double *b, double *y, double *part, double *asum_part, int nsplit,
              unsigned long long *stats, hipStream_t s);
 // out[c] = V[:, c] . z for c < ncols; part holds ncols * nchunks doubles.

@@ -3,6 +3,7 @@
 // preconditioner M = U^-1 L^-1 P applied in FP32 to the low-precision factors.
 #include <hip/hip_runtime.h>
 
+#include "asource.h"
 #include "common.h"
 #include "lp_common.h"
 #include "refine_kernels.h"
@@ -21,9 +22,12 @@ __device__ __forceinline__ double bits_to_double(unsigned long long b) {
 
 // ---------------------------------------------------------------- GEMV
 // partial[s][i] = sum over columns j of split s of A[i, j] x[j] (ascending
-// j); with asum, the |A[i, j]| row sums of the split go to asum_part.
-__global__ __launch_bounds__(256) void gemv_n_partial_kernel(int64_t n, const double *__restrict__ A,
-                                                             int64_t lda,
+// j); with asum, the |A[i, j]| row sums of the split go to asum_part.  The
+// seeded form regenerates each A[i, j] from its counter (consecutive j of a
+// row step the counter by G n), so the matrix is never read from memory; its
+// terms are taken in the same order, so both forms give the same bits.
+template <bool SEEDED>
+__global__ __launch_bounds__(256) void gemv_n_partial_kernel(int64_t n, ASource src,
                                                              const double *__restrict__ x,
                                                              int64_t cps, double *__restrict__ part,
                                                              double *__restrict__ asum_part) {
@@ -32,20 +36,34 @@ __global__ __launch_bounds__(256) void gemv_n_partial_kernel(int64_t n, const do
     const int64_t j1 = (j0 + cps < n) ? j0 + cps : n;
     if (i >= n) return;
     double acc = 0.0, as = 0.0;
-    int64_t j = j0;
-    for (; j + 4 <= j1; j += 4) {
-        const double a0 = MXLU_AT(A, i, j, lda), a1 = MXLU_AT(A, i, j + 1, lda);
-        const double a2 = MXLU_AT(A, i, j + 2, lda), a3 = MXLU_AT(A, i, j + 3, lda);
-        acc = fma(a0, x[j], acc);
-        acc = fma(a1, x[j + 1], acc);
-        acc = fma(a2, x[j + 2], acc);
-        acc = fma(a3, x[j + 3], acc);
-        if (asum_part) as += fabs(a0) + fabs(a1) + fabs(a2) + fabs(a3);
-    }
-    for (; j < j1; ++j) {
-        const double a = MXLU_AT(A, i, j, lda);
-        acc = fma(a, x[j], acc);
-        if (asum_part) as += fabs(a);
+    if constexpr (!SEEDED) {
+        const double *__restrict__ A = src.A;
+        const int64_t lda = src.lda;
+        int64_t j = j0;
+        for (; j + 4 <= j1; j += 4) {
+            const double a0 = MXLU_AT(A, i, j, lda), a1 = MXLU_AT(A, i, j + 1, lda);
+            const double a2 = MXLU_AT(A, i, j + 2, lda), a3 = MXLU_AT(A, i, j + 3, lda);
+            acc = fma(a0, x[j], acc);
+            acc = fma(a1, x[j + 1], acc);
+            acc = fma(a2, x[j + 2], acc);
+            acc = fma(a3, x[j + 3], acc);
+            if (asum_part) as += fabs(a0) + fabs(a1) + fabs(a2) + fabs(a3);
+        }
+        for (; j < j1; ++j) {
+            const double a = MXLU_AT(A, i, j, lda);
+            acc = fma(a, x[j], acc);
+            if (asum_part) as += fabs(a);
+        }
+    } else {
+        // |a| sums of generator values are exact in any order (multiples of
+        // 2^-32 below 2^21 in size), so the grouping above does not matter
+        const uint64_t step = kGenGolden * (uint64_t)n;
+        uint64_t z = src.key + kGenGolden * ((uint64_t)j0 * (uint64_t)n + (uint64_t)i + 1ull);
+        for (int64_t j = j0; j < j1; ++j, z += step) {
+            const double a = (src.diag && j == i) ? src.diag[i] : gen_value(z);
+            acc = fma(a, x[j], acc);
+            if (asum_part) as += fabs(a);
+        }
     }
     part[(size_t)blockIdx.y * n + i] = acc;
     if (asum_part) asum_part[(size_t)blockIdx.y * n + i] = as;
@@ -53,8 +71,8 @@ __global__ __launch_bounds__(256) void gemv_n_partial_kernel(int64_t n, const do
 
 // Transposed: part[s][i] = sum over rows j of split s of A[j, i] x[j]; one
 // wave per i (column i of A is contiguous).
-__global__ __launch_bounds__(256) void gemv_t_partial_kernel(int64_t n, const double *__restrict__ A,
-                                                             int64_t lda,
+template <bool SEEDED>
+__global__ __launch_bounds__(256) void gemv_t_partial_kernel(int64_t n, ASource src,
                                                              const double *__restrict__ x,
                                                              int64_t cps, double *__restrict__ part,
                                                              double *__restrict__ asum_part) {
@@ -64,10 +82,19 @@ __global__ __launch_bounds__(256) void gemv_t_partial_kernel(int64_t n, const do
     const int64_t j1 = (j0 + cps < n) ? j0 + cps : n;
     if (i >= n) return;
     double acc = 0.0, as = 0.0;
-    for (int64_t j = j0 + lane; j < j1; j += 64) {
-        const double a = MXLU_AT(A, j, i, lda);
-        acc = fma(a, x[j], acc);
-        as += fabs(a);
+    if constexpr (!SEEDED) {
+        for (int64_t j = j0 + lane; j < j1; j += 64) {
+            const double a = MXLU_AT(src.A, j, i, src.lda);
+            acc = fma(a, x[j], acc);
+            as += fabs(a);
+        }
+    } else {
+        uint64_t z = src.key + kGenGolden * ((uint64_t)i * (uint64_t)n + (uint64_t)(j0 + lane) + 1ull);
+        for (int64_t j = j0 + lane; j < j1; j += 64, z += 64ull * kGenGolden) {
+            const double a = (src.diag && j == i) ? src.diag[i] : gen_value(z);
+            acc = fma(a, x[j], acc);
+            as += fabs(a);
+        }
     }
     for (int off = 32; off > 0; off >>= 1) {
         acc += __shfl_xor(acc, off);
@@ -476,17 +503,24 @@ unsigned g1(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 namespace mxlu {
 
-int gemv_f64(int trans, int64_t n, const double *A, int64_t lda, const double *x,
+int gemv_f64(int trans, int64_t n, const ASource &src, const double *x,
              const double *b, double *y, double *part, double *asum_part, int nsplit,
              unsigned long long *stats, hipStream_t s) {
     if (n <= 0) return 0;
     const int64_t cps = (n + nsplit - 1) / nsplit;
-    if (trans == 0)
-        hipLaunchKernelGGL(gemv_n_partial_kernel, dim3(g1(n), (unsigned)nsplit), dim3(256), 0, s,
-                           n, A, lda, x, cps, part, asum_part);
+    const dim3 gn(g1(n), (unsigned)nsplit), gt((unsigned)((n + 3) / 4), (unsigned)nsplit);
+    if (trans == 0 && !src.seeded())
+        hipLaunchKernelGGL(gemv_n_partial_kernel<false>, gn, dim3(256), 0, s, n, src, x, cps, part,
+                           asum_part);
+    else if (trans == 0)
+        hipLaunchKernelGGL(gemv_n_partial_kernel<true>, gn, dim3(256), 0, s, n, src, x, cps, part,
+                           asum_part);
+    else if (!src.seeded())
+        hipLaunchKernelGGL(gemv_t_partial_kernel<false>, gt, dim3(256), 0, s, n, src, x, cps, part,
+                           asum_part);
     else
-        hipLaunchKernelGGL(gemv_t_partial_kernel, dim3((unsigned)((n + 3) / 4), (unsigned)nsplit),
-                           dim3(256), 0, s, n, A, lda, x, cps, part, asum_part);
+        hipLaunchKernelGGL(gemv_t_partial_kernel<true>, gt, dim3(256), 0, s, n, src, x, cps, part,
+                           asum_part);
     MXLU_LAUNCH_CHECK();
     hipLaunchKernelGGL(gemv_finish_kernel, dim3(g1(n)), dim3(256), 0, s, n, nsplit, part,
                        asum_part, b, y, x, stats);

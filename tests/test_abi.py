@@ -108,6 +108,24 @@ def test_mxp_options_and_workspace(L):
                        ctypes.byref(rep), None) == -1006
 
 
+def test_seeded_solve_argument_checks(L):
+    from paper_2604_09517_amd import _lib
+    o = _lib.MxpOpts()
+    L.mxp_default_opts(ctypes.byref(o))
+    rep = _lib.MxpReport()
+    p = ctypes.c_void_p(16)   # never dereferenced: every call below fails its checks
+    args = lambda n, dom, ldb, opts: (n, 1, 0, dom, 1, p, ldb, p, n, p, 1 << 30, None, opts,
+                                      ctypes.byref(rep), None)
+    assert L.mxp_solve_seeded(*args(-1, 1, 10, ctypes.byref(o))) == -1
+    assert L.mxp_solve_seeded(*args(10, 2, 10, ctypes.byref(o))) == -4
+    assert L.mxp_solve_seeded(*args(10, 1, 9, ctypes.byref(o))) == -7
+    assert L.mxp_solve_seeded(*args(10, 1, 10, None)) == -13
+    bad = _lib.MxpOpts()
+    L.mxp_default_opts(ctypes.byref(bad))
+    bad.pivot = 1                                  # pivoting needs ipiv
+    assert L.mxp_solve_seeded(*args(10, 0, 10, ctypes.byref(bad))) == -12
+
+
 def test_status_strings(L):
     for code in (0, -1001, -1002, -1003, -1004, -1005, -1006, -3, 7):
         assert len(L.mxlu_status_string(code)) > 0

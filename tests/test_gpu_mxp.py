@@ -395,3 +395,37 @@ def test_mxp_pivoted_solve_uniform_matrix(api, n, nb):
     note(f"pivoted bf16 n={n}: {rep}")
     assert rep["converged"] == 1
     assert checks.scaled_residual(A, x, b) < 16
+
+
+@pytest.mark.parametrize("prec,n,nb,pivot,dominant,trans", [
+    ("bf16", 1500, 128, False, True, 0), ("fp8", 1100, 128, False, True, 0),
+    ("bf16", 900, 64, False, True, 1), ("bf16", 700, 64, True, False, 0)])
+def test_seeded_solve_equals_stored_matrix(api, prec, n, nb, pivot, dominant, trans):
+    """mxp_solve_seeded regenerates A from its counter in the conversion and
+    in every FP64 residual; the operations and their order are those of
+    mxp_solve on the stored matrix, so factors, solution and counts agree
+    bit for bit."""
+    seed = 5000 + n
+    note(f"seeded solve prec={prec} n={n} pivot={pivot} dominant={dominant} trans={trans}")
+    A = api.fortran_empty(n, n)
+    api.fill_uniform(A, seed, inputs.STREAM_A)
+    if dominant:
+        api.make_diag_dominant(A)
+    b = torch.from_numpy(inputs.uniform_matrix(seed, inputs.STREAM_B, n, 1)[:, 0]).cuda()
+    kw = dict(prec=prec, nb=nb, pivot=pivot, refine="gmres", trans=bool(trans), scale_tile=128,
+              restart=100 if pivot else 30, max_outer=30, max_inner_total=1000)
+    X1, r1, w1, p1 = api.mxp_solve(A, b, allow_notconv=True, **kw)
+    X2, r2, w2, p2 = api.mxp_solve_seeded(n, seed, inputs.STREAM_A, b, dominant=dominant,
+                                          allow_notconv=True, **kw)
+    torch.cuda.synchronize()
+    note(f"  stored: {r1['outer_iters']}/{r1['inner_iters']} rho {r1['scaled_residual']:.3e}; "
+         f"seeded: {r2['outer_iters']}/{r2['inner_iters']} rho {r2['scaled_residual']:.3e}")
+    assert r1["status"] == r2["status"] == 0
+    assert (r1["outer_iters"], r1["inner_iters"]) == (r2["outer_iters"], r2["inner_iters"])
+    assert r1["scaled_residual"] == r2["scaled_residual"]
+    assert torch.equal(api.mxp_factors(w1, n, prec), api.mxp_factors(w2, n, prec))
+    if pivot:
+        assert torch.equal(p1, p2)
+    assert torch.equal(X1, X2)
+    rho = api.scaled_residual(A, X2, b, trans=bool(trans))[0]
+    assert rho < 16
