@@ -170,8 +170,12 @@ int mxlu_outer_update_f64(int64_t M, int64_t N, int64_t K, const double *A,
 enum {
     MXLU_PREC_BF16 = 0,  /* bf16 storage, BF16 MFMA trailing update, FP32 accumulation */
     MXLU_PREC_FP16 = 1,  /* fp16 storage, FP16 MFMA trailing update, FP32 accumulation */
-    MXLU_PREC_FP8 = 2    /* fp16 storage, e4m3fn operands with per-tile power-of-two
+    MXLU_PREC_FP8 = 2,   /* fp16 storage, e4m3fn operands with per-tile power-of-two
                             FP32 scales in the trailing update, FP32 accumulation */
+    MXLU_PREC_FP8_MX = 3 /* fp16 storage, e4m3fn operands with one E8M0 (power-of-two)
+                            scale per row of L21 / column of U12 and block of 32 k,
+                            applied by the matrix cores (OCP MX block scaling);
+                            FP32 accumulation; scale_tile unused */
 };
 enum { MXLU_IR_CLASSICAL = 0, MXLU_IR_GMRES = 1 };
 

@@ -38,7 +38,7 @@ _lib = None
 
 def build() -> str:
     """Compile the C oracle into oracle/libmxlu_oracle.so (always rebuilds)."""
-    tmp = LIB_PATH + ".tmp"
+    tmp = f"{LIB_PATH}.{os.getpid()}.tmp"   # per process: concurrent builds do not collide
     subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, SRC_PATH, "-lm"])
     os.replace(tmp, LIB_PATH)
     return LIB_PATH
@@ -93,6 +93,8 @@ def _bind(L):
     L.oracle_round_array.restype = None
     L.oracle_fp8_scale.argtypes = [ctypes.c_double]
     L.oracle_fp8_scale.restype = ctypes.c_double
+    L.oracle_mx_scale.argtypes = [ctypes.c_double]
+    L.oracle_mx_scale.restype = ctypes.c_double
     L.oracle_lp_getrf.argtypes = [i64, i64, i32, i32, i64, dp, i64, dp]
     L.oracle_lp_getrf.restype = i32
     L.oracle_lp_getrf_steps.argtypes = [i64, i64, i32, i32, i64, dp, i64, dp, i64]
@@ -194,9 +196,15 @@ def fp8_scale(amax):
     return lib().oracle_fp8_scale(float(amax))
 
 
+def mx_scale(amax):
+    """E8M0 block scale of the MX FP8 form (power of two, exponent in [-127, 127])."""
+    return lib().oracle_mx_scale(float(amax))
+
+
 def lp_getrf(A, nb, prec, pivot=False, tile=128, max_steps=-1):
     """Low-precision blocked LU (Sec. III-A.2).  prec: 0 bf16, 1 fp16, 2 fp8
-    updates with fp16 storage.  Returns (F, ipiv or None, info) where F holds
+    updates with fp16 storage and per-tile scales, 3 fp8 updates with fp16
+    storage and MX (E8M0 per 32 k) block scales.  Returns (F, ipiv or None, info) where F holds
     the stored factor values as FP64 numbers.  max_steps >= 0 stops after that
     many panel steps (the trailing block then holds the updated, unfactored
     Schur complement in storage precision)."""

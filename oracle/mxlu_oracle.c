@@ -327,6 +327,22 @@ double oracle_fp8_scale(double amax)
     return ldexp(1.0, k);
 }
 
+/*
+ * E8M0 block scale of the MX form: the smallest power of two 2^e with
+ * amax / 2^e <= 448 (as oracle_fp8_scale), e limited to the E8M0 exponent
+ * range [-127, 127]; 1 for an all-zero block.
+ */
+double oracle_mx_scale(double amax)
+{
+    if (!(amax > 0.0)) return 1.0;
+    int e2;
+    double f = frexp(amax / 448.0, &e2);
+    int k = (f == 0.5) ? e2 - 1 : e2;
+    if (k < -127) k = -127;
+    if (k > 127) k = 127;
+    return ldexp(1.0, k);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Low-precision LU (the mixed-precision variant)                            */
 /* ------------------------------------------------------------------------ */
@@ -348,6 +364,10 @@ double oracle_fp8_scale(double amax)
  *               kb x `tile` columns, to e4m3fn with power-of-two scales;
  *               acc = sum_k Lq Uq in FP32 (k ascending, from 0);
  *               A22 <- round_fp16( fp32(A22) - (acc * sL) * sU ).
+ *     prec 3:   MX form: each row of L21 and column of U12 quantised in
+ *               blocks of 32 k with one E8M0 scale per block;
+ *               acc = sum_k (Lq sL)(Uq sU) in FP32 (k ascending, from 0);
+ *               A22 <- round_fp16( fp32(A22) - acc ).
  */
 static float to_f32(double v) { return (float)v; }   /* exact for stored values */
 
@@ -355,7 +375,7 @@ int oracle_lp_getrf_steps(int64_t n, int64_t nb, int prec, int pivot, int64_t ti
                           double *S, int64_t lds, int32_t *ipiv, int64_t max_steps)
 {
     if (n < 0 || nb < 1 || lds < (n > 1 ? n : 1)) return -1;
-    if (prec < 0 || prec > 2 || tile < 1) return -3;
+    if (prec < 0 || prec > 3 || tile < 1) return -3;
     int sfmt = (prec == 0) ? ORACLE_BF16 : ORACLE_FP16;
     int info = 0;
 
@@ -367,13 +387,16 @@ int oracle_lp_getrf_steps(int64_t n, int64_t nb, int prec, int pivot, int64_t ti
     float *P = (float *)malloc(sizeof(float) * (size_t)n * (size_t)nb);
     float *Lq = NULL, *Uq = NULL;
     double *sL = NULL, *sU = NULL;
-    if (prec == 2) {
+    if (prec >= 2) {
+        /* prec 2: one scale per tile; prec 3: one per (line, block of 32 k) */
+        size_t ns = (prec == 2) ? (size_t)(n / tile + 1)
+                                : (size_t)n * (size_t)((nb + 31) / 32);
         Lq = (float *)malloc(sizeof(float) * (size_t)n * (size_t)nb);
         Uq = (float *)malloc(sizeof(float) * (size_t)n * (size_t)nb);
-        sL = (double *)malloc(sizeof(double) * (size_t)(n / tile + 1));
-        sU = (double *)malloc(sizeof(double) * (size_t)(n / tile + 1));
+        sL = (double *)malloc(sizeof(double) * ns);
+        sU = (double *)malloc(sizeof(double) * ns);
     }
-    if (!P || (prec == 2 && (!Lq || !Uq || !sL || !sU))) {
+    if (!P || (prec >= 2 && (!Lq || !Uq || !sL || !sU))) {
         free(P); free(Lq); free(Uq); free(sL); free(sU);
         return -1000;
     }
@@ -450,7 +473,57 @@ int oracle_lp_getrf_steps(int64_t n, int64_t nb, int prec, int pivot, int64_t ti
         }
         if (c1 >= n) continue;
         /* trailing update from the stored operands */
-        if (prec != 2) {
+        if (prec == 3) {
+            /* MX form: every row of L21 and every column of U12 quantised in
+               blocks of 32 consecutive k (aligned to the panel) with one
+               E8M0 (power-of-two) scale per block; the update sums the
+               exactly rescaled products (Lq sL)(Uq sU) in FP32, k ascending
+               from zero, and subtracts the sum from fp32(A22) */
+            int64_t mt = n - c1, nblk = (kb + 31) / 32;
+            for (int64_t i = c1; i < n; ++i)
+                for (int64_t b = 0; b < nblk; ++b) {
+                    int64_t ka = 32 * b, kz = (ka + 32 < kb) ? ka + 32 : kb;
+                    double amax = 0.0;
+                    for (int64_t k = ka; k < kz; ++k) {
+                        double v = fabs(S[IDX(i, k0 + k, lds)]);
+                        if (v > amax) amax = v;
+                    }
+                    double sc = oracle_mx_scale(amax);
+                    sL[(i - c1) * nblk + b] = sc;
+                    for (int64_t k = ka; k < kz; ++k)
+                        Lq[IDX(i - c1, k, mt)] = (float)oracle_round(
+                            S[IDX(i, k0 + k, lds)] / sc, ORACLE_E4M3);
+                }
+            for (int64_t c = c1; c < n; ++c)
+                for (int64_t b = 0; b < nblk; ++b) {
+                    int64_t ka = 32 * b, kz = (ka + 32 < kb) ? ka + 32 : kb;
+                    double amax = 0.0;
+                    for (int64_t k = ka; k < kz; ++k) {
+                        double v = fabs(S[IDX(k0 + k, c, lds)]);
+                        if (v > amax) amax = v;
+                    }
+                    double sc = oracle_mx_scale(amax);
+                    sU[(c - c1) * nblk + b] = sc;
+                    for (int64_t k = ka; k < kz; ++k)
+                        Uq[IDX(k, c - c1, kb)] = (float)oracle_round(
+                            S[IDX(k0 + k, c, lds)] / sc, ORACLE_E4M3);
+                }
+            #pragma omp parallel for schedule(static)
+            for (int64_t c = c1; c < n; ++c) {
+                for (int64_t i = c1; i < n; ++i) {
+                    float acc = 0.0f;
+                    for (int64_t k = 0; k < kb; ++k) {
+                        float l = (float)((double)Lq[IDX(i - c1, k, mt)] *
+                                          sL[(i - c1) * nblk + k / 32]);   /* exact */
+                        float u = (float)((double)Uq[IDX(k, c - c1, kb)] *
+                                          sU[(c - c1) * nblk + k / 32]);   /* exact */
+                        acc = fmaf(l, u, acc);
+                    }
+                    float a = to_f32(S[IDX(i, c, lds)]) - acc;
+                    S[IDX(i, c, lds)] = oracle_round((double)a, ORACLE_FP16);
+                }
+            }
+        } else if (prec != 2) {
             #pragma omp parallel for schedule(static)
             for (int64_t c = c1; c < n; ++c) {
                 for (int64_t i = c1; i < n; ++i) {

@@ -170,7 +170,7 @@ def scaled_residual(A, X, B, trans=False):
     return [out[i] for i in range(nrhs)]
 
 
-PREC = {"bf16": 0, "fp16": 1, "fp8": 2}
+PREC = {"bf16": 0, "fp16": 1, "fp8": 2, "fp8_mx": 3}
 REFINE = {"classical": 0, "gmres": 1}
 
 

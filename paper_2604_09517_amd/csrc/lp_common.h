@@ -121,6 +121,16 @@ __device__ __forceinline__ uint8_t f32_to_e4m3(float f) {
 
 // Smallest power of two s with amax / s <= 448 (s = 1 for amax = 0).
 // The ratio is formed in FP64 so that the power-of-two test is exact.
+// E8M0 exponent e of the MX block scale 2^e: the smallest e with
+// amax / 2^e <= 448, limited to [-127, 127]; 0 for an all-zero block.
+__device__ __forceinline__ int mx_block_exp(float amax) {
+    if (!(amax > 0.0f)) return 0;
+    int e;
+    const double m = frexp((double)amax / 448.0, &e);
+    const int k = (m == 0.5) ? e - 1 : e;
+    return k < -127 ? -127 : (k > 127 ? 127 : k);
+}
+
 __device__ __forceinline__ float fp8_tile_scale(float amax) {
     if (!(amax > 0.0f)) return 1.0f;
     const double r = (double)amax / 448.0;

@@ -15,7 +15,11 @@
 //
 // MFMA lane layouts (measured on gfx950; lane l, i = l % 16, g = l / 16):
 //   16x16x32 16-bit: A lane holds A[i][8g .. 8g+7], B lane B[8g .. 8g+7][i],
-//   16x16x128 fp8:   A lane holds A[i][32g .. 32g+31], B likewise,
+//   16x16x128 fp8:   A lane holds A[i][16g .. 16g+15] in bytes 0-15 and
+//                    A[i][64+16g .. 64+16g+15] in bytes 16-31, B likewise;
+//                    the block-scaled form takes the scale byte of lane
+//                    (i, g) for row i of A (column i of B) and the k block
+//                    32g .. 32g+31,
 //   both: accumulator register r holds D[4g + r][i].
 #include <hip/hip_runtime.h>
 
@@ -244,12 +248,20 @@ __device__ __forceinline__ void wait_vmcnt() {
     __builtin_amdgcn_s_waitcnt(0x0F70 | (N & 15) | ((N >> 4) << 14));
 }
 
-template <int FMT, int NS>
+// MX: instead of the tile scales, one E8M0 scale byte per line and block of
+// 32 k (sLx[b Mp + r], sUx[b Np + c]) goes to the matrix cores with the
+// operands: lane (li, lg) supplies the byte of block lg of the chunk for its
+// row (column), the operand bytes being placed so that the matrix cores' k
+// is the chunk's k (bytes 0-15 of a lane from k 16 lg, bytes 16-31 from
+// k 64 + 16 lg); the epilogue is then C - acc.
+template <int FMT, int NS, bool MX>
 __global__ __launch_bounds__(256, NS <= 2 ? 2 : 1) void lp_schur8_kernel(
     int64_t M, int64_t N, int K, const uint8_t *__restrict__ Lq, int64_t Mp,
     const float *__restrict__ sL, const uint8_t *__restrict__ Uq, int64_t Np,
-    const float *__restrict__ sU, int tile, uint16_t *__restrict__ C, int64_t ldc, int tiles_m,
+    const float *__restrict__ sU, int tile, const uint8_t *__restrict__ sLx,
+    const uint8_t *__restrict__ sUx, uint16_t *__restrict__ C, int64_t ldc, int tiles_m,
     int tiles_n) {
+    static_assert(!MX || NS == 2, "the MX scale loads are waited for with the chunk (vmcnt(0))");
     constexpr int kNs8 = NS;
     constexpr int SA = kTm8 * BK8, SB = kTn8 * BK8;   // bytes per stage
     constexpr int NA = SA / 4 / 1024, NB = SB / 4 / 1024;
@@ -305,9 +317,10 @@ __global__ __launch_bounds__(256, NS <= 2 ? 2 : 1) void lp_schur8_kernel(
             __builtin_amdgcn_global_load_lds((gvoid_t *)(gb + q * 1024), (lvoid_t *)(lb + q * 1024),
                                              16, 0, 0);
     };
-    auto frag = [](const uint8_t *p) {
-        const uint4 lo = reinterpret_cast<const uint4 *>(p)[0];
-        const uint4 hi = reinterpret_cast<const uint4 *>(p)[1];
+    // a line's 16 bytes at k 16 lg and at k 64 + 16 lg (the matrix cores' k order)
+    auto frag = [lg](const uint8_t *line) {
+        const uint4 lo = *reinterpret_cast<const uint4 *>(line + 16 * lg);
+        const uint4 hi = *reinterpret_cast<const uint4 *>(line + 64 + 16 * lg);
         return v8i{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
     };
 
@@ -326,6 +339,20 @@ __global__ __launch_bounds__(256, NS <= 2 ? 2 : 1) void lp_schur8_kernel(
                 cv[pr][bj] = *reinterpret_cast<const uint4 *>(&C[(size_t)r8 + (size_t)c * ldc]);
             }
     }
+    // MX scale bytes of chunk kc for this lane's four A rows and four B
+    // columns (rows beyond M read stale bytes: their outputs are not stored)
+    int sa[4] = {127, 127, 127, 127}, sb[4] = {127, 127, 127, 127};
+    int sa_n[4], sb_n[4];
+    auto load_scales = [&](int kc, int (&a4)[4], int (&b4)[4]) {
+        const size_t blk = (size_t)(4 * kc + lg);
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi)
+            a4[bi] = sLx[blk * Mp + (size_t)(row0 + wm * 64 + 32 * (bi >> 1) + 2 * li + (bi & 1))];
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj)
+            b4[bj] = sUx[blk * Np + (size_t)(col0 + wn * 64 + bj * 16 + li)];
+    };
+    if constexpr (MX) load_scales(0, sa, sb);
     for (int kt = 0; kt < nk; ++kt) {
         // chunk kt has landed once at most min(NS - 2, nk - 1 - kt) later
         // chunks are outstanding (the C loads were issued before them)
@@ -335,23 +362,32 @@ __global__ __launch_bounds__(256, NS <= 2 ? 2 : 1) void lp_schur8_kernel(
         else wait_vmcnt<0>();
         __syncthreads();   // every wave's part of chunk kt; stage (kt - 1) % NS free
         if (kt + kNs8 - 1 < nk) issue(kt + kNs8 - 1, (kt + kNs8 - 1) % kNs8);
+        if constexpr (MX)
+            if (kt + 1 < nk) load_scales(kt + 1, sa_n, sb_n);
         const uint8_t *as = &ring[kt % kNs8][0];
         const uint8_t *bs = &ring[kt % kNs8][SA];
         v8i a[4], b[4];
 #pragma unroll
         for (int bi = 0; bi < 4; ++bi)
-            a[bi] = frag(&as[(wm * 64 + 32 * (bi >> 1) + 2 * li + (bi & 1)) * BK8 + lg * 32]);
+            a[bi] = frag(&as[(wm * 64 + 32 * (bi >> 1) + 2 * li + (bi & 1)) * BK8]);
 #pragma unroll
-        for (int bj = 0; bj < 4; ++bj) b[bj] = frag(&bs[(wn * 64 + bj * 16 + li) * BK8 + lg * 32]);
+        for (int bj = 0; bj < 4; ++bj) b[bj] = frag(&bs[(wn * 64 + bj * 16 + li) * BK8]);
 #pragma unroll
         for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
             for (int bj = 0; bj < 4; ++bj)
                 acc[bi][bj] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
-                    a[bi], b[bj], acc[bi][bj], 0, 0, 0, 127, 0, 127);
+                    a[bi], b[bj], acc[bi][bj], 0, 0, 0, sa[bi], 0, sb[bj]);
+        if constexpr (MX)
+            if (kt + 1 < nk)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    sa[q] = sa_n[q];
+                    sb[q] = sb_n[q];
+                }
     }
 
-    // C <- round(fp32(C) - acc sL sU)
+    // C <- round(fp32(C) - acc sL sU)   (MX: C - acc)
     if (full) {
 #pragma unroll
         for (int pr = 0; pr < 2; ++pr)
@@ -359,8 +395,12 @@ __global__ __launch_bounds__(256, NS <= 2 ? 2 : 1) void lp_schur8_kernel(
             for (int bj = 0; bj < 4; ++bj) {
                 const int64_t r8 = row0 + wm * 64 + 32 * pr + 8 * lg;
                 const int64_t c = col0 + wn * 64 + bj * 16 + li;
-                const float su = sU[tix(c)];
-                const float sc_lo = sL[tix(r8)] * su, sc_hi = sL[tix(r8 + 4)] * su;
+                float sc_lo = 1.0f, sc_hi = 1.0f;
+                if constexpr (!MX) {
+                    const float su = sU[tix(c)];
+                    sc_lo = sL[tix(r8)] * su;
+                    sc_hi = sL[tix(r8 + 4)] * su;
+                }
                 const uint32_t c4[4] = {cv[pr][bj].x, cv[pr][bj].y, cv[pr][bj].z, cv[pr][bj].w};
                 uint32_t w4[4];
 #pragma unroll
@@ -385,8 +425,8 @@ __global__ __launch_bounds__(256, NS <= 2 ? 2 : 1) void lp_schur8_kernel(
                     const int64_t row = row_of(bi, r);
                     if (row < M && c < N) {
                         uint16_t *cp = &C[(size_t)row + (size_t)c * ldc];
-                        *cp = f32_to_lp<FMT>(lp_to_f32<FMT>(*cp) -
-                                             acc[bi][bj][r] * (sL[tix(row)] * sU[tix(c)]));
+                        const float sc = MX ? 1.0f : sL[tix(row)] * sU[tix(c)];
+                        *cp = f32_to_lp<FMT>(lp_to_f32<FMT>(*cp) - acc[bi][bj][r] * sc);
                     }
                 }
             }
@@ -434,12 +474,40 @@ int lp_schur_update_fp8(int fmt, int64_t M, int64_t N, int K, const uint8_t *Lq,
     // N = 131072), whose single wave per SIMD leaves the LDS reads and the
     // epilogue exposed
     constexpr int kStages = 2;
+    const uint8_t *none = nullptr;
     if (fmt == kFmtBf16)
-        hipLaunchKernelGGL((lp_schur8_kernel<kFmtBf16, kStages>), grid, dim3(256), 0, s, M, N, K, Lq,
-                           Mp, sL, Uq, Np, sU, tile, C, ldc, (int)tiles_m, (int)tiles_n);
+        hipLaunchKernelGGL((lp_schur8_kernel<kFmtBf16, kStages, false>), grid, dim3(256), 0, s, M,
+                           N, K, Lq, Mp, sL, Uq, Np, sU, tile, none, none, C, ldc, (int)tiles_m,
+                           (int)tiles_n);
     else
-        hipLaunchKernelGGL((lp_schur8_kernel<kFmtFp16, kStages>), grid, dim3(256), 0, s, M, N, K, Lq,
-                           Mp, sL, Uq, Np, sU, tile, C, ldc, (int)tiles_m, (int)tiles_n);
+        hipLaunchKernelGGL((lp_schur8_kernel<kFmtFp16, kStages, false>), grid, dim3(256), 0, s, M,
+                           N, K, Lq, Mp, sL, Uq, Np, sU, tile, none, none, C, ldc, (int)tiles_m,
+                           (int)tiles_n);
+    MXLU_LAUNCH_CHECK();
+    return 0;
+}
+
+int lp_schur_update_mx(int fmt, int64_t M, int64_t N, int K, const uint8_t *Lq, int64_t Mp,
+                       const uint8_t *sLx, const uint8_t *Uq, int64_t Np, const uint8_t *sUx,
+                       uint16_t *C, int64_t ldc, hipStream_t s) {
+    if (M <= 0 || N <= 0 || K <= 0) return 0;
+    if (K % BK8 || Mp % kTm8 || Np % kTn8 || Mp < M || Np < N || ldc % 4 ||
+        ((uintptr_t)Lq | (uintptr_t)Uq) % 16 || (uintptr_t)C % 8 || !sLx || !sUx) {
+        set_error_msg("lp_schur_update_mx: K % 128, padded packed operands, scales, ldc % 4 and "
+                      "alignment required");
+        return MXLU_E_NOMEM;
+    }
+    const int64_t tiles_m = (M + kTm8 - 1) / kTm8, tiles_n = (N + kTn8 - 1) / kTn8;
+    const dim3 grid((unsigned)(tiles_m * tiles_n));
+    const float *none = nullptr;
+    if (fmt == kFmtBf16)
+        hipLaunchKernelGGL((lp_schur8_kernel<kFmtBf16, 2, true>), grid, dim3(256), 0, s, M, N, K,
+                           Lq, Mp, none, Uq, Np, none, 4, sLx, sUx, C, ldc, (int)tiles_m,
+                           (int)tiles_n);
+    else
+        hipLaunchKernelGGL((lp_schur8_kernel<kFmtFp16, 2, true>), grid, dim3(256), 0, s, M, N, K,
+                           Lq, Mp, none, Uq, Np, none, 4, sLx, sUx, C, ldc, (int)tiles_m,
+                           (int)tiles_n);
     MXLU_LAUNCH_CHECK();
     return 0;
 }

@@ -62,6 +62,14 @@ int lp_quant_l21(int fmt, int64_t mt, int kb, int tile, const uint16_t *L21, int
 int lp_quant_u12(int fmt, int64_t nt, int kb, int tile, const uint16_t *U12, int64_t ldf,
                  uint8_t *Uq, int64_t Np, float *sU, hipStream_t s);
 
+// MX form: e4m3 operands in the same chunk-packed layout with one E8M0 scale
+// byte per line and block of 32 k: sLx[b Mp + r], sUx[b Np + c] (scale
+// 2^(byte - 127)); kb % 128 == 0.
+int lp_quant_l21_mx(int fmt, int64_t mt, int kb, const uint16_t *L21, int64_t ldf, uint8_t *LTq,
+                    int64_t Mp, uint8_t *sLx, hipStream_t s);
+int lp_quant_u12_mx(int fmt, int64_t nt, int kb, const uint16_t *U12, int64_t ldf, uint8_t *Uq,
+                    int64_t Np, uint8_t *sUx, hipStream_t s);
+
 // Trailing update on the matrix cores:
 //   16-bit: C <- round(fp32(C) - L U) with L (M x K) and U (K x N) chunk-packed
 //           (Mp, Np lines), K % kLpKc == 0, C 8-byte aligned with ldc % 4 == 0
@@ -72,5 +80,10 @@ int lp_schur_update(int fmt, int64_t M, int64_t N, int K, const uint16_t *Lp, in
 int lp_schur_update_fp8(int fmt, int64_t M, int64_t N, int K, const uint8_t *Lq, int64_t Mp,
                         const float *sL, const uint8_t *Uq, int64_t Np, const float *sU,
                         int tile, uint16_t *C, int64_t ldc, hipStream_t s);
+//   MX:     C <- round(fp32(C) - sum_k (Lq sLx)(Uq sUx)), the E8M0 block scales
+//           applied by the matrix cores
+int lp_schur_update_mx(int fmt, int64_t M, int64_t N, int K, const uint8_t *Lq, int64_t Mp,
+                       const uint8_t *sLx, const uint8_t *Uq, int64_t Np, const uint8_t *sUx,
+                       uint16_t *C, int64_t ldc, hipStream_t s);
 
 }  // namespace mxlu

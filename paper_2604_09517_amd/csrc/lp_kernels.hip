@@ -498,6 +498,78 @@ __global__ __launch_bounds__(256) void quant_u12_kernel(int64_t nt, int kb, int 
                 f32_to_e4m3(lp_to_f32<FMT>(U12[(size_t)k + (size_t)(q0 + j) * ldf]) * inv);
 }
 
+// MX form: L21 row i, block b of 32 consecutive k -> 32 e4m3 bytes at their
+// place in the chunk-packed layout and the E8M0 byte sLx[b Mp + i] (scale
+// 2^(byte - 127)).  One thread per row, coalesced across rows per column.
+template <int FMT>
+__global__ __launch_bounds__(256) void quant_l21_mx_kernel(int64_t mt, int kb,
+                                                           const uint16_t *__restrict__ L21,
+                                                           int64_t ldf, uint8_t *__restrict__ LTq,
+                                                           int64_t Mp, uint8_t *__restrict__ sLx) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= mt) return;
+    for (int b = 0; b < kb / 32; ++b) {
+        float v[32];
+        float amax = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 32; ++k) {
+            v[k] = lp_to_f32<FMT>(L21[(size_t)i + (size_t)(32 * b + k) * ldf]);
+            amax = fmaxf(amax, fabsf(v[k]));
+        }
+        const int e = mx_block_exp(amax);
+        const float inv = ldexpf(1.0f, -e);   // exact: a power of two
+        uint32_t w[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            w[q] = (uint32_t)f32_to_e4m3(v[4 * q] * inv) |
+                   ((uint32_t)f32_to_e4m3(v[4 * q + 1] * inv) << 8) |
+                   ((uint32_t)f32_to_e4m3(v[4 * q + 2] * inv) << 16) |
+                   ((uint32_t)f32_to_e4m3(v[4 * q + 3] * inv) << 24);
+        const int k0 = 32 * b;
+        uint4 *dst = reinterpret_cast<uint4 *>(
+            LTq + ((size_t)(k0 / kLp8Kc) * Mp + (size_t)i) * kLp8Kc + (k0 % kLp8Kc));
+        dst[0] = make_uint4(w[0], w[1], w[2], w[3]);
+        dst[1] = make_uint4(w[4], w[5], w[6], w[7]);
+        sLx[(size_t)b * Mp + i] = (uint8_t)(e + 127);
+    }
+}
+
+// MX form: U12 column j, block b of 32 consecutive k (contiguous in the
+// column) -> 32 e4m3 bytes and the E8M0 byte sUx[b Np + j].
+template <int FMT>
+__global__ __launch_bounds__(256) void quant_u12_mx_kernel(int64_t nt, int kb,
+                                                           const uint16_t *__restrict__ U12,
+                                                           int64_t ldf, uint8_t *__restrict__ Uq,
+                                                           int64_t Np, uint8_t *__restrict__ sUx) {
+    const int nb = kb / 32;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= nt * nb) return;
+    const int64_t j = t % nt;
+    const int b = (int)(t / nt);
+    const uint16_t *src = U12 + (size_t)(32 * b) + (size_t)j * ldf;
+    float v[32];
+    float amax = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+        v[k] = lp_to_f32<FMT>(src[k]);
+        amax = fmaxf(amax, fabsf(v[k]));
+    }
+    const int e = mx_block_exp(amax);
+    const float inv = ldexpf(1.0f, -e);
+    uint32_t w[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        w[q] = (uint32_t)f32_to_e4m3(v[4 * q] * inv) | ((uint32_t)f32_to_e4m3(v[4 * q + 1] * inv) << 8) |
+               ((uint32_t)f32_to_e4m3(v[4 * q + 2] * inv) << 16) |
+               ((uint32_t)f32_to_e4m3(v[4 * q + 3] * inv) << 24);
+    const int k0 = 32 * b;
+    uint4 *dst = reinterpret_cast<uint4 *>(
+        Uq + ((size_t)(k0 / kLp8Kc) * Np + (size_t)j) * kLp8Kc + (k0 % kLp8Kc));
+    dst[0] = make_uint4(w[0], w[1], w[2], w[3]);
+    dst[1] = make_uint4(w[4], w[5], w[6], w[7]);
+    sUx[(size_t)b * Np + j] = (uint8_t)(e + 127);
+}
+
 dim3 grid2(int64_t rows, int64_t cols) {
     return dim3((unsigned)((rows + 255) / 256), (unsigned)(cols < 4096 ? (cols > 0 ? cols : 1) : 4096));
 }
@@ -684,6 +756,43 @@ int lp_quant_l21(int fmt, int64_t mt, int kb, int tile, const uint16_t *L21, int
     else
         hipLaunchKernelGGL(quant_l21_kernel<kFmtFp16>, dim3(grid), dim3(256), 0, s, mt, kb, tile,
                            L21, ldf, LTq, Mp, sL);
+    MXLU_LAUNCH_CHECK();
+    return 0;
+}
+
+int lp_quant_l21_mx(int fmt, int64_t mt, int kb, const uint16_t *L21, int64_t ldf, uint8_t *LTq,
+                    int64_t Mp, uint8_t *sLx, hipStream_t s) {
+    if (mt <= 0 || kb <= 0) return 0;
+    if (kb % kLp8Kc || Mp < mt || Mp % kLp8Kc || (uintptr_t)LTq % 16) {
+        set_error_msg("lp_quant_l21_mx: kb % 128, Mp >= rows, Mp % 128 and alignment required");
+        return MXLU_E_NOMEM;
+    }
+    const unsigned grid = (unsigned)((mt + 255) / 256);
+    if (fmt == kFmtBf16)
+        hipLaunchKernelGGL(quant_l21_mx_kernel<kFmtBf16>, dim3(grid), dim3(256), 0, s, mt, kb, L21,
+                           ldf, LTq, Mp, sLx);
+    else
+        hipLaunchKernelGGL(quant_l21_mx_kernel<kFmtFp16>, dim3(grid), dim3(256), 0, s, mt, kb, L21,
+                           ldf, LTq, Mp, sLx);
+    MXLU_LAUNCH_CHECK();
+    return 0;
+}
+
+int lp_quant_u12_mx(int fmt, int64_t nt, int kb, const uint16_t *U12, int64_t ldf, uint8_t *Uq,
+                    int64_t Np, uint8_t *sUx, hipStream_t s) {
+    if (nt <= 0 || kb <= 0) return 0;
+    if (kb % kLp8Kc || Np < nt || (uintptr_t)Uq % 16) {
+        set_error_msg("lp_quant_u12_mx: kb % 128, Np >= columns and alignment required");
+        return MXLU_E_NOMEM;
+    }
+    const int64_t total = nt * (kb / 32);
+    const unsigned grid = (unsigned)((total + 255) / 256);
+    if (fmt == kFmtBf16)
+        hipLaunchKernelGGL(quant_u12_mx_kernel<kFmtBf16>, dim3(grid), dim3(256), 0, s, nt, kb, U12,
+                           ldf, Uq, Np, sUx);
+    else
+        hipLaunchKernelGGL(quant_u12_mx_kernel<kFmtFp16>, dim3(grid), dim3(256), 0, s, nt, kb, U12,
+                           ldf, Uq, Np, sUx);
     MXLU_LAUNCH_CHECK();
     return 0;
 }

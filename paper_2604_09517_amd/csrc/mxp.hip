@@ -67,7 +67,8 @@ int lp_factorize(const mxp_opts &o, int64_t n, const ASource &src, uint16_t *F,
                  int64_t ldf, int32_t *ipiv, int *info_host, hipStream_t s, double *t_conv,
                  double *t_fact) {
     const int fmt = (o.prec == MXLU_PREC_BF16) ? kFmtBf16 : kFmtFp16;
-    const bool fp8 = o.prec == MXLU_PREC_FP8;
+    const bool mx = o.prec == MXLU_PREC_FP8_MX;
+    const bool fp8 = o.prec == MXLU_PREC_FP8 || mx;
     const int64_t nb = std::min<int64_t>(o.nb, n);
     const int tile = o.scale_tile;
     Scratch scratch(s);
@@ -78,13 +79,21 @@ int lp_factorize(const mxp_opts &o, int64_t n, const ASource &src, uint16_t *F,
     const int64_t Mp = lp_round_up(n, kLpTileM), Np = lp_round_up(n, kLpTileN);
     uint8_t *LTq = nullptr, *Uq = nullptr;
     float *sL = nullptr, *sU = nullptr;
+    uint8_t *sLx = nullptr, *sUx = nullptr;   // MX block scales
     const int64_t Mp8 = lp_round_up(n, kLp8Tile), Np8 = lp_round_up(n, kLp8Tile);
     if (fp8) {
         LTq = scratch.alloc_n<uint8_t>((size_t)nb * Mp8);
         Uq = scratch.alloc_n<uint8_t>((size_t)nb * Np8);
-        sL = scratch.alloc_n<float>((size_t)(n / tile + 2));
-        sU = scratch.alloc_n<float>((size_t)(n / tile + 2));
-        if (!LTq || !Uq || !sL || !sU) return MXLU_E_NOMEM;
+        if (!LTq || !Uq) return MXLU_E_NOMEM;
+        if (mx) {
+            sLx = scratch.alloc_n<uint8_t>((size_t)(nb / 32) * Mp8);
+            sUx = scratch.alloc_n<uint8_t>((size_t)(nb / 32) * Np8);
+            if (!sLx || !sUx) return MXLU_E_NOMEM;
+        } else {
+            sL = scratch.alloc_n<float>((size_t)(n / tile + 2));
+            sU = scratch.alloc_n<float>((size_t)(n / tile + 2));
+            if (!sL || !sU) return MXLU_E_NOMEM;
+        }
     } else {
         LTp = scratch.alloc_n<uint16_t>((size_t)nb * Mp);
         Up = scratch.alloc_n<uint16_t>((size_t)nb * Np);
@@ -146,7 +155,14 @@ int lp_factorize(const mxp_opts &o, int64_t n, const ASource &src, uint16_t *F,
             const double ob = fp8 ? 1.0 : 2.0;
             const double schur_bytes =
                 4.0 * (double)nt * (double)nt + 2.0 * ob * (double)nt * (double)kb;
-            if (fp8) {
+            if (mx) {
+                const uint16_t *L21 = F + (size_t)c1 + (size_t)k0 * ldf;
+                MXLU_TRY(lp_quant_l21_mx(fmt, nt, (int)kb, L21, ldf, LTq, Mp8, sLx, s));
+                MXLU_TRY(lp_quant_u12_mx(fmt, nt, (int)kb, U12, ldf, Uq, Np8, sUx, s));
+                PhaseScope ph(kPhaseLpSchur, s, schur_bytes);
+                MXLU_TRY(lp_schur_update_mx(fmt, nt, nt, (int)kb, LTq, Mp8, sLx, Uq, Np8, sUx, A22,
+                                            ldf, s));
+            } else if (fp8) {
                 const uint16_t *L21 = F + (size_t)c1 + (size_t)k0 * ldf;
                 MXLU_TRY(lp_quant_l21(fmt, nt, (int)kb, tile, L21, ldf, LTq, Mp8, sL, s));
                 MXLU_TRY(lp_quant_u12(fmt, nt, (int)kb, tile, U12, ldf, Uq, Np8, sU, s));
@@ -362,7 +378,7 @@ extern "C" int64_t mxp_factor_ld(int64_t n) { return n < 0 ? 0 : factor_ld(n); }
 
 extern "C" int mxp_convert(int32_t prec, int64_t rows, int64_t cols, const double *A,
                            int64_t lda, uint16_t *F, int64_t ldf, void *stream) {
-    if (prec < 0 || prec > 2) return -1;
+    if (prec < 0 || prec > 3) return -1;
     if (rows < 0) return -2;
     if (cols < 0) return -3;
     if (rows > 0 && cols > 0 && !A) return -4;
@@ -388,9 +404,10 @@ int mxp_check(int64_t n, int64_t nrhs, const double *B, int64_t ldb, double *X, 
     if (n > 0 && !work) return -9;
     if (!opts) return -12;
     const mxp_opts &o = *opts;
-    if (o.prec < 0 || o.prec > 2 || (o.pivot != 0 && o.pivot != 1) || o.nb < 32 ||
+    if (o.prec < 0 || o.prec > 3 || (o.pivot != 0 && o.pivot != 1) || o.nb < 32 ||
         o.nb % 32 != 0 || (o.prec == MXLU_PREC_FP8 && (o.nb % 128 != 0 || o.scale_tile < 4 ||
                                                        o.scale_tile > 256 || o.scale_tile % 4)) ||
+        (o.prec == MXLU_PREC_FP8_MX && o.nb % 128 != 0) ||
         (o.refine != MXLU_IR_CLASSICAL && o.refine != MXLU_IR_GMRES) || o.restart < 1 ||
         o.restart > 255 || o.max_outer < 0 || o.max_inner_total < 0 || o.trans < 0 ||
         o.trans > 1 || o.factor_steps < 0)

@@ -30,8 +30,8 @@ from paper_2604_09517_amd import inputs
 
 pytestmark = pytest.mark.gpu
 EPS = 2.0 ** -53
-U_LP = {"bf16": 2.0 ** -8, "fp16": 2.0 ** -11, "fp8": 2.0 ** -4}
-PREC_ID = {"bf16": 0, "fp16": 1, "fp8": 2}
+U_LP = {"bf16": 2.0 ** -8, "fp16": 2.0 ** -11, "fp8": 2.0 ** -4, "fp8_mx": 2.0 ** -4}
+PREC_ID = {"bf16": 0, "fp16": 1, "fp8": 2, "fp8_mx": 3}
 
 
 @pytest.fixture(scope="module")
@@ -137,7 +137,7 @@ def componentwise_bound(A, F_ref, nb, prec):
     last = np.where(np.tri(n, dtype=bool), aL * np.diag(aU)[None, :], aU)
     upd = full - last
     us = U_LP["bf16"] if prec == "bf16" else U_LP["fp16"]
-    uq = 2.0 ** -3 if prec == "fp8" else us
+    uq = 2.0 ** -3 if prec.startswith("fp8") else us
     steps = np.minimum.outer(np.arange(n), np.arange(n)) // nb + 1
     return 4 * steps * (us * (np.abs(F_ref) + np.abs(A)) + uq * upd)
 
@@ -147,7 +147,9 @@ def componentwise_bound(A, F_ref, nb, prec):
     ("bf16", 640, 128, "dominant", 64), ("fp8", 512, 128, "dominant", 64),
     ("fp8", 700, 128, "dominant", 64), ("fp8", 680, 256, "dominant", 128),
     ("fp8", 2216, 1024, "dominant", 128), ("fp8", 500, 128, "scaled", 12),
-    ("fp8", 680, 256, "scaled", 128), ("bf16", 680, 256, "scaled", 128)])
+    ("fp8", 680, 256, "scaled", 128), ("bf16", 680, 256, "scaled", 128),
+    ("fp8_mx", 700, 128, "dominant", 32), ("fp8_mx", 680, 256, "scaled", 32),
+    ("fp8_mx", 2216, 1024, "scaled", 32)])
 def test_lp_factors_against_oracle(api, prec, n, nb, kind, tile):
     """Whole factorization: first panel and block row bit for bit, every
     other entry within the componentwise bound of two summation orders."""
@@ -178,7 +180,9 @@ def test_lp_factors_against_oracle(api, prec, n, nb, kind, tile):
     ("bf16", 2216, 512, "dominant", 128),
     ("fp8", 700, 128, "dominant", 64), ("fp8", 680, 256, "dominant", 128),
     ("fp8", 2216, 1024, "dominant", 128), ("fp8", 500, 128, "scaled", 12),
-    ("fp8", 1064, 256, "scaled", 128), ("fp8", 1064, 256, "scaled", 36)])
+    ("fp8", 1064, 256, "scaled", 128), ("fp8", 1064, 256, "scaled", 36),
+    ("fp8_mx", 700, 128, "dominant", 32), ("fp8_mx", 1064, 256, "scaled", 32),
+    ("fp8_mx", 2216, 1024, "scaled", 32)])
 def test_lp_one_update_within_one_ulp(api, prec, n, nb, kind, tile):
     """One panel step (partial factorization): the panel and U12 bit for bit,
     and every updated entry of the trailing block within one storage ulp of
@@ -241,7 +245,8 @@ def test_preconditioner_bitwise_on_oracle_factors(api, prec, trans):
 
 @pytest.mark.parametrize("prec,method,n,nb", [
     ("bf16", "gmres", 512, 128), ("bf16", "classical", 512, 128), ("fp16", "gmres", 777, 64),
-    ("fp8", "gmres", 1024, 128), ("bf16", "gmres", 2048, 256), ("fp8", "classical", 640, 128)])
+    ("fp8", "gmres", 1024, 128), ("bf16", "gmres", 2048, 256), ("fp8", "classical", 640, 128),
+    ("fp8_mx", "gmres", 1024, 128), ("fp8_mx", "classical", 896, 256)])
 def test_mxp_solve_matches_oracle(api, prec, method, n, nb):
     note(f"mxp_solve prec={prec} refine={method} n={n} nb={nb}")
     seed = inputs.config_seed(2) + n

@@ -181,6 +181,38 @@ def test_lp_lu_fp8_distinct_tile_scales_exact(oracle_lib, n, nb, tile):
     assert np.array_equal(np.triu(F), U2)
 
 
+@pytest.mark.parametrize("n,nb", [(96, 64), (160, 128)])
+def test_lp_lu_mx_block_scales_exact(oracle_lib, n, nb):
+    """MX FP8 update (E8M0 scale per row of L21 / column of U12 and block of
+    32 consecutive k): with the rows and columns scaled by powers of two
+    that change every 32 indices, the blocks of one row of L21 (and of one
+    column of U12) have different magnitudes; every quantised value is still
+    an e4m3 number times its own block's scale, so the update is exact and
+    the factors come back exactly -- only when each block is dequantised
+    with its own scale."""
+    A, L2, U2 = _tile_scaled_exact_lu(n, 32, seed=n + nb)
+    assert np.array_equal(oracle.round_lp(A, oracle.FP16), A)
+    l21 = np.abs(np.tril(L2, -1)[nb:, :nb])
+    blocks = [l21[:, b:b + 32].max(axis=1) for b in range(0, nb, 32)]
+    row = int(np.argmax([len({oracle.mx_scale(bk[r]) for bk in blocks}) for r in range(n - nb)]))
+    assert len({oracle.mx_scale(bk[row]) for bk in blocks}) > 1   # one row, distinct scales
+    F, _, info = oracle.lp_getrf(A, nb=nb, prec=3, pivot=False)
+    assert info == 0
+    assert np.array_equal(np.tril(F, -1), np.tril(L2, -1))
+    assert np.array_equal(np.triu(F), U2)
+
+
+def test_mx_scale_is_minimal_e8m0(oracle_lib):
+    rng = np.random.default_rng(8)
+    for amax in list(rng.uniform(1e-8, 1e4, 200)) + [448.0, 896.0, 1.0]:
+        s = oracle.mx_scale(amax)
+        assert s == oracle.fp8_scale(amax)
+        assert amax / s <= 448.0 < amax / (s / 2)
+    assert oracle.mx_scale(0.0) == 1.0
+    assert oracle.mx_scale(1e-60) == 2.0 ** -127        # clamped to the E8M0 range
+    assert oracle.mx_scale(1e60) == 2.0 ** 127
+
+
 def test_lp_lu_pivoted_recovers_permutation(oracle_lib):
     rng = np.random.default_rng(13)
     n = 10
@@ -201,7 +233,8 @@ def test_lp_lu_pivoted_recovers_permutation(oracle_lib):
     assert np.array_equal(ipiv64, ipiv)
 
 
-@pytest.mark.parametrize("prec,u", [(0, 2.0 ** -8), (1, 2.0 ** -11), (2, 2.0 ** -4)])
+@pytest.mark.parametrize("prec,u", [(0, 2.0 ** -8), (1, 2.0 ** -11), (2, 2.0 ** -4),
+                                    (3, 2.0 ** -4)])
 def test_lp_lu_backward_error_bound(oracle_lib, prec, u):
     n = 192
     A = inputs.diag_dominant_matrix(21, 0, n)
@@ -299,7 +332,7 @@ def test_refine_exact_factors_converge_immediately(oracle_lib):
 
 
 @pytest.mark.parametrize("method,prec", [("classical", 0), ("gmres", 0), ("gmres", 2),
-                                         ("classical", 1)])
+                                         ("classical", 1), ("gmres", 3)])
 def test_refine_reaches_fp64_accuracy_on_dominant_matrix(oracle_lib, method, prec):
     n = 256
     A = inputs.diag_dominant_matrix(inputs.config_seed(2), 0, n)

@@ -49,6 +49,10 @@ MUTANTS = [
      "double sl = sL[(i - c1) / tile > 0 ? (i - c1) / tile - 1 : 1];", 0),
     ("lp_fp8_first_column_tile_scale", "double su = sU[(c - c1) / tile];",
      "double su = sU[0];", 0),
+    ("lp_mx_neighbour_block_scale", "sL[(i - c1) * nblk + k / 32]);   /* exact */",
+     "sL[(i - c1) * nblk + ((k / 32) ^ 1) % nblk]);", 0),
+    ("lp_mx_u_first_block_scale", "sU[(c - c1) * nblk + k / 32]);   /* exact */",
+     "sU[(c - c1) * nblk]);", 0),
     ("lp_trsm_wrong_factor", "uu[i] = fmaf(-P[IDX(i, k, m)], uu[k], uu[i]);",
      "uu[i] = fmaf(-P[IDX(k, i, m)], uu[k], uu[i]);", 0),
     ("precond_no_forward_solve",
@@ -75,6 +79,7 @@ PINS = [
     lambda: P.test_lp_lu_fp8_update_exact_on_representable_operands(None),
     lambda: [P.test_lp_lu_fp8_distinct_tile_scales_exact(None, n, nb, t)
              for n, nb, t in ((24, 8, 4), (40, 16, 8), (36, 12, 12))],
+    lambda: [P.test_lp_lu_mx_block_scales_exact(None, n, nb) for n, nb in ((96, 64), (160, 128))],
     lambda: P.test_lp_lu_pivoted_recovers_permutation(None),
     lambda: P.test_preconditioner_solves_with_factors_and_adjoint(None),
     lambda: P.test_preconditioner_with_pivots_and_exact_factors(None),
