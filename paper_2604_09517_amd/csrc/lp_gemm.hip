@@ -147,10 +147,32 @@ __global__ __launch_bounds__(256, 2) void lp_schur16_kernel(
             }
     }
 
-    // chunk kc of this tile: L21 bytes [4 KB wave, 4 KB (wave+1)), U12 bytes
-    // [2 KB wave, 2 KB (wave+1)) go to stage st
-    const char *gA = reinterpret_cast<const char *>(Lp + (size_t)row0 * BK16) + wave * 4096 + lane * 16;
-    const char *gB = reinterpret_cast<const char *>(Up + (size_t)col0 * BK16) + wave * 2048 + lane * 16;
+    // LDS layout of a stage: 64-byte lines (one row of L21 or column of U12
+    // over the chunk's 32 k), four 16-byte segments.  The 16 lanes li of a
+    // lane group read one segment of 16 lines at once (one pass of a 16-byte
+    // LDS read), so (1) the A rows 32p + 2 li + h of one MFMA block sit in the
+    // consecutive lines 32p + 16h + li, and (2) segment s of line x is stored
+    // in slot s ^ sw(x), sw(x) = ((x >> 1) & 3) ^ ((x >> 3) & 1): the 16 lanes
+    // of a pass touch 16 distinct 16-byte bank groups of 256 bytes (8 in each
+    // half).  Wave w copies lines [64 w, 64 w + 64) of L21 and [32 w, 32 w +
+    // 32) of U12, slots in lane order; each lane fetches the global segment
+    // that belongs in its slot (4 lanes per contiguous 64-byte global line).
+    auto sw = [](int x) { return ((x >> 1) & 3) ^ ((x >> 3) & 1); };
+    const int t4 = lane >> 2, s4 = lane & 3;
+    int offA[4], offB[2];   // byte offsets of this lane's global segments in a chunk
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int x = wave * 64 + 16 * q + t4;
+        const int r = 32 * (x >> 5) + 2 * (x & 15) + ((x >> 4) & 1);
+        offA[q] = r * (BK16 * 2) + 16 * (s4 ^ sw(x));
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int x = wave * 32 + 16 * q + t4;
+        offB[q] = x * (BK16 * 2) + 16 * (s4 ^ sw(x));
+    }
+    const char *gA = reinterpret_cast<const char *>(Lp + (size_t)row0 * BK16);
+    const char *gB = reinterpret_cast<const char *>(Up + (size_t)col0 * BK16);
     const size_t strideA = (size_t)Mp * BK16 * sizeof(uint16_t);   // bytes per K chunk
     const size_t strideB = (size_t)Np * BK16 * sizeof(uint16_t);
     auto issue = [&](int kc, int st) {
@@ -160,11 +182,11 @@ __global__ __launch_bounds__(256, 2) void lp_schur16_kernel(
         char *lb = reinterpret_cast<char *>(&ring[st][SA]) + wave * 2048;
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-            __builtin_amdgcn_global_load_lds((gvoid_t *)(ga + q * 1024), (lvoid_t *)(la + q * 1024),
+            __builtin_amdgcn_global_load_lds((gvoid_t *)(ga + offA[q]), (lvoid_t *)(la + q * 1024),
                                              16, 0, 0);
 #pragma unroll
         for (int q = 0; q < 2; ++q)
-            __builtin_amdgcn_global_load_lds((gvoid_t *)(gb + q * 1024), (lvoid_t *)(lb + q * 1024),
+            __builtin_amdgcn_global_load_lds((gvoid_t *)(gb + offB[q]), (lvoid_t *)(lb + q * 1024),
                                              16, 0, 0);
     };
 
@@ -182,14 +204,16 @@ __global__ __launch_bounds__(256, 2) void lp_schur16_kernel(
         if (kt + kNs16 - 1 < nk) issue(kt + kNs16 - 1, (kt + kNs16 - 1) % kNs16);
         const uint16_t *as = &ring[kt % kNs16][0];
         const uint16_t *bs = &ring[kt % kNs16][SA];
+        // lines read are 16-aligned plus li, so their swizzle is sw(li)
+        const int so = 8 * (lg ^ sw(li));
         uint4 a[8], b[4];
 #pragma unroll
         for (int bi = 0; bi < 8; ++bi)
             a[bi] = neg16(*reinterpret_cast<const uint4 *>(
-                &as[(wm * 128 + 32 * (bi >> 1) + 2 * li + (bi & 1)) * BK16 + lg * 8]));
+                &as[(wm * 128 + 32 * (bi >> 1) + 16 * (bi & 1) + li) * BK16 + so]));
 #pragma unroll
         for (int bj = 0; bj < 4; ++bj)
-            b[bj] = *reinterpret_cast<const uint4 *>(&bs[(wn * 64 + bj * 16 + li) * BK16 + lg * 8]);
+            b[bj] = *reinterpret_cast<const uint4 *>(&bs[(wn * 64 + bj * 16 + li) * BK16 + so]);
 #pragma unroll
         for (int bi = 0; bi < 8; ++bi)
 #pragma unroll
@@ -301,8 +325,33 @@ __global__ __launch_bounds__(256, NS <= 2 ? 2 : 1) void lp_schur8_kernel(
         for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
     uint4 cv[2][4];
 
-    const char *gA = reinterpret_cast<const char *>(Lq + (size_t)row0 * BK8) + wave * (SA / 4) + lane * 16;
-    const char *gB = reinterpret_cast<const char *>(Uq + (size_t)col0 * BK8) + wave * (SB / 4) + lane * 16;
+    // LDS layout of a stage: 128-byte lines (one row of L21 or column of U12
+    // over the chunk's 128 k), 16-byte segments.  A row is read by the 16
+    // lanes li of a lane group at once (one pass of a 16-byte LDS read), so
+    // (1) the A rows 32p + 2 li + h that one MFMA block takes sit in 16
+    // consecutive lines, line 32p + 16h + li, and (2) segment s of line x is
+    // stored in slot s ^ sw(x), sw(x) = (x & 7) ^ ((x >> 3) & 1): the 16 lanes
+    // of a pass then touch 16 distinct 16-byte bank groups of the 256 bytes
+    // the LDS serves per cycle (and 8 distinct ones in each half).  The
+    // global->LDS copy writes slots in lane order, so each lane fetches the
+    // global segment that belongs in its slot; the 8 lanes of a line still
+    // read one contiguous 128-byte global line.
+    auto sw = [](int x) { return (x & 7) ^ ((x >> 3) & 1); };
+    const int t8 = lane >> 3, s8 = lane & 7;
+    int offA[NA], offB[NB];   // byte offsets of this lane's global segments in a chunk
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+        const int x = wave * (SA / 4 / BK8) + 8 * q + t8;            // LDS line
+        const int r = 32 * (x >> 5) + 2 * (x & 15) + ((x >> 4) & 1);   // tile row
+        offA[q] = r * BK8 + 16 * (s8 ^ sw(x));
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const int x = wave * (SB / 4 / BK8) + 8 * q + t8;
+        offB[q] = x * BK8 + 16 * (s8 ^ sw(x));
+    }
+    const char *gA = reinterpret_cast<const char *>(Lq + (size_t)row0 * BK8);
+    const char *gB = reinterpret_cast<const char *>(Uq + (size_t)col0 * BK8);
     auto issue = [&](int kc, int st) {
         const char *ga = gA + (size_t)kc * Mp * BK8;
         const char *gb = gB + (size_t)kc * Np * BK8;
@@ -310,17 +359,20 @@ __global__ __launch_bounds__(256, NS <= 2 ? 2 : 1) void lp_schur8_kernel(
         char *lb = reinterpret_cast<char *>(&ring[st][SA]) + wave * (SB / 4);
 #pragma unroll
         for (int q = 0; q < NA; ++q)
-            __builtin_amdgcn_global_load_lds((gvoid_t *)(ga + q * 1024), (lvoid_t *)(la + q * 1024),
+            __builtin_amdgcn_global_load_lds((gvoid_t *)(ga + offA[q]), (lvoid_t *)(la + q * 1024),
                                              16, 0, 0);
 #pragma unroll
         for (int q = 0; q < NB; ++q)
-            __builtin_amdgcn_global_load_lds((gvoid_t *)(gb + q * 1024), (lvoid_t *)(lb + q * 1024),
+            __builtin_amdgcn_global_load_lds((gvoid_t *)(gb + offB[q]), (lvoid_t *)(lb + q * 1024),
                                              16, 0, 0);
     };
-    // a line's 16 bytes at k 16 lg and at k 64 + 16 lg (the matrix cores' k order)
-    auto frag = [lg](const uint8_t *line) {
-        const uint4 lo = *reinterpret_cast<const uint4 *>(line + 16 * lg);
-        const uint4 hi = *reinterpret_cast<const uint4 *>(line + 64 + 16 * lg);
+    // Line x's 16 bytes at k 16 lg and at k 64 + 16 lg (the matrix cores' k
+    // order: segments lg and lg ^ 4); the lines a lane reads are 16-aligned
+    // plus li, so sw(x) = sw(li).
+    const int so = 16 * (lg ^ sw(li));
+    auto frag = [so](const uint8_t *line) {
+        const uint4 lo = *reinterpret_cast<const uint4 *>(line + so);
+        const uint4 hi = *reinterpret_cast<const uint4 *>(line + (so ^ 64));
         return v8i{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
     };
 
@@ -369,7 +421,7 @@ __global__ __launch_bounds__(256, NS <= 2 ? 2 : 1) void lp_schur8_kernel(
         v8i a[4], b[4];
 #pragma unroll
         for (int bi = 0; bi < 4; ++bi)
-            a[bi] = frag(&as[(wm * 64 + 32 * (bi >> 1) + 2 * li + (bi & 1)) * BK8]);
+            a[bi] = frag(&as[(wm * 64 + 32 * (bi >> 1) + 16 * (bi & 1) + li) * BK8]);
 #pragma unroll
         for (int bj = 0; bj < 4; ++bj) b[bj] = frag(&bs[(wn * 64 + bj * 16 + li) * BK8]);
 #pragma unroll
