@@ -80,6 +80,85 @@ static_assert(TM == kLpTileM && TN == kLpTileN, "tile and packing must agree");
 
 typedef __attribute__((address_space(1))) void gvoid_t;
 typedef __attribute__((address_space(3))) void lvoid_t;
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+// LDS byte address of a pointer into a __shared__ array
+__device__ __forceinline__ uint32_t lds_addr(const void *p) {
+    return (uint32_t)reinterpret_cast<uintptr_t>((const lvoid_t *)p);
+}
+
+// Operand fragments of one K chunk read from the LDS ring.  These reads are
+// written as one assembly block that waits for its own results (lgkmcnt(0))
+// because the compiler cannot tell the ring stage read here from the stages
+// that the direct global->LDS copies of later chunks are still filling: it
+// would put a wait for every outstanding copy (vmcnt(0)) before the first
+// read, which leaves no copy in flight while the matrix cores run.  The
+// ring's own vmcnt wait and workgroup barrier order these reads after the
+// copies of the chunk they read.  The outputs are early-clobber: a read is
+// issued before the later reads have taken their addresses.
+//
+// 16-bit form: a[i] at a0 + 1024 i (i < 8), b[j] at b0 + 1024 j (j < 4).
+__device__ __forceinline__ void lds_frags16(uint32_t a0, uint32_t b0, uint4 (&a)[8],
+                                            uint4 (&b)[4]) {
+    v4i x[12];
+    asm volatile(
+        "ds_read_b128 %0, %12\n\t"
+        "ds_read_b128 %1, %12 offset:1024\n\t"
+        "ds_read_b128 %2, %12 offset:2048\n\t"
+        "ds_read_b128 %3, %12 offset:3072\n\t"
+        "ds_read_b128 %4, %12 offset:4096\n\t"
+        "ds_read_b128 %5, %12 offset:5120\n\t"
+        "ds_read_b128 %6, %12 offset:6144\n\t"
+        "ds_read_b128 %7, %12 offset:7168\n\t"
+        "ds_read_b128 %8, %13\n\t"
+        "ds_read_b128 %9, %13 offset:1024\n\t"
+        "ds_read_b128 %10, %13 offset:2048\n\t"
+        "ds_read_b128 %11, %13 offset:3072\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(x[0]), "=&v"(x[1]), "=&v"(x[2]), "=&v"(x[3]), "=&v"(x[4]), "=&v"(x[5]), "=&v"(x[6]),
+          "=&v"(x[7]), "=&v"(x[8]), "=&v"(x[9]), "=&v"(x[10]), "=&v"(x[11])
+        : "v"(a0), "v"(b0));
+#pragma unroll
+    for (int i = 0; i < 8; ++i) a[i] = __builtin_bit_cast(uint4, x[i]);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) b[j] = __builtin_bit_cast(uint4, x[8 + j]);
+}
+
+// FP8 form: fragment i (i < 4) of A is 16 bytes at alo + 2048 i and 16 at
+// ahi + 2048 i, likewise B from blo / bhi.
+__device__ __forceinline__ void lds_frags8(uint32_t alo, uint32_t ahi, uint32_t blo, uint32_t bhi,
+                                           v8i (&a)[4], v8i (&b)[4]) {
+    v4i x[16];
+    asm volatile(
+        "ds_read_b128 %0, %16\n\t"
+        "ds_read_b128 %1, %17\n\t"
+        "ds_read_b128 %2, %16 offset:2048\n\t"
+        "ds_read_b128 %3, %17 offset:2048\n\t"
+        "ds_read_b128 %4, %16 offset:4096\n\t"
+        "ds_read_b128 %5, %17 offset:4096\n\t"
+        "ds_read_b128 %6, %16 offset:6144\n\t"
+        "ds_read_b128 %7, %17 offset:6144\n\t"
+        "ds_read_b128 %8, %18\n\t"
+        "ds_read_b128 %9, %19\n\t"
+        "ds_read_b128 %10, %18 offset:2048\n\t"
+        "ds_read_b128 %11, %19 offset:2048\n\t"
+        "ds_read_b128 %12, %18 offset:4096\n\t"
+        "ds_read_b128 %13, %19 offset:4096\n\t"
+        "ds_read_b128 %14, %18 offset:6144\n\t"
+        "ds_read_b128 %15, %19 offset:6144\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(x[0]), "=&v"(x[1]), "=&v"(x[2]), "=&v"(x[3]), "=&v"(x[4]), "=&v"(x[5]), "=&v"(x[6]),
+          "=&v"(x[7]), "=&v"(x[8]), "=&v"(x[9]), "=&v"(x[10]), "=&v"(x[11]), "=&v"(x[12]),
+          "=&v"(x[13]), "=&v"(x[14]), "=&v"(x[15])
+        : "v"(alo), "v"(ahi), "v"(blo), "v"(bhi));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        a[i] = v8i{x[2 * i].x, x[2 * i].y, x[2 * i].z, x[2 * i].w,
+                   x[2 * i + 1].x, x[2 * i + 1].y, x[2 * i + 1].z, x[2 * i + 1].w};
+        b[i] = v8i{x[8 + 2 * i].x, x[8 + 2 * i].y, x[8 + 2 * i].z, x[8 + 2 * i].w,
+                   x[9 + 2 * i].x, x[9 + 2 * i].y, x[9 + 2 * i].z, x[9 + 2 * i].w};
+    }
+}
 
 __device__ __forceinline__ uint4 neg16(uint4 v) {   // flip the sign bit of 8 16-bit values
     v.x ^= 0x80008000u;
@@ -206,14 +285,12 @@ __global__ __launch_bounds__(256, 2) void lp_schur16_kernel(
         const uint16_t *bs = &ring[kt % kNs16][SA];
         // lines read are 16-aligned plus li, so their swizzle is sw(li)
         const int so = 8 * (lg ^ sw(li));
+        // A block bi at line wm 128 + 16 bi + li, B block bj at wn 64 + 16 bj + li
         uint4 a[8], b[4];
+        lds_frags16(lds_addr(&as[(wm * 128 + li) * BK16 + so]),
+                    lds_addr(&bs[(wn * 64 + li) * BK16 + so]), a, b);
 #pragma unroll
-        for (int bi = 0; bi < 8; ++bi)
-            a[bi] = neg16(*reinterpret_cast<const uint4 *>(
-                &as[(wm * 128 + 32 * (bi >> 1) + 16 * (bi & 1) + li) * BK16 + so]));
-#pragma unroll
-        for (int bj = 0; bj < 4; ++bj)
-            b[bj] = *reinterpret_cast<const uint4 *>(&bs[(wn * 64 + bj * 16 + li) * BK16 + so]);
+        for (int bi = 0; bi < 8; ++bi) a[bi] = neg16(a[bi]);
 #pragma unroll
         for (int bi = 0; bi < 8; ++bi)
 #pragma unroll
@@ -311,8 +388,7 @@ __global__ __launch_bounds__(256, NS <= 2 ? 2 : 1) void lp_schur8_kernel(
     // The accumulators start at zero and the epilogue forms C - acc sL sU (the
     // scalings are exact: powers of two), so the C tile is needed only at the
     // end: interior tiles with 16-byte aligned columns (uniform branch) load it
-    // right after the first operand chunk, and its latency overlaps that
-    // chunk's.
+    // just before the first operand chunks, and its latency overlaps theirs.
     const bool full = row0 + kTm8 <= M && col0 + kTn8 <= N && (ldc & 7) == 0 &&
                       ((uintptr_t)C & 15) == 0;
     auto row_of = [&](int bi, int r) -> int64_t {
@@ -370,17 +446,11 @@ __global__ __launch_bounds__(256, NS <= 2 ? 2 : 1) void lp_schur8_kernel(
     // order: segments lg and lg ^ 4); the lines a lane reads are 16-aligned
     // plus li, so sw(x) = sw(li).
     const int so = 16 * (lg ^ sw(li));
-    auto frag = [so](const uint8_t *line) {
-        const uint4 lo = *reinterpret_cast<const uint4 *>(line + so);
-        const uint4 hi = *reinterpret_cast<const uint4 *>(line + (so ^ 64));
-        return v8i{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
-    };
 
     const int nk = K / BK8;
     constexpr int kLoads = NA + NB;   // loads per wave and chunk
-#pragma unroll
-    for (int c = 0; c < kNs8 - 1; ++c)
-        if (c < nk) issue(c, c);
+    // the C tile's loads go first, so that the ring's waits below count only
+    // operand chunks issued after the one they wait for
     if (full) {
 #pragma unroll
         for (int pr = 0; pr < 2; ++pr)
@@ -391,6 +461,9 @@ __global__ __launch_bounds__(256, NS <= 2 ? 2 : 1) void lp_schur8_kernel(
                 cv[pr][bj] = *reinterpret_cast<const uint4 *>(&C[(size_t)r8 + (size_t)c * ldc]);
             }
     }
+#pragma unroll
+    for (int c = 0; c < kNs8 - 1; ++c)
+        if (c < nk) issue(c, c);
     // MX scale bytes of chunk kc for this lane's four A rows and four B
     // columns (rows beyond M read stale bytes: their outputs are not stored)
     int sa[4] = {127, 127, 127, 127}, sb[4] = {127, 127, 127, 127};
@@ -407,7 +480,7 @@ __global__ __launch_bounds__(256, NS <= 2 ? 2 : 1) void lp_schur8_kernel(
     if constexpr (MX) load_scales(0, sa, sb);
     for (int kt = 0; kt < nk; ++kt) {
         // chunk kt has landed once at most min(NS - 2, nk - 1 - kt) later
-        // chunks are outstanding (the C loads were issued before them)
+        // chunks are outstanding
         const int later = min(kNs8 - 2, nk - 1 - kt);
         if (kNs8 >= 4 && later >= 2) wait_vmcnt<2 * kLoads>();
         else if (kNs8 >= 3 && later >= 1) wait_vmcnt<kLoads>();
@@ -418,12 +491,11 @@ __global__ __launch_bounds__(256, NS <= 2 ? 2 : 1) void lp_schur8_kernel(
             if (kt + 1 < nk) load_scales(kt + 1, sa_n, sb_n);
         const uint8_t *as = &ring[kt % kNs8][0];
         const uint8_t *bs = &ring[kt % kNs8][SA];
+        // A block bi at line wm 64 + 16 bi + li, B block bj at wn 64 + 16 bj + li
         v8i a[4], b[4];
-#pragma unroll
-        for (int bi = 0; bi < 4; ++bi)
-            a[bi] = frag(&as[(wm * 64 + 32 * (bi >> 1) + 16 * (bi & 1) + li) * BK8]);
-#pragma unroll
-        for (int bj = 0; bj < 4; ++bj) b[bj] = frag(&bs[(wn * 64 + bj * 16 + li) * BK8]);
+        const uint8_t *la = &as[(wm * 64 + li) * BK8], *lb = &bs[(wn * 64 + li) * BK8];
+        lds_frags8(lds_addr(la + so), lds_addr(la + (so ^ 64)), lds_addr(lb + so),
+                   lds_addr(lb + (so ^ 64)), a, b);
 #pragma unroll
         for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
@@ -522,9 +594,9 @@ int lp_schur_update_fp8(int fmt, int64_t M, int64_t N, int K, const uint8_t *Lq,
     const int64_t tiles_m = (M + kTm8 - 1) / kTm8, tiles_n = (N + kTn8 - 1) / kTn8;
     const dim3 grid((unsigned)(tiles_m * tiles_n));
     // two stages with two workgroups per CU: measured faster than three or
-    // four stages with one workgroup per CU (4.5 s against 3.2 s per solve at
-    // N = 131072), whose single wave per SIMD leaves the LDS reads and the
-    // epilogue exposed
+    // four stages with one workgroup per CU (11.5 ms against 17.2 and 18.2 ms
+    // per launch on average at N = 131072, NB = 1024), whose single wave per
+    // SIMD leaves the barrier, the LDS reads and the epilogue exposed
     constexpr int kStages = 2;
     const uint8_t *none = nullptr;
     if (fmt == kFmtBf16)
