@@ -360,6 +360,46 @@ def test_full_size_bf16_configuration(api):
         assert abs(r_i) <= 16 * EPS * n * (np.abs(arow).sum() * np.abs(x).max() + np.abs(b).max())
 
 
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+def test_full_size_fp8_configuration(api):
+    """N = 131072 diagonally dominant, FP8 e4m3 updates with per-tile scales,
+    FP16 storage, NB = 1024, GMRES-IR: converged, independent scaled residual
+    and sampled rows below the threshold, and the seeded form (A regenerated
+    inside the conversion and every residual, no FP64 copy) gives the same X
+    bit for bit."""
+    cfg = inputs.WORKLOADS["fp8_ir"]
+    n, nb, seed = cfg["n"], cfg["nb"], inputs.config_seed(cfg["index"])
+    note(f"full size fp8 n={n} nb={nb}")
+    dA = api.fortran_empty(n, n)
+    api.fill_uniform(dA, seed, inputs.STREAM_A)
+    api.make_diag_dominant(dA)
+    db = torch.from_numpy(inputs.uniform_matrix(seed, inputs.STREAM_B, n, 1)[:, 0]).cuda()
+    X, rep, work, _ = api.mxp_solve(dA, db, prec="fp8", nb=nb, refine="gmres", scale_tile=128)
+    torch.cuda.synchronize()
+    note(f"report {rep}")
+    assert rep["converged"] == 1 and rep["info"] == 0
+    rho = api.scaled_residual(dA, X, db)[0]
+    note(f"independent scaled residual {rho:.3e}")
+    assert rho < 16
+    x = X.cpu().numpy()
+    b = db.cpu().numpy()
+    for i in (0, 1, 65537, n - 1):
+        arow = inputs.uniform_at(seed, inputs.STREAM_A,
+                                 np.arange(n, dtype=np.uint64) * np.uint64(n) + np.uint64(i))
+        arow[i] = np.abs(arow).sum() - np.abs(arow[i])
+        r_i = b[i] - arow @ x
+        assert abs(r_i) <= 16 * EPS * n * (np.abs(arow).sum() * np.abs(x).max() + np.abs(b).max())
+    del dA
+    torch.cuda.empty_cache()
+    Xs, reps, _, _ = api.mxp_solve_seeded(n, seed, inputs.STREAM_A, db, dominant=True, work=work,
+                                          prec="fp8", nb=nb, refine="gmres", scale_tile=128)
+    torch.cuda.synchronize()
+    note(f"seeded report {reps}")
+    assert reps["outer_iters"] == rep["outer_iters"] and reps["inner_iters"] == rep["inner_iters"]
+    assert torch.equal(Xs, X)
+
+
 def test_lp_pivoted_first_panel_matches_oracle(api):
     """Partial pivoting on FP32 panel values: the first panel (same FP32
     operation order) gives the oracle's pivots and values bit for bit."""
