@@ -37,18 +37,22 @@ typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef int v8i __attribute__((ext_vector_type(8)));
 
 constexpr int TM = 256, TN = 128;
-constexpr int GROUP_M = 8;
 
+// Tile of workgroup g: consecutive workgroup ids go to the eight XCDs in
+// turn, so each XCD takes a contiguous range of the tile order, in which
+// groups of GM tile rows are walked column by column (the operand panels of
+// the tiles an XCD runs at once stay in its L2).
+template <int GM>
 __device__ inline void tile_of(int g, int tiles_m, int tiles_n, int &tm, int &tn) {
     const int G = tiles_m * tiles_n;
     const int per = G / 8, rem = G % 8;
     const int xcd = g % 8, local = g / 8;
     const int t = (xcd < rem) ? xcd * (per + 1) + local
                               : rem * (per + 1) + (xcd - rem) * per + local;
-    const int in_group = GROUP_M * tiles_n;
+    const int in_group = GM * tiles_n;
     const int group = t / in_group;
-    const int first_m = group * GROUP_M;
-    const int gsize = min(tiles_m - first_m, GROUP_M);
+    const int first_m = group * GM;
+    const int gsize = min(tiles_m - first_m, GM);
     const int r = t - group * in_group;
     tm = first_m + r % gsize;
     tn = r / gsize;
@@ -177,7 +181,7 @@ __global__ __launch_bounds__(256, 2) void lp_schur16_kernel(
     __shared__ __attribute__((aligned(1024))) uint16_t ring[kNs16][SA + SB];
 
     int tm, tn;
-    tile_of(blockIdx.x, tiles_m, tiles_n, tm, tn);
+    tile_of<8>(blockIdx.x, tiles_m, tiles_n, tm, tn);
     const int64_t row0 = (int64_t)tm * TM, col0 = (int64_t)tn * TN;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int wm = wave & 1, wn = wave >> 1;
@@ -369,7 +373,7 @@ __global__ __launch_bounds__(256, NS <= 2 ? 2 : 1) void lp_schur8_kernel(
     __shared__ __attribute__((aligned(1024))) uint8_t ring[kNs8][SA + SB];
 
     int tm, tn;
-    tile_of(blockIdx.x, tiles_m, tiles_n, tm, tn);
+    tile_of<16>(blockIdx.x, tiles_m, tiles_n, tm, tn);
     const int64_t row0 = (int64_t)tm * kTm8, col0 = (int64_t)tn * kTn8;
     // scale-tile index of a row or column (32-bit; a shift for power-of-two tiles)
     const bool pow2 = (tile & (tile - 1)) == 0;
@@ -596,7 +600,10 @@ int lp_schur_update_fp8(int fmt, int64_t M, int64_t N, int K, const uint8_t *Lq,
     // two stages with two workgroups per CU: measured faster than three or
     // four stages with one workgroup per CU (11.5 ms against 17.2 and 18.2 ms
     // per launch on average at N = 131072, NB = 1024), whose single wave per
-    // SIMD leaves the barrier, the LDS reads and the epilogue exposed
+    // SIMD leaves the barrier, the LDS reads and the epilogue exposed, and
+    // faster than a 256 x 256 tile with 128 x 128 per wave (11.6 ms); groups
+    // of 16 tile rows in the tile order (11.06 ms) against 4, 8 and 32 (11.18,
+    // 11.50, 13.00 ms)
     constexpr int kStages = 2;
     const uint8_t *none = nullptr;
     if (fmt == kFmtBf16)
