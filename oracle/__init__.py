@@ -31,7 +31,7 @@ LIB_PATH = os.path.join(_HERE, "libmxlu_oracle.so")
 CFLAGS = ["-O2", "-fopenmp", "-ffp-contract=off", "-mfma", "-fPIC", "-shared",
           "-std=c11"]
 
-BF16, FP16, E4M3 = 0, 1, 2
+BF16, FP16, E4M3, FP32 = 0, 1, 2, 3
 
 _lib = None
 
@@ -185,7 +185,7 @@ def getrs(LU, ipiv, B, trans=False):
 
 
 def round_lp(x, fmt):
-    """Round FP64 values to bf16 (0), fp16 (1) or e4m3fn (2), returned as FP64."""
+    """Round FP64 values to bf16 (0), fp16 (1), e4m3fn (2) or fp32 (3), returned as FP64."""
     a = np.ascontiguousarray(x, dtype=np.float64)
     out = np.empty_like(a)
     lib().oracle_round_array(a.size, _ptr(a), _ptr(out), int(fmt))
@@ -204,7 +204,7 @@ def mx_scale(amax):
 def lp_getrf(A, nb, prec, pivot=False, tile=128, max_steps=-1):
     """Low-precision blocked LU (Sec. III-A.2).  prec: 0 bf16, 1 fp16, 2 fp8
     updates with fp16 storage and per-tile scales, 3 fp8 updates with fp16
-    storage and MX (E8M0 per 32 k) block scales.  Returns (F, ipiv or None, info) where F holds
+    storage and MX (E8M0 per 32 k) block scales, 4 fp32 storage.  Returns (F, ipiv or None, info) where F holds
     the stored factor values as FP64 numbers.  max_steps >= 0 stops after that
     many panel steps (the trailing block then holds the updated, unfactored
     Schur complement in storage precision)."""

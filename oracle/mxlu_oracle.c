@@ -279,7 +279,7 @@ int oracle_getrs(int64_t n, int64_t nrhs, const double *LU, int64_t lda,
  *   e4m3fn  p = 4,  emin = -6,   largest finite 448, no inf (OCP FP8 spec):
  *           conversions saturate to +-448.
  */
-enum { ORACLE_BF16 = 0, ORACLE_FP16 = 1, ORACLE_E4M3 = 2 };
+enum { ORACLE_BF16 = 0, ORACLE_FP16 = 1, ORACLE_E4M3 = 2, ORACLE_FP32 = 3 };
 
 double oracle_round(double x, int fmt)
 {
@@ -290,6 +290,7 @@ double oracle_round(double x, int fmt)
     case ORACLE_BF16: p = 8;  emin = -126; maxfin = ldexp(2.0 - ldexp(1.0, -7), 127); saturate = 0; break;
     case ORACLE_FP16: p = 11; emin = -14;  maxfin = 65504.0; saturate = 0; break;
     case ORACLE_E4M3: p = 4;  emin = -6;   maxfin = 448.0;   saturate = 1; break;
+    case ORACLE_FP32: p = 24; emin = -126; maxfin = ldexp(2.0 - ldexp(1.0, -23), 127); saturate = 0; break;
     default: return NAN;
     }
     if (x != x || x == 0.0) return x;
@@ -348,7 +349,7 @@ double oracle_mx_scale(double amax)
 /* ------------------------------------------------------------------------ */
 /*
  * Storage S holds, as FP64 numbers, values representable in the storage
- * format (bf16 for prec 0, fp16 for prec 1 and 2).  prec 2 keeps fp16 storage
+ * format (bf16 for prec 0, fp16 for prec 1, 2 and 3, FP32 for prec 4).  prec 2 keeps fp16 storage
  * but performs the trailing update with e4m3fn operands and FP32 tile scales.
  *
  * Step at column k0 with width kb (m = n - k0 rows):
@@ -364,6 +365,8 @@ double oracle_mx_scale(double amax)
  *               kb x `tile` columns, to e4m3fn with power-of-two scales;
  *               acc = sum_k Lq Uq in FP32 (k ascending, from 0);
  *               A22 <- round_fp16( fp32(A22) - (acc * sL) * sU ).
+ *     prec 4:   FP32 storage (IEEE binary32): every rounding to storage is
+ *               a rounding to FP32, the update as for prec 0/1.
  *     prec 3:   MX form: each row of L21 and column of U12 quantised in
  *               blocks of 32 k with one E8M0 scale per block;
  *               acc = sum_k (Lq sL)(Uq sU) in FP32 (k ascending, from 0);
@@ -375,8 +378,8 @@ int oracle_lp_getrf_steps(int64_t n, int64_t nb, int prec, int pivot, int64_t ti
                           double *S, int64_t lds, int32_t *ipiv, int64_t max_steps)
 {
     if (n < 0 || nb < 1 || lds < (n > 1 ? n : 1)) return -1;
-    if (prec < 0 || prec > 3 || tile < 1) return -3;
-    int sfmt = (prec == 0) ? ORACLE_BF16 : ORACLE_FP16;
+    if (prec < 0 || prec > 4 || tile < 1) return -3;
+    int sfmt = (prec == 0) ? ORACLE_BF16 : (prec == 4) ? ORACLE_FP32 : ORACLE_FP16;
     int info = 0;
 
     /* storage conversion of the input */
@@ -387,7 +390,8 @@ int oracle_lp_getrf_steps(int64_t n, int64_t nb, int prec, int pivot, int64_t ti
     float *P = (float *)malloc(sizeof(float) * (size_t)n * (size_t)nb);
     float *Lq = NULL, *Uq = NULL;
     double *sL = NULL, *sU = NULL;
-    if (prec >= 2) {
+    const int fp8 = (prec == 2 || prec == 3);
+    if (fp8) {
         /* prec 2: one scale per tile; prec 3: one per (line, block of 32 k) */
         size_t ns = (prec == 2) ? (size_t)(n / tile + 1)
                                 : (size_t)n * (size_t)((nb + 31) / 32);
@@ -396,7 +400,7 @@ int oracle_lp_getrf_steps(int64_t n, int64_t nb, int prec, int pivot, int64_t ti
         sL = (double *)malloc(sizeof(double) * ns);
         sU = (double *)malloc(sizeof(double) * ns);
     }
-    if (!P || (prec >= 2 && (!Lq || !Uq || !sL || !sU))) {
+    if (!P || (fp8 && (!Lq || !Uq || !sL || !sU))) {
         free(P); free(Lq); free(Uq); free(sL); free(sU);
         return -1000;
     }

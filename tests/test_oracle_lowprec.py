@@ -21,6 +21,7 @@ FORMATS = {
     "bf16": (oracle.BF16, 8, -126, float.fromhex("0x1.fep127"), torch.bfloat16),
     "fp16": (oracle.FP16, 11, -14, 65504.0, torch.float16),
     "e4m3": (oracle.E4M3, 4, -6, 448.0, torch.float8_e4m3fn),
+    "fp32": (oracle.FP32, 24, -126, float.fromhex("0x1.fffffep127"), torch.float32),
 }
 
 
@@ -63,7 +64,7 @@ def test_rounding_matches_torch_casts_on_fp32_inputs(oracle_lib, fmt):
     assert np.array_equal(got, ref)
 
 
-@pytest.mark.parametrize("fmt", ["bf16", "fp16", "e4m3"])
+@pytest.mark.parametrize("fmt", ["bf16", "fp16", "e4m3", "fp32"])
 def test_rounding_is_correct_directly_from_fp64(oracle_lib, fmt):
     """Values that are not FP32 numbers: a path through FP32 would round twice."""
     fid, p, emin, maxfin, _ = FORMATS[fmt]
@@ -83,6 +84,22 @@ def test_rounding_is_correct_directly_from_fp64(oracle_lib, fmt):
     if fmt != "e4m3":
         h = oracle.round_lp(np.array([half, np.nextafter(half, 2)]), fid)
         assert h[0] == 1.0 and h[1] == 1.0 + q
+
+
+def test_fp32_rounding_is_the_ieee_cast(oracle_lib):
+    """FP32 storage (the precision ladder's FP32 rung): rounding an FP64 value
+    to FP32 is IEEE binary32 round-to-nearest-even, i.e. numpy's cast, over
+    normal, subnormal and overflowing values."""
+    rng = np.random.default_rng(8)
+    xs = np.concatenate([
+        rng.standard_normal(20000) * 2.0 ** rng.integers(-160, 130, 20000),
+        [2.0 ** -149, 2.0 ** -150, 3 * 2.0 ** -151, 2.0 ** 128, -(2.0 ** 128),
+         float.fromhex("0x1.ffffffp127"), float.fromhex("0x1.fffffe8p127")],
+    ])
+    got = oracle.round_lp(xs, oracle.FP32)
+    with np.errstate(over="ignore"):
+        ref = xs.astype(np.float32).astype(np.float64)
+    assert np.array_equal(got, ref)
 
 
 def test_rounding_specials(oracle_lib):
@@ -116,13 +133,13 @@ def _exact_lu_pair(n, rng, dominant_l=True):
     return L, U
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 4])
 def test_lp_lu_reproduces_exact_factors(oracle_lib, prec):
     rng = np.random.default_rng(11)
     n = 12
     L, U = _exact_lu_pair(n, rng)
     A = L @ U
-    assert np.array_equal(oracle.round_lp(A, prec), A)
+    assert np.array_equal(oracle.round_lp(A, {0: 0, 1: 1, 4: oracle.FP32}[prec]), A)
     F, _, info = oracle.lp_getrf(A, nb=5, prec=prec, pivot=False)
     assert info == 0
     assert np.array_equal(np.tril(F, -1), np.tril(L, -1))
@@ -234,19 +251,23 @@ def test_lp_lu_pivoted_recovers_permutation(oracle_lib):
 
 
 @pytest.mark.parametrize("prec,u", [(0, 2.0 ** -8), (1, 2.0 ** -11), (2, 2.0 ** -4),
-                                    (3, 2.0 ** -4)])
+                                    (3, 2.0 ** -4), (4, 2.0 ** -24)])
 def test_lp_lu_backward_error_bound(oracle_lib, prec, u):
     n = 192
     A = inputs.diag_dominant_matrix(21, 0, n)
     F, _, info = oracle.lp_getrf(A, nb=32, prec=prec, pivot=False, tile=64)
     assert info == 0
     L, U = checks.unpack_lu(F)
+    # storage rounding (u) plus the FP32 arithmetic of the k sums (n 2^-24),
+    # which dominates only for FP32 storage
+    u32 = 2.0 ** -24
     err = np.abs(L @ U - A).sum(1).max() / np.abs(A).sum(1).max()
-    assert err <= 4 * u
+    assert err <= 4 * u + n * u32
     # and close to the FP64 factors (the FP64 oracle pivots on the diagonal here)
     LU64, ipiv64, _ = oracle.getrf(A, 32)
     assert np.array_equal(ipiv64, np.arange(n))
-    assert np.abs(np.triu(F) - np.triu(LU64)).max() <= 8 * u * np.abs(np.triu(LU64)).max()
+    assert (np.abs(np.triu(F) - np.triu(LU64)).max()
+            <= (8 * u + 2 * n * u32) * np.abs(np.triu(LU64)).max())
 
 
 def test_dominant_matrix_pivots_on_diagonal(oracle_lib):
@@ -332,7 +353,7 @@ def test_refine_exact_factors_converge_immediately(oracle_lib):
 
 
 @pytest.mark.parametrize("method,prec", [("classical", 0), ("gmres", 0), ("gmres", 2),
-                                         ("classical", 1), ("gmres", 3)])
+                                         ("classical", 1), ("gmres", 3), ("gmres", 4)])
 def test_refine_reaches_fp64_accuracy_on_dominant_matrix(oracle_lib, method, prec):
     n = 256
     A = inputs.diag_dominant_matrix(inputs.config_seed(2), 0, n)

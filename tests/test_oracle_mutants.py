@@ -53,6 +53,10 @@ MUTANTS = [
      "sL[(i - c1) * nblk + ((k / 32) ^ 1) % nblk]);", 0),
     ("lp_mx_u_first_block_scale", "sU[(c - c1) * nblk + k / 32]);   /* exact */",
      "sU[(c - c1) * nblk]);", 0),
+    ("lp_fp32_storage_rounds_to_fp16",
+     "int sfmt = (prec == 0) ? ORACLE_BF16 : (prec == 4) ? ORACLE_FP32 : ORACLE_FP16;",
+     "int sfmt = (prec == 0) ? ORACLE_BF16 : (prec == 4) ? ORACLE_FP16 : ORACLE_FP16;", 0),
+    ("round_fp32_precision", "case ORACLE_FP32: p = 24;", "case ORACLE_FP32: p = 23;", 0),
     ("lp_trsm_wrong_factor", "uu[i] = fmaf(-P[IDX(i, k, m)], uu[k], uu[i]);",
      "uu[i] = fmaf(-P[IDX(k, i, m)], uu[k], uu[i]);", 0),
     ("precond_no_forward_solve",
@@ -76,6 +80,8 @@ PINS = [
              for f in ("bf16", "fp16", "e4m3")],
     lambda: P.test_fp8_scale_is_minimal_power_of_two(None),
     lambda: [P.test_lp_lu_reproduces_exact_factors(None, p) for p in (0, 1)],
+    lambda: P.test_fp32_rounding_is_the_ieee_cast(None),
+    lambda: P.test_lp_lu_backward_error_bound(None, 4, 2.0 ** -24),
     lambda: P.test_lp_lu_fp8_update_exact_on_representable_operands(None),
     lambda: [P.test_lp_lu_fp8_distinct_tile_scales_exact(None, n, nb, t)
              for n, nb, t in ((24, 8, 4), (40, 16, 8), (36, 12, 12))],
