@@ -172,10 +172,13 @@ enum {
     MXLU_PREC_FP16 = 1,  /* fp16 storage, FP16 MFMA trailing update, FP32 accumulation */
     MXLU_PREC_FP8 = 2,   /* fp16 storage, e4m3fn operands with per-tile power-of-two
                             FP32 scales in the trailing update, FP32 accumulation */
-    MXLU_PREC_FP8_MX = 3 /* fp16 storage, e4m3fn operands with one E8M0 (power-of-two)
+    MXLU_PREC_FP8_MX = 3, /* fp16 storage, e4m3fn operands with one E8M0 (power-of-two)
                             scale per row of L21 / column of U12 and block of 32 k,
                             applied by the matrix cores (OCP MX block scaling);
                             FP32 accumulation; scale_tile unused */
+    MXLU_PREC_FP32 = 4    /* fp32 storage (4 bytes per factor value), FP32 panel, TRSM and
+                            trailing update (vector fused multiply-adds, k ascending);
+                            forward solves only (trans must be 0) */
 };
 enum { MXLU_IR_CLASSICAL = 0, MXLU_IR_GMRES = 1 };
 
@@ -218,8 +221,9 @@ void mxp_default_opts(mxp_opts *opts);
  * at leading dimension lda (>= n), or 0 when an argument is invalid or the
  * size overflows.  The workspace starts with the low-precision factors: an n x n
  * column-major array of 16-bit words (bf16 for MXLU_PREC_BF16, fp16 for the
- * other two precisions) with leading dimension mxp_factor_ld(n), holding L
- * (unit lower, below the diagonal) and U (upper), as lu_factor does in FP64. */
+ * FP16 and FP8 precisions) or of FP32 values (MXLU_PREC_FP32) with leading
+ * dimension mxp_factor_ld(n), holding L (unit lower, below the diagonal) and U
+ * (upper), as lu_factor does in FP64. */
 size_t mxp_workspace_bytes(int64_t n, int64_t lda, const mxp_opts *opts);
 int64_t mxp_factor_ld(int64_t n);
 
@@ -227,7 +231,8 @@ int64_t mxp_factor_ld(int64_t n);
  * mxp_convert -- the down-conversion step alone (Sec. III-A.2: the matrix is
  * stored in reduced precision): F (rows x cols, 16-bit words, leading
  * dimension ldf) <- A (FP64) rounded to nearest, ties to even, directly from
- * FP64.  prec: MXLU_PREC_BF16 -> bf16, otherwise fp16.  Asynchronous.
+ * FP64.  prec: MXLU_PREC_BF16 -> bf16, MXLU_PREC_FP16 / FP8 / FP8_MX -> fp16
+ * (MXLU_PREC_FP32 is not a 16-bit format: -1).  Asynchronous.
  */
 int mxp_convert(int32_t prec, int64_t rows, int64_t cols, const double *A, int64_t lda,
                 uint16_t *F, int64_t ldf, void *stream);

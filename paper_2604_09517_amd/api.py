@@ -170,7 +170,7 @@ def scaled_residual(A, X, B, trans=False):
     return [out[i] for i in range(nrhs)]
 
 
-PREC = {"bf16": 0, "fp16": 1, "fp8": 2, "fp8_mx": 3}
+PREC = {"bf16": 0, "fp16": 1, "fp8": 2, "fp8_mx": 3, "fp32": 4}
 REFINE = {"classical": 0, "gmres": 1}
 
 
@@ -207,10 +207,14 @@ def mxp_factor_ld(n):
 
 def mxp_factors(work, n, prec="bf16"):
     """View of the low-precision factors held at the start of `work`
-    (n x n, column-major, as torch.bfloat16 or torch.float16)."""
+    (n x n, column-major, as torch.bfloat16, torch.float16 or, for FP32
+    storage, torch.float32)."""
     ldf = mxp_factor_ld(n)
-    dt = torch.bfloat16 if prec in ("bf16", 0) else torch.float16
-    words = work[: 2 * ldf * n].view(dt)
+    if prec in ("fp32", 4):
+        dt, esz = torch.float32, 4
+    else:
+        dt, esz = (torch.bfloat16 if prec in ("bf16", 0) else torch.float16), 2
+    words = work[: esz * ldf * n].view(dt)
     return words.view(n, ldf).t()[:n, :]
 
 

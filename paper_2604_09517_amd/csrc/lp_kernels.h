@@ -18,6 +18,8 @@ int lp_convert(int fmt, int64_t rows, int64_t cols, const double *A, int64_t lda
 // seed); gen_dominant_diag fills the diagonal of the seeded dominant matrix.
 int lp_convert_src(int fmt, int64_t n, const ASource &src, uint16_t *F, int64_t ldf,
                    hipStream_t s);
+// F = fp32(A) for FP32 factor storage (A in memory or seeded)
+int lp_convert_src_f32(int64_t n, const ASource &src, float *F, int64_t ldf, hipStream_t s);
 int gen_dominant_diag(int64_t n, uint64_t key, double *diag, hipStream_t s);
 // P (FP32) <- F (16-bit), exact; F <- round(P).
 int lp_load_f32(int fmt, int64_t rows, int64_t cols, const uint16_t *F, int64_t ldf, float *P,

@@ -56,6 +56,15 @@ __global__ void convert_seeded_kernel(int64_t n, ASource src, uint16_t *__restri
         F[(size_t)i + (size_t)j * (size_t)ldf] = f64_to_lp<FMT>(src.at(i, j));
 }
 
+// FP32 storage: F = fp32(A), IEEE round to nearest even (the cast), from A in
+// memory or regenerated from its seed.
+__global__ void convert_f32_kernel(int64_t n, ASource src, float *__restrict__ F, int64_t ldf) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int64_t j = blockIdx.y; j < n; j += gridDim.y)
+        F[(size_t)i + (size_t)j * (size_t)ldf] = (float)src.at(i, j);
+}
+
 template <int FMT>
 __global__ void lp_to_f32_kernel(int64_t rows, int64_t cols, const uint16_t *__restrict__ F,
                                  int64_t ldf, float *__restrict__ P, int64_t ldp) {
@@ -601,6 +610,13 @@ int lp_convert_src(int fmt, int64_t n, const ASource &src, uint16_t *F, int64_t 
     else
         hipLaunchKernelGGL(convert_seeded_kernel<kFmtFp16>, grid2(n, n), dim3(256), 0, s, n, src, F,
                            ldf);
+    MXLU_LAUNCH_CHECK();
+    return 0;
+}
+
+int lp_convert_src_f32(int64_t n, const ASource &src, float *F, int64_t ldf, hipStream_t s) {
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(convert_f32_kernel, grid2(n, n), dim3(256), 0, s, n, src, F, ldf);
     MXLU_LAUNCH_CHECK();
     return 0;
 }

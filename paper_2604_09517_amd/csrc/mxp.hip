@@ -192,12 +192,90 @@ int lp_factorize(const mxp_opts &o, int64_t n, const ASource &src, uint16_t *F,
     return 0;
 }
 
+// FP32 factor storage (the first rung of the precision ladder): the factors
+// are FP32 numbers in the workspace, so the panel, the interchanges, the U12
+// TRSM and the trailing update all work in place on them with the FP32 kernels
+// (every element takes its terms in ascending k, one fused multiply-add each).
+int lp_factorize_f32(const mxp_opts &o, int64_t n, const ASource &src, float *F, int64_t ldf,
+                     int32_t *ipiv, int *info_host, hipStream_t s, double *t_conv,
+                     double *t_fact) {
+    const int64_t nb = std::min<int64_t>(o.nb, n);
+    Scratch scratch(s);
+    int *d_info = scratch.alloc_n<int>(4);
+    if (!d_info) return MXLU_E_NOMEM;
+    MXLU_HIP_TRY(hipMemsetAsync(d_info, 0, 4 * sizeof(int), s));
+    PanelExchange ex{};
+    int *moves = nullptr;
+    if (o.pivot) {
+        MXLU_TRY(alloc_panel_exchange(scratch, n, &ex, s));
+        moves = scratch.alloc_n<int>(kSwapMovesInts);
+        if (!moves) return MXLU_E_NOMEM;
+    }
+    Timer tc(s), tf(s);
+    tc.start();
+    {
+        PhaseScope ph(kPhaseConvert, s, 12.0 * (double)n * (double)n);
+        MXLU_TRY(lp_convert_src_f32(n, src, F, ldf, s));
+    }
+    tc.stop();
+    tf.start();
+    {
+        PhaseScope ph(kPhaseLpFactor, s, (2.0 / 3.0) * (double)n * n * n);
+        int64_t step = 0;
+        for (int64_t k0 = 0; k0 < n; k0 += nb, ++step) {
+            if (o.factor_steps > 0 && step >= o.factor_steps) break;
+            profile_set_step(step);
+            const int64_t kb = std::min(nb, n - k0), m = n - k0, c1 = k0 + kb;
+            float *Fk = F + (size_t)k0 + (size_t)k0 * ldf;
+            {
+                PhaseScope ph(kPhasePfact, s, 4.0 * (double)m * kb);
+                if (o.pivot)
+                    MXLU_TRY(panel_factor<float>(Fk, ldf, m, kb, k0, ipiv, ex, moves, s));
+                else
+                    MXLU_TRY(lp_panel_factor_nopiv(m, (int)kb, Fk, ldf, d_info, k0, s));
+            }
+            if (o.pivot && n > kb) {
+                PhaseScope ph(kPhaseSwap, s, 16.0 * kb * (double)(n - kb));
+                MXLU_TRY(swap_compose(ipiv, k0, (int)kb, n, moves, s));
+                MXLU_TRY(swap_apply<float>(F, ldf, k0, moves, 0, n - kb, k0, kb, s));
+            }
+            if (c1 >= n) continue;
+            const int64_t nt = n - c1;
+            float *U12 = F + (size_t)k0 + (size_t)c1 * ldf;
+            {
+                PhaseScope ph(kPhaseTrsm, s, (double)kb * (kb - 1) * (double)nt);
+                MXLU_TRY(trsm_f32_llnu(kb, nt, Fk, ldf, U12, ldf, s));
+            }
+            {   // A22 -= L21 U12 in FP32 (work: bytes of A22 read and written)
+                PhaseScope ph(kPhaseLpSchur, s, 8.0 * (double)nt * (double)nt);
+                MXLU_TRY(gemm_f32_sub(nt, nt, kb, F + (size_t)c1 + (size_t)k0 * ldf, ldf, U12, ldf,
+                                      F + (size_t)c1 + (size_t)c1 * ldf, ldf, s));
+            }
+        }
+    }
+    profile_set_step(-1);
+    tf.stop();
+    int hinfo[4] = {0, 0, 0, 0};
+    MXLU_HIP_TRY(hipMemcpyAsync(hinfo, o.pivot ? ex.flags : d_info, sizeof(hinfo),
+                                hipMemcpyDeviceToHost, s));
+    MXLU_HIP_TRY(hipStreamSynchronize(s));
+    if (o.pivot && hinfo[1]) {
+        set_error_msg("mxp_solve: panel grid barrier wait expired");
+        return MXLU_E_TIMEOUT;
+    }
+    *info_host = hinfo[0];
+    *t_conv = tc.ms();
+    *t_fact = tf.ms();
+    return 0;
+}
+
 // ------------------------------------------------------------------ refine
 struct RefineCtx {
     int fmt, trans;
     int64_t n, ldf;
     ASource src;   // the FP64 matrix: in memory or regenerated from its seed
     const uint16_t *F;
+    const float *F32 = nullptr;   // FP32 factor storage
     const int32_t *perm;
     hipStream_t s;
     const mxp_opts *o;
@@ -211,6 +289,8 @@ struct RefineCtx {
 };
 
 int precond(RefineCtx &c, const double *r, double *d) {
+    if (c.F32)
+        return lp_precond_apply_f32(c.n, c.F32, c.ldf, c.perm, r, d, c.v32, c.stats + 3, c.s);
     return lp_precond_apply(c.fmt, c.trans, c.n, c.F, c.ldf, c.perm, r, d, c.v32, c.stats + 3,
                             c.ch, c.s);
 }
@@ -369,9 +449,10 @@ extern "C" void mxp_default_opts(mxp_opts *o) {
 extern "C" size_t mxp_workspace_bytes(int64_t n, int64_t lda, const mxp_opts *o) {
     if (n < 0 || lda < std::max<int64_t>(1, n) || !o) return 0;
     const int64_t ldf = factor_ld(n);
-    const double bytes = (double)ldf * (double)n * 2.0 + 256.0;
+    const size_t esz = o->prec == MXLU_PREC_FP32 ? 4 : 2;   // bytes per stored factor value
+    const double bytes = (double)ldf * (double)n * (double)esz + 256.0;
     if (bytes > 9.0e18) return 0;
-    return (size_t)ldf * (size_t)n * 2 + 256;
+    return (size_t)ldf * (size_t)n * esz + 256;
 }
 
 extern "C" int64_t mxp_factor_ld(int64_t n) { return n < 0 ? 0 : factor_ld(n); }
@@ -404,10 +485,11 @@ int mxp_check(int64_t n, int64_t nrhs, const double *B, int64_t ldb, double *X, 
     if (n > 0 && !work) return -9;
     if (!opts) return -12;
     const mxp_opts &o = *opts;
-    if (o.prec < 0 || o.prec > 3 || (o.pivot != 0 && o.pivot != 1) || o.nb < 32 ||
+    if (o.prec < 0 || o.prec > 4 || (o.pivot != 0 && o.pivot != 1) || o.nb < 32 ||
         o.nb % 32 != 0 || (o.prec == MXLU_PREC_FP8 && (o.nb % 128 != 0 || o.scale_tile < 4 ||
                                                        o.scale_tile > 256 || o.scale_tile % 4)) ||
         (o.prec == MXLU_PREC_FP8_MX && o.nb % 128 != 0) ||
+        (o.prec == MXLU_PREC_FP32 && o.trans != 0) ||
         (o.refine != MXLU_IR_CLASSICAL && o.refine != MXLU_IR_GMRES) || o.restart < 1 ||
         o.restart > 255 || o.max_outer < 0 || o.max_inner_total < 0 || o.trans < 0 ||
         o.trans > 1 || o.factor_steps < 0)
@@ -422,13 +504,19 @@ int mxp_impl(int64_t n, int64_t nrhs, const ASource &src, const double *B, int64
     const mxp_opts &o = *opts;
     (void)work_bytes;
     const int fmt = (o.prec == MXLU_PREC_BF16) ? kFmtBf16 : kFmtFp16;
+    const bool f32 = o.prec == MXLU_PREC_FP32;
     const int64_t ldf = factor_ld(n);
     uint16_t *F = reinterpret_cast<uint16_t *>(work);
+    float *F32 = reinterpret_cast<float *>(work);
 
     double t_conv = 0.0, t_fact = 0.0;
     int info = 0;
-    if (!o.reuse_factors)
-        MXLU_TRY(lp_factorize(o, n, src, F, ldf, ipiv, &info, s, &t_conv, &t_fact));
+    if (!o.reuse_factors) {
+        if (f32)
+            MXLU_TRY(lp_factorize_f32(o, n, src, F32, ldf, ipiv, &info, s, &t_conv, &t_fact));
+        else
+            MXLU_TRY(lp_factorize(o, n, src, F, ldf, ipiv, &info, s, &t_conv, &t_fact));
+    }
 
     Scratch scratch(s);
     RefineCtx c;
@@ -438,6 +526,7 @@ int mxp_impl(int64_t n, int64_t nrhs, const ASource &src, const double *B, int64
     c.ldf = ldf;
     c.src = src;
     c.F = F;
+    c.F32 = f32 ? F32 : nullptr;
     c.perm = nullptr;
     if (o.pivot) {
         int32_t *perm = scratch.alloc_n<int32_t>((size_t)n);

@@ -43,5 +43,9 @@ struct TrsvChain {
 int lp_precond_apply(int fmt, int trans, int64_t n, const uint16_t *F, int64_t ldf,
                      const int32_t *perm, const double *r, double *d, float *v32,
                      unsigned long long *smax, TrsvChain &ch, hipStream_t s);
+// d = M r with M = U^-1 L^-1 P from FP32 factors (FP32 storage; forward only).
+int lp_precond_apply_f32(int64_t n, const float *F, int64_t ldf, const int32_t *perm,
+                         const double *r, double *d, float *v32, unsigned long long *smax,
+                         hipStream_t s);
 
 }  // namespace mxlu

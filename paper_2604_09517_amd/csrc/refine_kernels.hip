@@ -3,6 +3,8 @@
 // preconditioner M = U^-1 L^-1 P applied in FP32 to the low-precision factors.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "asource.h"
 #include "common.h"
 #include "lp_common.h"
@@ -499,6 +501,73 @@ __global__ __launch_bounds__(256) void trsv_chain_kernel(int64_t n, const uint16
 
 unsigned g1(int64_t n) { return (unsigned)((n + 255) / 256); }
 
+// FP32-storage preconditioner: the factors are FP32 numbers, solved block by
+// block (kTrsv32Bs rows) in solve order with two launches per block: one
+// workgroup solves the diagonal block (its rows staged in LDS, thread = row,
+// each finished value broadcast through LDS), then a grid applies the block's
+// solution to the rows still to be solved (thread = row, the block's values in
+// LDS, the factor streamed column by column).  Every element takes its terms in
+// the order of the column-oriented substitution: ascending k for L, descending
+// k for U (then the division by the diagonal), one fused multiply-add each.
+constexpr int kTrsv32Bs = 128;
+
+template <bool LOWER>
+__global__ __launch_bounds__(kTrsv32Bs) void trsv_f32_diag_kernel(const float *__restrict__ F,
+                                                                  int64_t ldf, int64_t b0,
+                                                                  int rows, float *__restrict__ v) {
+    __shared__ float Ld[kTrsv32Bs][kTrsv32Bs + 1];
+    __shared__ float xk[2];
+    const int t = threadIdx.x;
+    for (int c = 0; c < rows; ++c)
+        if (t < rows) Ld[t][c] = F[(size_t)(b0 + t) + (size_t)(b0 + c) * ldf];
+    __syncthreads();
+    float x = t < rows ? v[b0 + t] : 0.0f;
+    // slot k & 1 is rewritten at step k + 2, after every thread has passed the
+    // barrier of step k + 1 and so has read it at step k
+    if constexpr (LOWER) {
+        for (int k = 0; k < rows; ++k) {
+            if (t == k) xk[k & 1] = x;
+            __syncthreads();
+            const float xv = xk[k & 1];
+            if (t > k && t < rows) x = fmaf(-Ld[t][k], xv, x);
+        }
+    } else {
+        for (int k = rows - 1; k >= 0; --k) {
+            if (t == k) {
+                x = x / Ld[k][k];
+                xk[k & 1] = x;
+            }
+            __syncthreads();
+            const float xv = xk[k & 1];
+            if (t < k) x = fmaf(-Ld[t][k], xv, x);
+        }
+    }
+    if (t < rows) v[b0 + t] = x;
+}
+
+// rows i >= b0 + rows (LOWER) or i < b0 (upper): v_i -= sum over the block
+template <bool LOWER>
+__global__ __launch_bounds__(256) void trsv_f32_apply_kernel(int64_t n, const float *__restrict__ F,
+                                                             int64_t ldf, int64_t b0, int rows,
+                                                             float *__restrict__ v) {
+    __shared__ float xb[kTrsv32Bs];
+    const int t = threadIdx.x;
+    if (t < rows) xb[t] = v[b0 + t];
+    __syncthreads();
+    const int64_t i = (LOWER ? b0 + rows : 0) + (int64_t)blockIdx.x * 256 + t;
+    if (i >= (LOWER ? n : b0)) return;
+    float x = v[i];
+    if constexpr (LOWER) {
+#pragma unroll 16
+        for (int k = 0; k < rows; ++k) x = fmaf(-F[(size_t)i + (size_t)(b0 + k) * ldf], xb[k], x);
+    } else {
+#pragma unroll 16
+        for (int k = rows - 1; k >= 0; --k)
+            x = fmaf(-F[(size_t)i + (size_t)(b0 + k) * ldf], xb[k], x);
+    }
+    v[i] = x;
+}
+
 }  // namespace
 
 namespace mxlu {
@@ -590,6 +659,43 @@ static int trsv_run(int64_t n, const uint16_t *F, int64_t ldf, float *v, TrsvCha
     const uint32_t tag = ++ch.tag;
     hipLaunchKernelGGL((trsv_chain_kernel<FMT, KIND>), dim3((unsigned)nblk), dim3(256), 0, s, n, F,
                        ldf, v, ch.xs, tag, (int)nblk, ch.expired);
+    MXLU_LAUNCH_CHECK();
+    return 0;
+}
+
+int lp_precond_apply_f32(int64_t n, const float *F, int64_t ldf, const int32_t *perm,
+                         const double *r, double *d, float *v32, unsigned long long *smax,
+                         hipStream_t s) {
+    if (n <= 0) return 0;
+    MXLU_HIP_TRY(hipMemsetAsync(smax, 0, sizeof(unsigned long long), s));
+    MXLU_TRY(absmax_f64(n, r, smax, s));
+    hipLaunchKernelGGL(precond_in_kernel, dim3(g1(n)), dim3(256), 0, s, n, r, perm, smax, v32);
+    MXLU_LAUNCH_CHECK();
+    for (int64_t b0 = 0; b0 < n; b0 += kTrsv32Bs) {   // L, forward
+        const int rows = (int)std::min<int64_t>(kTrsv32Bs, n - b0);
+        hipLaunchKernelGGL(trsv_f32_diag_kernel<true>, dim3(1), dim3(kTrsv32Bs), 0, s, F, ldf, b0,
+                           rows, v32);
+        MXLU_LAUNCH_CHECK();
+        const int64_t below = n - b0 - rows;
+        if (below > 0) {
+            hipLaunchKernelGGL(trsv_f32_apply_kernel<true>, dim3((unsigned)((below + 255) / 256)),
+                               dim3(256), 0, s, n, F, ldf, b0, rows, v32);
+            MXLU_LAUNCH_CHECK();
+        }
+    }
+    for (int64_t b0 = (n - 1) / kTrsv32Bs * kTrsv32Bs; b0 >= 0; b0 -= kTrsv32Bs) {   // U, backward
+        const int rows = (int)std::min<int64_t>(kTrsv32Bs, n - b0);
+        hipLaunchKernelGGL(trsv_f32_diag_kernel<false>, dim3(1), dim3(kTrsv32Bs), 0, s, F, ldf, b0,
+                           rows, v32);
+        MXLU_LAUNCH_CHECK();
+        if (b0 > 0) {
+            hipLaunchKernelGGL(trsv_f32_apply_kernel<false>, dim3((unsigned)((b0 + 255) / 256)),
+                               dim3(256), 0, s, n, F, ldf, b0, rows, v32);
+            MXLU_LAUNCH_CHECK();
+        }
+    }
+    hipLaunchKernelGGL(precond_out_kernel, dim3(g1(n)), dim3(256), 0, s, n, v32, nullptr, smax,
+                       d);
     MXLU_LAUNCH_CHECK();
     return 0;
 }

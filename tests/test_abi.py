@@ -106,6 +106,17 @@ def test_mxp_options_and_workspace(L):
     bad.factor_steps = 0                           # workspace too small
     assert L.mxp_solve(64, 1, p, 64, p, 64, p, 64, p, 16, None, ctypes.byref(bad),
                        ctypes.byref(rep), None) == -1006
+    bad.prec = 5                                   # no such precision
+    assert L.mxp_solve(64, 1, p, 64, p, 64, p, 64, p, 1 << 20, None, ctypes.byref(bad),
+                       ctypes.byref(rep), None) == -12
+    bad.prec = 4                                   # FP32 storage: forward solves only
+    bad.trans = 1
+    assert L.mxp_solve(64, 1, p, 64, p, 64, p, 64, p, 1 << 20, None, ctypes.byref(bad),
+                       ctypes.byref(rep), None) == -12
+    bad.trans = 0
+    # FP32 storage holds 4 bytes per factor value
+    assert L.mxp_workspace_bytes(1000, 1000, ctypes.byref(bad)) >= 4 * ldf * 1000
+    assert L.mxp_convert(4, 8, 8, p, 8, p, 8, None) == -1   # not a 16-bit format
 
 
 def test_seeded_solve_argument_checks(L):

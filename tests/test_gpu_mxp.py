@@ -30,8 +30,9 @@ from paper_2604_09517_amd import inputs
 
 pytestmark = pytest.mark.gpu
 EPS = 2.0 ** -53
-U_LP = {"bf16": 2.0 ** -8, "fp16": 2.0 ** -11, "fp8": 2.0 ** -4, "fp8_mx": 2.0 ** -4}
-PREC_ID = {"bf16": 0, "fp16": 1, "fp8": 2, "fp8_mx": 3}
+U_LP = {"bf16": 2.0 ** -8, "fp16": 2.0 ** -11, "fp8": 2.0 ** -4, "fp8_mx": 2.0 ** -4,
+        "fp32": 2.0 ** -24}
+PREC_ID = {"bf16": 0, "fp16": 1, "fp8": 2, "fp8_mx": 3, "fp32": 4}
 
 
 @pytest.fixture(scope="module")
@@ -444,7 +445,8 @@ def test_mxp_pivoted_solve_uniform_matrix(api, n, nb):
 
 @pytest.mark.parametrize("prec,n,nb,pivot,dominant,trans", [
     ("bf16", 1500, 128, False, True, 0), ("fp8", 1100, 128, False, True, 0),
-    ("bf16", 900, 64, False, True, 1), ("bf16", 700, 64, True, False, 0)])
+    ("bf16", 900, 64, False, True, 1), ("bf16", 700, 64, True, False, 0),
+    ("fp32", 800, 64, False, True, 0)])
 def test_seeded_solve_equals_stored_matrix(api, prec, n, nb, pivot, dominant, trans):
     """mxp_solve_seeded regenerates A from its counter in the conversion and
     in every FP64 residual; the operations and their order are those of
@@ -474,3 +476,80 @@ def test_seeded_solve_equals_stored_matrix(api, prec, n, nb, pivot, dominant, tr
     assert torch.equal(X1, X2)
     rho = api.scaled_residual(A, X2, b, trans=bool(trans))[0]
     assert rho < 16
+
+
+@pytest.mark.parametrize("n,nb,pivot", [(300, 64, False), (700, 128, False), (1100, 256, False),
+                                        (520, 64, True), (900, 128, True)])
+def test_fp32_storage_factors_bitwise(api, n, nb, pivot):
+    """FP32 factor storage: panel, TRSM and trailing update take the oracle's
+    operations in the oracle's order (one fused multiply-add per term, k
+    ascending, nothing rounded to a narrower format), so the whole
+    factorization -- and with pivoting every interchange -- is bit for bit
+    the oracle's.  Pivoted cases use the uniform (not dominant) matrix."""
+    note(f"fp32 storage n={n} nb={nb} pivot={pivot}")
+    seed = 91 + n
+    A = (inputs.uniform_matrix(seed, 0, n, n) if pivot
+         else inputs.diag_dominant_matrix(seed, 0, n))
+    b = inputs.uniform_matrix(seed, 1, n, 1)[:, 0]
+    dA, db = to_dev(A), to_dev(b)
+    X, rep, work, ipiv = api.mxp_solve(dA, db, prec="fp32", nb=nb, pivot=pivot, max_outer=0,
+                                       allow_notconv=True)
+    torch.cuda.synchronize()
+    F = factors_to_host(api, work, n, "fp32")
+    F_ref, ipiv_ref, info = oracle.lp_getrf(A, nb, 4, pivot=pivot)
+    assert rep["info"] == info == 0
+    if pivot:
+        assert np.array_equal(ipiv.cpu().numpy(), ipiv_ref)
+    assert np.array_equal(F, F_ref)
+
+
+@pytest.mark.parametrize("pivot", [False, True])
+def test_fp32_storage_preconditioner_bitwise(api, pivot):
+    """x0 = M b from FP32 factors: the block solves take every term in the
+    substitution's order (k ascending for L, descending for U, then the
+    division), so x0 equals the oracle's preconditioner bit for bit."""
+    n, nb = 650, 64
+    A = (inputs.uniform_matrix(83, 0, n, n) if pivot else inputs.diag_dominant_matrix(83, 0, n))
+    b = inputs.uniform_matrix(83, 1, n, 1)[:, 0]
+    F_ref, ipiv_ref, _ = oracle.lp_getrf(A, nb, 4, pivot=pivot)
+    dA, db = to_dev(A), to_dev(b)
+    opts = api.mxp_options(prec="fp32", nb=nb, pivot=pivot, max_outer=0, reuse_factors=True)
+    work = torch.zeros(api.mxp_workspace_bytes(n, opts, n), dtype=torch.uint8, device="cuda")
+    api.mxp_factors(work, n, "fp32").copy_(torch.from_numpy(F_ref).to(torch.float32))
+    ipiv = torch.from_numpy(ipiv_ref.astype(np.int32)).cuda() if pivot else None
+    X, rep, _, _ = api.mxp_solve(dA, db, work=work, ipiv=ipiv, opts=opts, allow_notconv=True)
+    torch.cuda.synchronize()
+    ref = oracle.lp_precond(F_ref, ipiv_ref if pivot else None, b)
+    assert np.array_equal(X.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("method,pivot,n,nb", [("gmres", False, 1024, 128),
+                                               ("classical", False, 700, 64),
+                                               ("gmres", True, 900, 128)])
+def test_fp32_storage_solve(api, method, pivot, n, nb):
+    """FP32 storage through refinement: converged below the threshold, outer
+    iterations as the oracle refinement's on the oracle's factors."""
+    seed = inputs.config_seed(2) + n
+    A = (inputs.uniform_matrix(seed, 0, n, n) if pivot
+         else inputs.diag_dominant_matrix(seed, 0, n))
+    b = inputs.uniform_matrix(seed, 1, n, 1)[:, 0]
+    dA, db = to_dev(A), to_dev(b)
+    X, rep, _, _ = api.mxp_solve(dA, db, prec="fp32", nb=nb, pivot=pivot, refine=method)
+    torch.cuda.synchronize()
+    x = X.cpu().numpy()
+    rho = checks.scaled_residual(A, x, b)
+    F_ref, ipiv_ref, _ = oracle.lp_getrf(A, nb, 4, pivot=pivot)
+    out = refine.refine(A, b, F_ref, ipiv_ref if pivot else None, method=method)
+    note(f"fp32 storage {method} pivot={pivot} n={n}: outer {rep['outer_iters']} "
+         f"(oracle {out['outer_iters']}), inner {rep['inner_iters']} "
+         f"(oracle {out['inner_iters']}), rho {rho:.2f}")
+    assert rep["converged"] == 1 and out["converged"] and rho < 16
+    assert abs(rep["outer_iters"] - out["outer_iters"]) <= 1
+
+
+def test_fp32_storage_rejects_transposed_solve(api):
+    n = 128
+    A = inputs.diag_dominant_matrix(3, 0, n)
+    b = inputs.uniform_matrix(3, 1, n, 1)[:, 0]
+    with pytest.raises(ValueError, match="argument 12"):   # the options
+        api.mxp_solve(to_dev(A), to_dev(b), prec="fp32", nb=64, trans=True)
