@@ -324,10 +324,8 @@ def run_mxp(args, cfg, name, steps, warmup):
     del A, X, b, x_ref
     torch.cuda.empty_cache()
     prec_id = 0 if prec == "bf16" else 2
-    # the oracle's BF16 solve is the slower one per flop (39 s at N = 4096):
-    # a smaller sample keeps the default run within minutes
-    n_sample = 3072 if prec == "bf16" else 4096
-    return out, (lambda: cpu_baseline_mxp(cfg, seed, prec_id, n_sample))
+    # about 16 s of host work for either leg
+    return out, (lambda: cpu_baseline_mxp(cfg, seed, prec_id, 6144))
 
 
 # ---------------------------------------------------------------- phase model
