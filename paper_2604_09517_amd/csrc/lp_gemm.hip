@@ -85,6 +85,29 @@ static_assert(TM == kLpTileM && TN == kLpTileN, "tile and packing must agree");
 typedef __attribute__((address_space(1))) void gvoid_t;
 typedef __attribute__((address_space(3))) void lvoid_t;
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+
+// 16 bytes of the C tile, optionally as streaming (non-temporal) accesses:
+// each C element is touched once per update, and keeping it out of the caches
+// leaves them to the operand panels that every tile of a tile row or column
+// reads again.  Measured: the FP8 update gains with both (11.1 -> 9.5-9.9 ms
+// per launch at N = 131072, NB = 1024; loads or stores alone are slower than
+// neither), the 16-bit update loses with any (2.29 -> 2.34-2.43 ms at
+// N = 65536, NB = 512), so it keeps ordinary accesses.
+template <bool NT>
+__device__ __forceinline__ uint4 c_load(const uint16_t *p) {
+    if constexpr (!NT) return *reinterpret_cast<const uint4 *>(p);
+    const v4u v = __builtin_nontemporal_load(reinterpret_cast<const v4u *>(p));
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+template <bool NT>
+__device__ __forceinline__ void c_store(uint16_t *p, uint4 v) {
+    if constexpr (!NT) {
+        *reinterpret_cast<uint4 *>(p) = v;
+        return;
+    }
+    __builtin_nontemporal_store(v4u{v.x, v.y, v.z, v.w}, reinterpret_cast<v4u *>(p));
+}
 
 // LDS byte address of a pointer into a __shared__ array
 __device__ __forceinline__ uint32_t lds_addr(const void *p) {
@@ -172,7 +195,7 @@ __device__ __forceinline__ uint4 neg16(uint4 v) {   // flip the sign bit of 8 16
     return v;
 }
 
-template <int FMT>
+template <int FMT, bool NTL = false, bool NTS = false>
 __global__ __launch_bounds__(256, 2) void lp_schur16_kernel(
     int64_t M, int64_t N, int K, const uint16_t *__restrict__ Lp, int64_t Mp,
     const uint16_t *__restrict__ Up, int64_t Np, uint16_t *__restrict__ C, int64_t ldc,
@@ -206,7 +229,7 @@ __global__ __launch_bounds__(256, 2) void lp_schur16_kernel(
             for (int bj = 0; bj < 4; ++bj) {
                 const int64_t r8 = row0 + wm * 128 + 32 * pr + 8 * lg;
                 const int64_t c = col0 + wn * 64 + bj * 16 + li;
-                const uint4 v = *reinterpret_cast<const uint4 *>(&C[(size_t)r8 + (size_t)c * ldc]);
+                const uint4 v = c_load<NTL>(&C[(size_t)r8 + (size_t)c * ldc]);
                 const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
@@ -313,8 +336,7 @@ __global__ __launch_bounds__(256, 2) void lp_schur16_kernel(
                 for (int r = 0; r < 4; ++r)
                     w4[r] = (uint32_t)f32_to_lp<FMT>(acc[2 * pr][bj][r]) |
                             ((uint32_t)f32_to_lp<FMT>(acc[2 * pr + 1][bj][r]) << 16);
-                *reinterpret_cast<uint4 *>(&C[(size_t)r8 + (size_t)c * ldc]) =
-                    make_uint4(w4[0], w4[1], w4[2], w4[3]);
+                c_store<NTS>(&C[(size_t)r8 + (size_t)c * ldc], make_uint4(w4[0], w4[1], w4[2], w4[3]));
             }
     } else {
 #pragma unroll
@@ -359,7 +381,7 @@ __device__ __forceinline__ void wait_vmcnt() {
 // row (column), the operand bytes being placed so that the matrix cores' k
 // is the chunk's k (bytes 0-15 of a lane from k 16 lg, bytes 16-31 from
 // k 64 + 16 lg); the epilogue is then C - acc.
-template <int FMT, int NS, bool MX>
+template <int FMT, int NS, bool MX, bool NTL = true, bool NTS = true>
 __global__ __launch_bounds__(256, NS <= 2 ? 2 : 1) void lp_schur8_kernel(
     int64_t M, int64_t N, int K, const uint8_t *__restrict__ Lq, int64_t Mp,
     const float *__restrict__ sL, const uint8_t *__restrict__ Uq, int64_t Np,
@@ -462,7 +484,7 @@ __global__ __launch_bounds__(256, NS <= 2 ? 2 : 1) void lp_schur8_kernel(
             for (int bj = 0; bj < 4; ++bj) {
                 const int64_t r8 = row0 + wm * 64 + 32 * pr + 8 * lg;
                 const int64_t c = col0 + wn * 64 + bj * 16 + li;
-                cv[pr][bj] = *reinterpret_cast<const uint4 *>(&C[(size_t)r8 + (size_t)c * ldc]);
+                cv[pr][bj] = c_load<NTL>(&C[(size_t)r8 + (size_t)c * ldc]);
             }
     }
 #pragma unroll
@@ -539,8 +561,7 @@ __global__ __launch_bounds__(256, NS <= 2 ? 2 : 1) void lp_schur8_kernel(
                         lp_to_f32<FMT>((uint16_t)(c4[r] >> 16)) - acc[2 * pr + 1][bj][r] * sc;
                     w4[r] = (uint32_t)f32_to_lp<FMT>(lo) | ((uint32_t)f32_to_lp<FMT>(hi) << 16);
                 }
-                *reinterpret_cast<uint4 *>(&C[(size_t)r8 + (size_t)c * ldc]) =
-                    make_uint4(w4[0], w4[1], w4[2], w4[3]);
+                c_store<NTS>(&C[(size_t)r8 + (size_t)c * ldc], make_uint4(w4[0], w4[1], w4[2], w4[3]));
             }
     } else {
 #pragma unroll
