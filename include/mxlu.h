@@ -108,6 +108,16 @@ int mxlu_release(void);
 int mxlu_debug_expire_waits(int on);
 
 /*
+ * mxlu_debug_poison_scratch -- test hook, process-wide (-1 = off, the
+ * default): when 0..255, every scratch buffer the library allocates for a
+ * call is first filled with that byte on the call's stream, so that tests can
+ * show that no result depends on what the memory held before (the results
+ * with 0x00 and with 0xFF, a NaN pattern, must be the same bit for bit).
+ * Returns 0, or -1 for a value outside [-1, 255].
+ */
+int mxlu_debug_poison_scratch(int byte);
+
+/*
  * lu_solve -- triangular solves with the factors of lu_factor (Sec. III-A.1).
  *   trans = 0: solves A X = B  (apply P, L y = P b, U x = y)
  *   trans = 1: solves A^T X = B (U^T y = b, L^T z = y, x = P^T z)

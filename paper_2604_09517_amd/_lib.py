@@ -44,6 +44,7 @@ SIGNATURES = {
     "mxlu_set_lookahead": (_int, [_int]),
     "mxlu_release": (_int, []),
     "mxlu_debug_expire_waits": (_int, [_int]),
+    "mxlu_debug_poison_scratch": (_int, [_int]),
     "mxlu_panel_factor_f64": (_int, [_i64, _i64, _vp, _i64, _vp, _vp]),
     "mxlu_plan_panel_cus": (_int, [_int]),
     "mxlu_plan_panel_leaf": (_int, [_i64, _int, _int, _int, _int, _i64, _int,

@@ -106,6 +106,12 @@ def debug_expire_waits(on):
     check("mxlu_debug_expire_waits", lib().mxlu_debug_expire_waits(1 if on else 0))
 
 
+def debug_poison_scratch(byte):
+    """Test hook: every scratch buffer starts filled with `byte` (None: off)."""
+    check("mxlu_debug_poison_scratch",
+          lib().mxlu_debug_poison_scratch(-1 if byte is None else int(byte)))
+
+
 def lu_solve(LU, ipiv, B, trans=False):
     """In-place solve A X = B (or A^T X = B) with the factors of lu_factor."""
     pl, n, _, lda = _mat(LU, "LU")

@@ -1,12 +1,16 @@
 // Status strings, error recording and stream-ordered scratch memory.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdio>
 #include <cstring>
 
 #include "common.h"
 
 namespace mxlu {
+
+// Test hook: byte value every new scratch buffer is filled with (-1: none).
+static std::atomic<int> g_poison_scratch{-1};
 
 static thread_local char g_last_error[512] = "";
 
@@ -52,10 +56,21 @@ void *Scratch::alloc(size_t bytes) {
         return nullptr;
     }
     ptrs_[count_++] = p;
+    const int poison = g_poison_scratch.load();
+    if (poison >= 0 && hipMemsetAsync(p, poison, bytes ? bytes : 16, stream_) != hipSuccess) {
+        set_error("hipMemsetAsync", hipGetLastError());
+        return nullptr;
+    }
     return p;
 }
 
 }  // namespace mxlu
+
+extern "C" int mxlu_debug_poison_scratch(int byte) {
+    if (byte < -1 || byte > 255) return -1;
+    mxlu::g_poison_scratch.store(byte);
+    return 0;
+}
 
 extern "C" const char *mxlu_status_string(int status) {
     switch (status) {

@@ -423,3 +423,34 @@ def test_release_then_factor_again(api):
     api.profile_enable(False)
     _, piv_ref, _ = oracle.getrf(A_h, nb)
     assert info == 0 and np.array_equal(ipiv.cpu().numpy(), piv_ref)
+
+
+@pytest.mark.parametrize("lookahead", [0, 1])
+def test_results_independent_of_scratch_contents(api, lookahead):
+    """Determinism: the factorization and the solve on scratch memory that
+    starts as zeros and on scratch that starts as NaN bytes (0xFF) give the
+    same pivots, factors and solution bit for bit: no uninitialised scratch
+    reaches a result."""
+    n, nb = 2304, 128
+    seed = 4242
+    A0 = api.fortran_empty(n, n)
+    api.fill_uniform(A0, seed, inputs.STREAM_A)
+    b0 = torch.from_numpy(inputs.uniform_matrix(seed, inputs.STREAM_B, n, 1)[:, 0]).cuda()
+    api.set_lookahead(lookahead)
+    try:
+        out = []
+        for byte in (0x00, 0xFF):
+            api.debug_poison_scratch(byte)   # every scratch buffer starts as `byte`
+            A = A0.clone()
+            b = b0.clone()
+            ipiv0 = torch.full((n,), -7, dtype=torch.int32, device="cuda")
+            LU, ipiv, _ = api.lu_factor(A, nb=nb, ipiv=ipiv0)
+            x = api.lu_solve(LU, ipiv, b)
+            torch.cuda.synchronize()
+            out.append((LU.cpu(), ipiv.cpu(), x.cpu()))
+    finally:
+        api.set_lookahead(1)
+        api.debug_poison_scratch(None)
+    assert torch.equal(out[0][1], out[1][1])
+    assert torch.equal(out[0][0], out[1][0])
+    assert torch.equal(out[0][2], out[1][2])

@@ -553,3 +553,40 @@ def test_fp32_storage_rejects_transposed_solve(api):
     b = inputs.uniform_matrix(3, 1, n, 1)[:, 0]
     with pytest.raises(ValueError, match="argument 12"):   # the options
         api.mxp_solve(to_dev(A), to_dev(b), prec="fp32", nb=64, trans=True)
+
+
+@pytest.mark.parametrize("prec,pivot", [("bf16", False), ("fp8", False), ("fp8_mx", False),
+                                        ("bf16", True), ("fp32", False)])
+def test_mxp_results_independent_of_workspace_contents(api, prec, pivot):
+    """Determinism: the caller's workspace and the library's scratch starting
+    as zeros or as NaN bytes (0xFF) give the same factors, pivots, solution
+    and iteration counts bit for bit."""
+    n, nb = 1100, 128 if prec.startswith("fp8") else 64
+    seed = 777 + n
+    A = (inputs.uniform_matrix(seed, 0, n, n) if pivot
+         else inputs.diag_dominant_matrix(seed, 0, n))
+    b = inputs.uniform_matrix(seed, 1, n, 1)[:, 0]
+    dA, db = to_dev(A), to_dev(b)
+    opts = api.mxp_options(prec=prec, nb=nb, pivot=pivot, restart=60)
+    res = []
+    try:
+        for byte in (0x00, 0xFF):
+            api.debug_poison_scratch(byte)   # every scratch buffer starts as `byte`
+            work = torch.empty(api.mxp_workspace_bytes(n, opts, n), dtype=torch.uint8,
+                               device="cuda")
+            work.fill_(byte)
+            X = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+            ipiv = torch.full((n,), -7, dtype=torch.int32, device="cuda") if pivot else None
+            X, rep, work, ipiv = api.mxp_solve(dA, db, X=X, work=work, ipiv=ipiv, opts=opts)
+            torch.cuda.synchronize()
+            res.append((api.mxp_factors(work, n, prec).cpu().clone(), X.cpu(),
+                        None if ipiv is None else ipiv.cpu(), rep["outer_iters"],
+                        rep["inner_iters"]))
+    finally:
+        api.debug_poison_scratch(None)
+    assert torch.equal(res[0][0].view(torch.int16 if prec != "fp32" else torch.int32),
+                       res[1][0].view(torch.int16 if prec != "fp32" else torch.int32))
+    assert torch.equal(res[0][1], res[1][1])
+    if pivot:
+        assert torch.equal(res[0][2], res[1][2])
+    assert res[0][3:] == res[1][3:]
