@@ -74,6 +74,12 @@ int panel_leaf(int64_t m, int w, T *P, int64_t ldp, int64_t r0, int32_t *ipiv,
 // matrix of T.  An interchange row outside [j0 + t, nrows) counts as none.
 int swap_compose(const int32_t *ipiv, int64_t j0, int cnt, int64_t nrows, int *moves,
                  hipStream_t s);
+// The interchanges of every step applied to the columns left of its panel,
+// deferred to after the factorization (each element moves once).  q, r: n
+// ints of scratch; T: (n - nb) x nb doubles of scratch.
+int laswp_left_deferred_f64(double *A, int64_t lda, int64_t n, int64_t nb,
+                            const int32_t *ipiv, int *moves, int32_t *q, int32_t *r, double *T,
+                            hipStream_t s);
 template <typename T>
 int swap_apply(T *A, int64_t lda, int64_t j0, const int *moves, int64_t c_begin, int64_t ncols,
                int64_t skip_begin, int64_t skip_len, hipStream_t s);

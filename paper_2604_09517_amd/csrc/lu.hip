@@ -314,6 +314,12 @@ int factor_impl(int64_t n, int64_t nb, double *A, int64_t lda, int32_t *ipiv, hi
     const int64_t ldbn = (n + 1) / 2 * 2;
     double *Bn = scratch.alloc_n<double>((size_t)nb * (size_t)ldbn);
     if (!Bn) return MXLU_E_NOMEM;
+    // the deferred interchanges left of the panels: two row maps and one
+    // panel's rows below it
+    int32_t *perm_q = scratch.alloc_n<int32_t>((size_t)n);
+    int32_t *perm_r = scratch.alloc_n<int32_t>((size_t)n);
+    double *rowsT = n > nb ? scratch.alloc_n<double>((size_t)(n - nb) * (size_t)nb) : nullptr;
+    if (!perm_q || !perm_r || (n > nb && !rowsT)) return MXLU_E_NOMEM;
 
     const OverlapStreams *ov =
         g_lookahead.load() > 0 ? overlap_streams() : nullptr;
@@ -340,9 +346,9 @@ int factor_impl(int64_t n, int64_t nb, double *A, int64_t lda, int32_t *ipiv, hi
                                      s));
         }
         ahead = false;
-        {   // SWAP on the columns left and right of the panel
-            PhaseScope ph(kPhaseSwap, s, 32.0 * kb * (double)(n - kb));
-            MXLU_TRY(laswp_f64(A, lda, n, ipiv, k0, (int)kb, 0, n - kb, k0, kb, moves, s));
+        if (c1 < n) {   // SWAP on the columns right of the panel (those left of it: below)
+            PhaseScope ph(kPhaseSwap, s, 32.0 * kb * (double)(n - c1));
+            MXLU_TRY(laswp_f64(A, lda, n, ipiv, k0, (int)kb, c1, n - c1, c1, 0, moves, s));
         }
         if (c1 >= n) continue;
         const int64_t nt = n - c1;
@@ -399,6 +405,11 @@ int factor_impl(int64_t n, int64_t nb, double *A, int64_t lda, int32_t *ipiv, hi
         ahead = true;
     }
     profile_set_step(-1);
+    {   // the interchanges of every step on the L columns left of its panel,
+        // applied once now that no step reads those columns any more
+        PhaseScope ph(kPhaseSwap, s, 32.0 * (double)n * (double)n / 2.0);
+        MXLU_TRY(laswp_left_deferred_f64(A, lda, n, nb, ipiv, moves, perm_q, perm_r, rowsT, s));
+    }
     int flags[4] = {0, 0, 0, 0};
     MXLU_HIP_TRY(hipMemcpyAsync(flags, ex.flags, sizeof(flags), hipMemcpyDeviceToHost, s));
     MXLU_HIP_TRY(hipStreamSynchronize(s));

@@ -137,6 +137,53 @@ __global__ __launch_bounds__(256) void swap_apply_kernel(T *__restrict__ A, int6
 }
 
 // ---------------------------------------------------------------------------
+// Deferred interchanges of the columns left of the panels.  No later step
+// reads the L columns of a finished panel, so their row interchanges can wait
+// until the factorization is done; then each element moves once.  Panel j's
+// rows below it end up gathered through q_j = r_{j+1} o ... o r_{K-1}, the
+// composition of the gather maps of the later steps' interchanges (r_s(i) is
+// the row whose content step s moves to row i: the identity but for the
+// moves of step s).  q is built from the last step backwards.
+__global__ void perm_iota_kernel(int64_t n, int32_t *__restrict__ q) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) q[i] = (int32_t)i;
+}
+
+// r at the moved rows of one step: their sources (set) or themselves (reset)
+__global__ void perm_moves_kernel(const int *__restrict__ moves, int64_t j0,
+                                  int32_t *__restrict__ r, int reset) {
+    const int nm = moves[0];
+    for (int t = threadIdx.x; t < nm; t += 256) {
+        const int d = moves[1 + t];
+        r[j0 + d] = (int32_t)(j0 + (reset ? d : moves[1 + 2 * kMaxSwaps + t]));
+    }
+}
+
+// q[i] <- r[q[i]] for rows [i0, n)
+__global__ void perm_compose_kernel(int64_t i0, int64_t n, const int32_t *__restrict__ r,
+                                    int32_t *__restrict__ q) {
+    const int64_t i = i0 + (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) q[i] = r[q[i]];
+}
+
+// T (rows x cols, leading dimension rows) <- A[q[r0 + i], c0 + c]
+__global__ void gather_rows_kernel(const double *__restrict__ A, int64_t lda, int64_t r0,
+                                   int64_t rows, int64_t c0, const int32_t *__restrict__ q,
+                                   double *__restrict__ T) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t c = blockIdx.y;
+    if (i < rows) T[i + c * rows] = MXLU_AT(A, q[r0 + i], c0 + c, lda);
+}
+
+// A[r0 + i, c0 + c] <- T
+__global__ void put_rows_kernel(const double *__restrict__ T, int64_t rows, double *__restrict__ A,
+                                int64_t lda, int64_t r0, int64_t c0) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t c = blockIdx.y;
+    if (i < rows) MXLU_AT(A, r0 + i, c0 + c, lda) = T[i + c * rows];
+}
+
+// ---------------------------------------------------------------------------
 // DTRSM family, kb <= 256 rows: thread i owns row i of a strip of NC columns
 // of B in registers.  Step k broadcasts the finished row k through LDS (one
 // LDS barrier per k, double-buffered) and every row still to be solved takes
@@ -415,6 +462,40 @@ int laswp_f64(double *A, int64_t lda, int64_t nrows, const int32_t *ipiv, int64_
     if (cnt <= 0 || ncols <= 0) return 0;
     MXLU_TRY(swap_compose(ipiv, j0, cnt, nrows, moves, s));
     return swap_apply<double>(A, lda, j0, moves, c_begin, ncols, skip_begin, skip_len, s);
+}
+
+int laswp_left_deferred_f64(double *A, int64_t lda, int64_t n, int64_t nb,
+                            const int32_t *ipiv, int *moves, int32_t *q, int32_t *r, double *T,
+                            hipStream_t s) {
+    const int64_t K = (n + nb - 1) / nb;
+    if (K < 2) return 0;
+    const unsigned gn = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(perm_iota_kernel, dim3(gn), dim3(256), 0, s, n, q);
+    MXLU_LAUNCH_CHECK();
+    hipLaunchKernelGGL(perm_iota_kernel, dim3(gn), dim3(256), 0, s, n, r);
+    MXLU_LAUNCH_CHECK();
+    for (int64_t j = K - 2; j >= 0; --j) {
+        const int64_t j1 = (j + 1) * nb, kb1 = std::min(nb, n - j1);
+        // q <- r_{j+1} o q
+        MXLU_TRY(swap_compose(ipiv, j1, (int)kb1, n, moves, s));
+        hipLaunchKernelGGL(perm_moves_kernel, dim3(1), dim3(256), 0, s, moves, j1, r, 0);
+        MXLU_LAUNCH_CHECK();
+        const int64_t rows = n - j1;
+        const unsigned gr = (unsigned)((rows + 255) / 256);
+        hipLaunchKernelGGL(perm_compose_kernel, dim3(gr), dim3(256), 0, s, j1, n, r, q);
+        MXLU_LAUNCH_CHECK();
+        hipLaunchKernelGGL(perm_moves_kernel, dim3(1), dim3(256), 0, s, moves, j1, r, 1);
+        MXLU_LAUNCH_CHECK();
+        // panel j's columns, rows below it, gathered through q
+        const int64_t c0 = j * nb, cols = nb;
+        hipLaunchKernelGGL(gather_rows_kernel, dim3(gr, (unsigned)cols), dim3(256), 0, s, A, lda,
+                           j1, rows, c0, q, T);
+        MXLU_LAUNCH_CHECK();
+        hipLaunchKernelGGL(put_rows_kernel, dim3(gr, (unsigned)cols), dim3(256), 0, s, T, rows, A,
+                           lda, j1, c0);
+        MXLU_LAUNCH_CHECK();
+    }
+    return 0;
 }
 
 template <bool LOWER, bool UNIT, bool TRANS>
