@@ -77,6 +77,9 @@ int swap_compose(const int32_t *ipiv, int64_t j0, int cnt, int64_t nrows, int *m
 // The interchanges of every step applied to the columns left of its panel,
 // deferred to after the factorization (each element moves once).  q, r: n
 // ints of scratch; T: (n - nb) x nb doubles of scratch.
+// y -= A x (one right-hand side; A is M x K, column-major), deterministic.
+int gemv_f64_sub(int64_t M, int64_t K, const double *A, int64_t lda, const double *x, double *y,
+                 hipStream_t s);
 int laswp_left_deferred_f64(double *A, int64_t lda, int64_t n, int64_t nb,
                             const int32_t *ipiv, int *moves, int32_t *q, int32_t *r, double *T,
                             hipStream_t s);

@@ -552,7 +552,10 @@ int solve_impl(int64_t n, int64_t nrhs, const double *LU, int64_t lda, const int
                 else
                     MXLU_TRY(trsm_llnu_f64((int)bb, nr, &MXLU_AT(LU, b0, b0, lda), lda, Y + b0, ldy,
                                            s));
-                if (b0 + bb < n)
+                if (b0 + bb < n && nr == 1)
+                    MXLU_TRY(gemv_f64_sub(n - b0 - bb, bb, &MXLU_AT(LU, b0 + bb, b0, lda), lda, Y + b0,
+                                          Y + b0 + bb, s));
+                else if (b0 + bb < n)
                     MXLU_TRY(gemm_f64_sub(n - b0 - bb, nr, bb, &MXLU_AT(LU, b0 + bb, b0, lda), lda,
                                      Y + b0, ldy, Y + b0 + bb, ldy, s));
             }
@@ -565,7 +568,9 @@ int solve_impl(int64_t n, int64_t nrhs, const double *LU, int64_t lda, const int
                 else
                     MXLU_TRY(trsm_lunn_f64((int)bb, nr, &MXLU_AT(LU, b0, b0, lda), lda, Y + b0, ldy,
                                            s));
-                if (b0 > 0)
+                if (b0 > 0 && nr == 1)
+                    MXLU_TRY(gemv_f64_sub(b0, bb, &MXLU_AT(LU, 0, b0, lda), lda, Y + b0, Y, s));
+                else if (b0 > 0)
                     MXLU_TRY(gemm_f64_sub(b0, nr, bb, &MXLU_AT(LU, 0, b0, lda), lda, Y + b0, ldy, Y,
                                      ldy, s));
             }

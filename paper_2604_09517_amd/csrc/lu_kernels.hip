@@ -167,8 +167,8 @@ __global__ void perm_compose_kernel(int64_t i0, int64_t n, const int32_t *__rest
 }
 
 // T (rows x cols, leading dimension rows) <- A[q[r0 + i], c0 + c]
-__global__ void gather_rows_kernel(const double *__restrict__ A, int64_t lda, int64_t r0,
-                                   int64_t rows, int64_t c0, const int32_t *__restrict__ q,
+__global__ void gather_panel_rows_kernel(const double *__restrict__ A, int64_t lda, int64_t r0,
+                                         int64_t rows, int64_t c0, const int32_t *__restrict__ q,
                                    double *__restrict__ T) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t c = blockIdx.y;
@@ -176,11 +176,43 @@ __global__ void gather_rows_kernel(const double *__restrict__ A, int64_t lda, in
 }
 
 // A[r0 + i, c0 + c] <- T
-__global__ void put_rows_kernel(const double *__restrict__ T, int64_t rows, double *__restrict__ A,
+__global__ void put_panel_rows_kernel(const double *__restrict__ T, int64_t rows, double *__restrict__ A,
                                 int64_t lda, int64_t r0, int64_t c0) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t c = blockIdx.y;
     if (i < rows) MXLU_AT(A, r0 + i, c0 + c, lda) = T[i + c * rows];
+}
+
+// One right-hand side: y -= A x with A (M x K, K <= 256 per pass) streamed
+// by 64-row x 4-group workgroups: thread (r, g) sums the terms of its row over
+// the g-th quarter of the k range in ascending k; the four partial sums are
+// combined in a fixed order, so the result does not depend on timing.  Four
+// times the workgroups of a row-per-thread form, with each thread's loads
+// independent of its arithmetic.
+__global__ __launch_bounds__(256) void gemv_f64_sub_kernel(int64_t M, int64_t K,
+                                                           const double *__restrict__ A,
+                                                           int64_t lda,
+                                                           const double *__restrict__ x,
+                                                           double *__restrict__ y) {
+    __shared__ double xs[256];
+    __shared__ double part[4][64];
+    const int tid = threadIdx.x, r = tid & 63, g = tid >> 6;
+    const int64_t i = (int64_t)blockIdx.x * 64 + r;
+    double acc = 0.0;
+    for (int64_t k0 = 0; k0 < K; k0 += 256) {
+        const int kc = (int)((K - k0 < 256) ? K - k0 : 256);
+        __syncthreads();
+        if (tid < kc) xs[tid] = x[k0 + tid];
+        __syncthreads();
+        const int q = (kc + 3) / 4, ka = g * q, kz = (ka + q < kc) ? ka + q : kc;
+        if (i < M) {
+#pragma unroll 8
+            for (int k = ka; k < kz; ++k) acc = fma(MXLU_AT(A, i, k0 + k, lda), xs[k], acc);
+        }
+    }
+    part[g][r] = acc;
+    __syncthreads();
+    if (g == 0 && i < M) y[i] = y[i] - ((part[0][r] + part[1][r]) + (part[2][r] + part[3][r]));
 }
 
 // ---------------------------------------------------------------------------
@@ -295,27 +327,61 @@ __global__ __launch_bounds__(256) void gemm_tn_skinny_kernel(int64_t M, int N, i
 // Permutation of the solve: replay the n interchanges on an index array kept
 // in LDS when it fits, else in global memory.
 // ---------------------------------------------------------------------------
+// perm: the gather map of all interchanges of ipiv applied in order (row i of
+// P b is b[perm[i]]).  The interchanges are taken 256 at a time: those of a
+// block move only its own rows and rows below it, so each thread follows one
+// candidate row (a row of the block, or a pivot row below it where it first
+// appears) back through the block's interchanges to the row its content comes
+// from, and the block's moves are applied at once.  An entry outside
+// [j, n) is taken as no interchange, as in swap_compose.
 __global__ __launch_bounds__(256) void perm_from_ipiv_kernel(int64_t n,
                                                              const int32_t *__restrict__ ipiv,
                                                              int32_t *__restrict__ perm,
                                                              int in_lds) {
     extern __shared__ int sperm[];
+    __shared__ int s_piv[256];
     int *p = in_lds ? sperm : perm;
-    for (int64_t t = threadIdx.x; t < n; t += 256) p[t] = (int)t;
+    const int tid = threadIdx.x;
+    for (int64_t t = tid; t < n; t += 256) p[t] = (int)t;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int64_t j = 0; j < n; ++j) {
-            const int q = ipiv[j];
-            if (q != j) {
-                const int a = p[j];
-                p[j] = p[q];
-                p[q] = a;
+    for (int64_t j0 = 0; j0 < n; j0 += 256) {
+        const int cnt = (int)((n - j0 < 256) ? n - j0 : 256);
+        if (tid < cnt) {
+            const int64_t q = (int64_t)ipiv[j0 + tid] - j0;
+            s_piv[tid] = (q >= tid && q < n - j0) ? (int)q : tid;
+        }
+        __syncthreads();
+        int d[2] = {-1, -1}, v[2] = {0, 0};
+        if (tid < cnt) {
+            d[0] = tid;
+            const int q = s_piv[tid];
+            if (q >= cnt) {
+                d[1] = q;
+                for (int u = 0; u < tid; ++u)
+                    if (s_piv[u] == q) {
+                        d[1] = -1;
+                        break;
+                    }
             }
         }
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            if (d[e] < 0) continue;
+            int src = d[e];
+            for (int u = cnt - 1; u >= 0; --u) {
+                const int q = s_piv[u];
+                src = (src == u) ? q : ((src == q) ? u : src);
+            }
+            v[e] = p[j0 + src];
+        }
+        __syncthreads();   // every source read before any move is written
+#pragma unroll
+        for (int e = 0; e < 2; ++e)
+            if (d[e] >= 0) p[j0 + d[e]] = v[e];
+        __syncthreads();
     }
-    __syncthreads();
     if (in_lds)
-        for (int64_t t = threadIdx.x; t < n; t += 256) perm[t] = sperm[t];
+        for (int64_t t = tid; t < n; t += 256) perm[t] = sperm[t];
 }
 
 __device__ __forceinline__ double readlane_f64(double v, int lane) {
@@ -488,13 +554,22 @@ int laswp_left_deferred_f64(double *A, int64_t lda, int64_t n, int64_t nb,
         MXLU_LAUNCH_CHECK();
         // panel j's columns, rows below it, gathered through q
         const int64_t c0 = j * nb, cols = nb;
-        hipLaunchKernelGGL(gather_rows_kernel, dim3(gr, (unsigned)cols), dim3(256), 0, s, A, lda,
+        hipLaunchKernelGGL(gather_panel_rows_kernel, dim3(gr, (unsigned)cols), dim3(256), 0, s, A, lda,
                            j1, rows, c0, q, T);
         MXLU_LAUNCH_CHECK();
-        hipLaunchKernelGGL(put_rows_kernel, dim3(gr, (unsigned)cols), dim3(256), 0, s, T, rows, A,
+        hipLaunchKernelGGL(put_panel_rows_kernel, dim3(gr, (unsigned)cols), dim3(256), 0, s, T, rows, A,
                            lda, j1, c0);
         MXLU_LAUNCH_CHECK();
     }
+    return 0;
+}
+
+int gemv_f64_sub(int64_t M, int64_t K, const double *A, int64_t lda, const double *x, double *y,
+                 hipStream_t s) {
+    if (M <= 0 || K <= 0) return 0;
+    hipLaunchKernelGGL(gemv_f64_sub_kernel, dim3((unsigned)((M + 63) / 64)), dim3(256), 0, s, M, K,
+                       A, lda, x, y);
+    MXLU_LAUNCH_CHECK();
     return 0;
 }
 
