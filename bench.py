@@ -333,7 +333,9 @@ PHASE_UNITS = {
     # phase: (work of one panel step from (n, m, nb), description)
     "gemm": (lambda n, m, nb: 2.0 * (m - nb) ** 2 * nb, "2 (m-nb)^2 nb  [~ N^2 NB]"),
     "pfact": (lambda n, m, nb: float(m) * nb * nb, "m nb^2  [~ N NB^2]"),
-    "swap": (lambda n, m, nb: float(n) * nb, "n nb  [~ N NB]"),
+    # the interchanges of a step reach the columns right of its panel; those
+    # left of it are applied once after the factorization (step -1 below)
+    "swap": (lambda n, m, nb: float(m - nb) * nb, "(m-nb) nb  [~ N NB]"),
     "trsm": (lambda n, m, nb: float(nb) * nb * (m - nb), "nb^2 (m-nb)"),
 }
 
@@ -397,12 +399,14 @@ def run_phase_model(args):
     for nb in nbs:
         for la in (0, 1):
             series, wall = phase_series(n, nb, la)
-            walls[(nb, la)] = (wall, {p: sum(v.values()) for p, v in series.items()})
+            walls[(nb, la)] = (wall, {p: sum(v.values()) for p, v in series.items()},
+                               series["swap"].get(-1, 0.0))
             log(f"phase series n={n} nb={nb} lookahead={la}: {wall:.1f} ms")
             if la == 0:
                 for ph, d in series.items():
                     for step, ms in d.items():
-                        rows.append((nb, step, n - step * nb, ph, ms))
+                        if step >= 0:   # the deferred interchanges are no panel step
+                            rows.append((nb, step, n - step * nb, ph, ms))
     fits = {}
     for ph, (f, desc) in PHASE_UNITS.items():
         pts = [(f(n, m, nb), ms) for nb, step, m, p, ms in rows if p == ph and m - nb > 0]
@@ -418,7 +422,7 @@ def run_phase_model(args):
         g = {s: ms for b, s, m, p, ms in rows if b == nb and p == "gemm"}
         w = {s: ms for b, s, m, p, ms in rows if b == nb and p == "swap"}
         meas = next((s for s in steps if s in g and s in w and w[s] >= g[s]), None)
-        pred = next((s for s in steps if asw * n * nb + csw >=
+        pred = next((s for s in steps if asw * (n - s * nb - nb) * nb + csw >=
                      ag * 2.0 * (n - s * nb - nb) ** 2 * nb + cg), None)
         cross[nb] = (meas, pred, len(steps))
     # serial totals per NB predicted by the fit, against the measured ones
@@ -432,7 +436,7 @@ def run_phase_model(args):
                     continue
                 a, c = fits[ph][:2]
                 t += a * f(n, m, nb) + c
-        pred_tot[nb] = t
+        pred_tot[nb] = t + walls[(nb, 0)][2]   # plus the measured deferred interchanges
     lines = ["# Per-step phase model of the FP64 factorization (N = 32768)", "",
              "Command: `python bench.py --phase-model <out.md>` (HIP events around every "
              "phase of every panel step on the stream it runs on; one warm-up factorization, "
@@ -445,15 +449,19 @@ def run_phase_model(args):
     for ph, (a, c, r2, rel, desc, cnt) in fits.items():
         lines.append(f"| {ph} | {desc} | {a:.4e} | {c:.4f} | {r2:.4f} | {rel:.3f} | {cnt} |")
     g_rate = 1.0 / fits["gemm"][0] / 1e9 if fits["gemm"][0] > 0 else 0.0
+    deferred = {nb: walls[(nb, 0)][2] for nb in nbs}
     lines += ["", f"The DGEMM slope corresponds to {g_rate:.1f} TFLOP/s at the margin; the "
-              "intercepts are per-step latencies (launch gaps, partial waves).", "",
+              "intercepts are per-step latencies (launch gaps, partial waves).  The "
+              "interchanges of the columns left of each panel run once after the "
+              "factorization: " + ", ".join(f"{deferred[nb]:.1f} ms at NB = {nb}" for nb in nbs)
+              + " (included in the SWAP sums below).", "",
               "| NB | serial total measured (ms) | serial total from the fit (ms) | "
               "look-ahead 1 total (ms) | PFACT / SWAP / DTRSM / DGEMM sums at depth 0 (ms) | "
               "GEMM/SWAP crossover step measured / fitted (of steps) |",
               "|---|---|---|---|---|---|"]
     for nb in nbs:
-        w0, s0 = walls[(nb, 0)]
-        w1, _ = walls[(nb, 1)]
+        w0, s0, _ = walls[(nb, 0)]
+        w1 = walls[(nb, 1)][0]
         cm, cp, ns = cross[nb]
         lines.append(f"| {nb} | {w0:.1f} | {pred_tot[nb]:.1f} | {w1:.1f} | "
                      f"{s0['pfact']:.1f} / {s0['swap']:.1f} / {s0['trsm']:.1f} / "
