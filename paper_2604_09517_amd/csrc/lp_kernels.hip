@@ -711,11 +711,17 @@ int trsm_f32_llnu(int64_t kb, int64_t ncols, const float *L, int64_t ldl, float 
                   hipStream_t s) {
     for (int64_t b0 = 0; b0 < kb; b0 += 256) {
         const int bb = (int)((kb - b0 < 256) ? kb - b0 : 256);
-        // 16 columns per workgroup: measured faster than 64 (whose 183
-        // registers leave two waves per SIMD)
         const float *Lb = L + (size_t)b0 + (size_t)b0 * ldl;
-        hipLaunchKernelGGL(trsm_f32_llnu_kernel<16>, dim3((unsigned)((ncols + 15) / 16)),
-                           dim3(256), 0, s, bb, ncols, Lb, ldl, B + b0, ldb);
+        // wide blocks (the U12 TRSM of every step): 32 columns per workgroup,
+        // which halves the workgroups re-reading the 256 x 256 diagonal block
+        // (measured: 319 against 336 ms per FP8 solve at N = 131072; 64
+        // columns, 357 ms); narrow ones (inside the panel): 16
+        if (ncols >= 8192)
+            hipLaunchKernelGGL(trsm_f32_llnu_kernel<32>, dim3((unsigned)((ncols + 31) / 32)),
+                               dim3(256), 0, s, bb, ncols, Lb, ldl, B + b0, ldb);
+        else
+            hipLaunchKernelGGL(trsm_f32_llnu_kernel<16>, dim3((unsigned)((ncols + 15) / 16)),
+                               dim3(256), 0, s, bb, ncols, Lb, ldl, B + b0, ldb);
         MXLU_LAUNCH_CHECK();
         if (b0 + bb < kb) {
             int rc = gemm_f32_sub(kb - b0 - bb, ncols, bb, L + (size_t)(b0 + bb) + (size_t)b0 * ldl,
