@@ -31,8 +31,10 @@ int gemm_f32_sub(int64_t M, int64_t N, int64_t K, const float *A, int64_t lda, c
                  int64_t ldb, float *C, int64_t ldc, hipStream_t s);
 // No-pivot FP32 factorization of the m x kb panel P in place; the first
 // exactly-zero pivot (col_base + column, 1-based) goes to *info if still 0.
-int lp_panel_factor_nopiv(int64_t m, int kb, float *P, int64_t ldp, int *info, int64_t col_base,
-                          hipStream_t s);
+// count: a device int, zero on entry and left zero, used by the leaves (one
+// panel at a time per count).
+int lp_panel_factor_nopiv(int64_t m, int kb, float *P, int64_t ldp, int *info, int *count,
+                          int64_t col_base, hipStream_t s);
 // B (kb x ncols) <- L^-1 B, L unit lower (FP32), any kb.
 int trsm_f32_llnu(int64_t kb, int64_t ncols, const float *L, int64_t ldl, float *B, int64_t ldb,
                   hipStream_t s);
@@ -72,20 +74,24 @@ int lp_quant_l21_mx(int fmt, int64_t mt, int kb, const uint16_t *L21, int64_t ld
 int lp_quant_u12_mx(int fmt, int64_t nt, int kb, const uint16_t *U12, int64_t ldf, uint8_t *Uq,
                     int64_t Np, uint8_t *sUx, hipStream_t s);
 
-// Trailing update on the matrix cores:
+// Trailing update on the matrix cores, of the M x N block C whose columns are
+// lines j0 .. j0 + N - 1 of the packed U operand (and of its scales; j0 a
+// multiple of the tile width 128, and for FP8 of the scale tile, so that the
+// tiles are those of the whole update):
 //   16-bit: C <- round(fp32(C) - L U) with L (M x K) and U (K x N) chunk-packed
 //           (Mp, Np lines), K % kLpKc == 0, C 8-byte aligned with ldc % 4 == 0
 //   FP8:    C <- round(fp32(C) - (Lq Uq) sL sU), e4m3fn operands chunk-packed
 //           (Mp, Np lines), K % kLp8Kc == 0, tile % 4 == 0
 int lp_schur_update(int fmt, int64_t M, int64_t N, int K, const uint16_t *Lp, int64_t Mp,
-                    const uint16_t *Up, int64_t Np, uint16_t *C, int64_t ldc, hipStream_t s);
+                    const uint16_t *Up, int64_t Np, int64_t j0, uint16_t *C, int64_t ldc,
+                    hipStream_t s);
 int lp_schur_update_fp8(int fmt, int64_t M, int64_t N, int K, const uint8_t *Lq, int64_t Mp,
                         const float *sL, const uint8_t *Uq, int64_t Np, const float *sU,
-                        int tile, uint16_t *C, int64_t ldc, hipStream_t s);
+                        int tile, int64_t j0, uint16_t *C, int64_t ldc, hipStream_t s);
 //   MX:     C <- round(fp32(C) - sum_k (Lq sLx)(Uq sUx)), the E8M0 block scales
 //           applied by the matrix cores
 int lp_schur_update_mx(int fmt, int64_t M, int64_t N, int K, const uint8_t *Lq, int64_t Mp,
                        const uint8_t *sLx, const uint8_t *Uq, int64_t Np, const uint8_t *sUx,
-                       uint16_t *C, int64_t ldc, hipStream_t s);
+                       int64_t j0, uint16_t *C, int64_t ldc, hipStream_t s);
 
 }  // namespace mxlu

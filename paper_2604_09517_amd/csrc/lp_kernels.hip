@@ -90,14 +90,20 @@ __global__ void f32_to_lp_kernel(int64_t rows, int64_t cols, const float *__rest
 // workgroups [0, nrow) then finish rows c+ib.. of the block columns (row
 // TRSM with U of the diagonal block), workgroups [nrow, nrow+ncol) finish
 // rows c..c+ib of the panel columns right of the block (unit-lower TRSM).
+// The factored diagonal block goes back to P once, from the last workgroup
+// to have read it (counted in *count, zero on entry and left zero): a
+// workgroup that wrote it earlier would change values that a workgroup
+// scheduled later still has to read.
 // FULL: ib == kLpIb, the loops carry no width predicates (every loop is
 // unrolled at compile time, so the rows stay in registers).
 template <bool FULL>
 __global__ __launch_bounds__(256) void lp_leaf_nopiv_kernel(int m, int kb, int c, int ib_arg,
                                                             float *__restrict__ P, int64_t ldp,
                                                             int nrow, int *__restrict__ info,
+                                                            int *__restrict__ count,
                                                             int64_t col_base) {
     __shared__ float D[kLpIb][kLpIb + 1];
+    __shared__ int last;
     const int ib = FULL ? kLpIb : ib_arg;
     const int tid = threadIdx.x;
     if (tid < 64) {
@@ -129,7 +135,15 @@ __global__ __launch_bounds__(256) void lp_leaf_nopiv_kernel(int m, int kb, int c
             for (int k = 0; k < kLpIb; ++k) D[tid][k] = x[k];
     }
     __syncthreads();
-    if (blockIdx.x == 0) {
+    // D is built from every value of the block this workgroup loaded, so its
+    // reads have completed once the barrier is passed; atomics on one word
+    // are ordered, so the workgroup that counts last writes after every read
+    if (tid == 0) {
+        last = atomicAdd(count, 1) == (int)gridDim.x - 1;
+        if (last) atomicExch(count, 0);   // ready for the next leaf on this stream
+    }
+    __syncthreads();
+    if (last) {
         for (int t = tid; t < ib * ib; t += 256) {
             const int i = t % ib, j = t / ib;
             P[(size_t)(c + i) + (size_t)(c + j) * ldp] = D[i][j];
@@ -676,35 +690,37 @@ int gemm_f32_sub(int64_t M, int64_t N, int64_t K, const float *A, int64_t lda, c
 // kLpIb columns.  Every element still takes its terms in ascending k, one
 // fused multiply-add each, so the result equals the column-by-column order.
 static int panel_nopiv_rec(int64_t m, int64_t c0, int64_t w, float *P, int64_t ldp, int *info,
-                           int64_t col_base, hipStream_t s) {
+                           int *count, int64_t col_base, hipStream_t s) {
     if (w <= kLpIb) {
         const int64_t rows_below = m - c0 - w;
         const int nrow = (int)((rows_below + 255) / 256);
         const dim3 grid((unsigned)(nrow > 0 ? nrow : 1));
         if (w == kLpIb)
             hipLaunchKernelGGL(lp_leaf_nopiv_kernel<true>, grid, dim3(256), 0, s, (int)m,
-                               (int)(c0 + w), (int)c0, (int)w, P, ldp, nrow, info, col_base);
+                               (int)(c0 + w), (int)c0, (int)w, P, ldp, nrow, info, count,
+                               col_base);
         else
             hipLaunchKernelGGL(lp_leaf_nopiv_kernel<false>, grid, dim3(256), 0, s, (int)m,
-                               (int)(c0 + w), (int)c0, (int)w, P, ldp, nrow, info, col_base);
+                               (int)(c0 + w), (int)c0, (int)w, P, ldp, nrow, info, count,
+                               col_base);
         MXLU_LAUNCH_CHECK();
         return 0;
     }
     const int64_t w1 = std::max<int64_t>(kLpIb, (w / 2) / kLpIb * kLpIb);
-    MXLU_TRY(panel_nopiv_rec(m, c0, w1, P, ldp, info, col_base, s));
+    MXLU_TRY(panel_nopiv_rec(m, c0, w1, P, ldp, info, count, col_base, s));
     float *L11 = P + (size_t)c0 + (size_t)c0 * ldp;
     float *U12 = P + (size_t)c0 + (size_t)(c0 + w1) * ldp;
     MXLU_TRY(trsm_f32_llnu(w1, w - w1, L11, ldp, U12, ldp, s));
     if (m - c0 - w1 > 0)
         MXLU_TRY(gemm_f32_sub(m - c0 - w1, w - w1, w1, P + (size_t)(c0 + w1) + (size_t)c0 * ldp, ldp,
                               U12, ldp, P + (size_t)(c0 + w1) + (size_t)(c0 + w1) * ldp, ldp, s));
-    return panel_nopiv_rec(m, c0 + w1, w - w1, P, ldp, info, col_base, s);
+    return panel_nopiv_rec(m, c0 + w1, w - w1, P, ldp, info, count, col_base, s);
 }
 
-int lp_panel_factor_nopiv(int64_t m, int kb, float *P, int64_t ldp, int *info, int64_t col_base,
-                          hipStream_t s) {
+int lp_panel_factor_nopiv(int64_t m, int kb, float *P, int64_t ldp, int *info, int *count,
+                          int64_t col_base, hipStream_t s) {
     if (m <= 0 || kb <= 0) return 0;
-    return panel_nopiv_rec(m, 0, kb, P, ldp, info, col_base, s);
+    return panel_nopiv_rec(m, 0, kb, P, ldp, info, count, col_base, s);
 }
 
 int trsm_f32_llnu(int64_t kb, int64_t ncols, const float *L, int64_t ldl, float *B, int64_t ldb,
