@@ -71,6 +71,11 @@ int lu_factor(int64_t n, int64_t nb, double *A, int64_t lda, int32_t *ipiv,
  *            other CUs; both join the caller's stream before the next SWAP.
  *            Used when n and nb are multiples of 128, lda is even, A is
  *            16-byte aligned and n > nb; otherwise lu_factor runs depth 0.
+ * The same depth applies to the low-precision factorization of mxp_solve
+ * without pivoting: at depth 1 the update of the next panel's columns runs
+ * first, then that panel is factored on a side stream of the library while
+ * the rest of the update runs on the caller's stream (used when nb is a
+ * multiple of 128 and, for FP8 with tile scales, of scale_tile).
  * The factors and ipiv are the same at both depths (each element takes the
  * same operations in the same order).  Returns 0, or -1 for a depth other
  * than 0 or 1.
@@ -79,8 +84,8 @@ int mxlu_set_lookahead(int depth);
 
 /*
  * mxlu_release -- destroys what the library keeps between calls: the two
- * CU-masked streams of the look-ahead (per device) and the pooled timing
- * events.  They are created again on demand.  Call it only while no library
+ * CU-masked streams of the look-ahead and the side stream of the
+ * mixed-precision look-ahead (per device), and the pooled timing events.  They are created again on demand.  Call it only while no library
  * work is in flight; it also runs at process exit (registered when the
  * streams are first created, so before the HIP runtime's own teardown).
  * Returns 0.
@@ -93,7 +98,7 @@ int mxlu_set_lookahead(int depth);
  * its waits are bounded, and when one expires lu_factor returns
  * MXLU_E_TIMEOUT (the factors are then invalid, but every access stays
  * inside A and ipiv).  Look-ahead factorizations of one process are
- * serialised (they share the masked streams).
+ * serialised (they share the library's streams).
  */
 int mxlu_release(void);
 

@@ -6,6 +6,7 @@
 
 #include <atomic>
 #include <cstdint>
+#include <mutex>
 
 namespace mxlu {
 
@@ -134,5 +135,15 @@ int gather_rows_f64(int64_t n, int64_t nrhs, const int32_t *perm, const double *
                     int64_t ldb, double *Y, int64_t ldy, hipStream_t s);
 int scatter_rows_f64(int64_t n, int64_t nrhs, const int32_t *perm, const double *Y,
                      int64_t ldy, double *B, int64_t ldb, hipStream_t s);
+
+// Streams of the mixed-precision factorization's look-ahead: `panel` factors
+// the next panel while the rest of the trailing update runs on the caller's
+// stream.  False at look-ahead depth 0 or when the streams are missing; on
+// true the caller holds the process-wide look-ahead lock in *lk until its
+// factorization has completed (the streams are shared by every call).
+struct AheadStreams {
+    hipStream_t panel = nullptr;
+};
+bool lp_ahead_streams(AheadStreams *out, std::unique_lock<std::mutex> *lk);
 
 }  // namespace mxlu

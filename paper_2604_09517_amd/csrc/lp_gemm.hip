@@ -587,13 +587,16 @@ __global__ __launch_bounds__(256, NS <= 2 ? 2 : 1) void lp_schur8_kernel(
 namespace mxlu {
 
 int lp_schur_update(int fmt, int64_t M, int64_t N, int K, const uint16_t *Lp, int64_t Mp,
-                    const uint16_t *Up, int64_t Np, uint16_t *C, int64_t ldc, hipStream_t s) {
+                    const uint16_t *Up, int64_t Np, int64_t j0, uint16_t *C, int64_t ldc,
+                    hipStream_t s) {
     if (M <= 0 || N <= 0 || K <= 0) return 0;
-    if (K % BK16 || Mp % TM || Np % TN || Mp < M || Np < N || ldc % 4 ||
-        ((uintptr_t)Lp | (uintptr_t)Up) % 16 || (uintptr_t)C % 8) {
-        set_error_msg("lp_schur_update: K % 32, padded packed operands, ldc % 4 and alignment required");
+    if (K % BK16 || Mp % TM || Np % TN || Mp < M || j0 < 0 || j0 % TN || Np - j0 < N ||
+        ldc % 4 || ((uintptr_t)Lp | (uintptr_t)Up) % 16 || (uintptr_t)C % 8) {
+        set_error_msg("lp_schur_update: K % 32, padded packed operands, j0 % 128, ldc % 4 and "
+                      "alignment required");
         return MXLU_E_NOMEM;
     }
+    Up += (size_t)j0 * BK16;   // line j0 of every K chunk
     const int64_t tiles_m = (M + TM - 1) / TM, tiles_n = (N + TN - 1) / TN;
     const dim3 grid((unsigned)(tiles_m * tiles_n));
     if (fmt == kFmtBf16)
@@ -608,14 +611,17 @@ int lp_schur_update(int fmt, int64_t M, int64_t N, int K, const uint16_t *Lp, in
 
 int lp_schur_update_fp8(int fmt, int64_t M, int64_t N, int K, const uint8_t *Lq, int64_t Mp,
                         const float *sL, const uint8_t *Uq, int64_t Np, const float *sU,
-                        int tile, uint16_t *C, int64_t ldc, hipStream_t s) {
+                        int tile, int64_t j0, uint16_t *C, int64_t ldc, hipStream_t s) {
     if (M <= 0 || N <= 0 || K <= 0) return 0;
-    if (K % BK8 || Mp % kTm8 || Np % kTn8 || Mp < M || Np < N || tile % 4 || tile <= 0 ||
-        ldc % 4 || ((uintptr_t)Lq | (uintptr_t)Uq) % 16 || (uintptr_t)C % 8) {
-        set_error_msg("lp_schur_update_fp8: K % 128, padded packed operands, tile % 4, ldc % 4 "
-                      "and alignment required");
+    if (K % BK8 || Mp % kTm8 || Np % kTn8 || Mp < M || tile % 4 || tile <= 0 || j0 < 0 ||
+        j0 % kTn8 || j0 % tile || Np - j0 < N || ldc % 4 ||
+        ((uintptr_t)Lq | (uintptr_t)Uq) % 16 || (uintptr_t)C % 8) {
+        set_error_msg("lp_schur_update_fp8: K % 128, padded packed operands, tile % 4, j0 a "
+                      "multiple of 128 and of the tile, ldc % 4 and alignment required");
         return MXLU_E_NOMEM;
     }
+    Uq += (size_t)j0 * BK8;   // line j0 of every K chunk
+    sU += j0 / tile;
     const int64_t tiles_m = (M + kTm8 - 1) / kTm8, tiles_n = (N + kTn8 - 1) / kTn8;
     const dim3 grid((unsigned)(tiles_m * tiles_n));
     // two stages with two workgroups per CU: measured faster than three or
@@ -641,14 +647,16 @@ int lp_schur_update_fp8(int fmt, int64_t M, int64_t N, int K, const uint8_t *Lq,
 
 int lp_schur_update_mx(int fmt, int64_t M, int64_t N, int K, const uint8_t *Lq, int64_t Mp,
                        const uint8_t *sLx, const uint8_t *Uq, int64_t Np, const uint8_t *sUx,
-                       uint16_t *C, int64_t ldc, hipStream_t s) {
+                       int64_t j0, uint16_t *C, int64_t ldc, hipStream_t s) {
     if (M <= 0 || N <= 0 || K <= 0) return 0;
-    if (K % BK8 || Mp % kTm8 || Np % kTn8 || Mp < M || Np < N || ldc % 4 ||
-        ((uintptr_t)Lq | (uintptr_t)Uq) % 16 || (uintptr_t)C % 8 || !sLx || !sUx) {
-        set_error_msg("lp_schur_update_mx: K % 128, padded packed operands, scales, ldc % 4 and "
-                      "alignment required");
+    if (K % BK8 || Mp % kTm8 || Np % kTn8 || Mp < M || j0 < 0 || j0 % kTn8 || Np - j0 < N ||
+        ldc % 4 || ((uintptr_t)Lq | (uintptr_t)Uq) % 16 || (uintptr_t)C % 8 || !sLx || !sUx) {
+        set_error_msg("lp_schur_update_mx: K % 128, padded packed operands, scales, j0 % 128, "
+                      "ldc % 4 and alignment required");
         return MXLU_E_NOMEM;
     }
+    Uq += (size_t)j0 * BK8;   // line j0 of every K chunk
+    sUx += j0;                // sUx[b Np + c]: line j0 of every block
     const int64_t tiles_m = (M + kTm8 - 1) / kTm8, tiles_n = (N + kTn8 - 1) / kTn8;
     const dim3 grid((unsigned)(tiles_m * tiles_n));
     const float *none = nullptr;

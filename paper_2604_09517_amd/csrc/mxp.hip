@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -62,6 +63,42 @@ struct Timer {
     }
 };
 
+// Fork and join of the look-ahead stream p with the factorization stream s;
+// joins p back into s when it goes out of scope (also on an error return, so
+// that no work of the call still runs when its scratch memory is released).
+class AheadJoin {
+  public:
+    AheadJoin(hipStream_t s, hipStream_t p) : s_(s), p_(p) {}
+    ~AheadJoin() {
+        if (active_) (void)join();
+        for (hipEvent_t e : ev_)
+            if (e) (void)hipEventDestroy(e);
+    }
+    int create() {
+        for (hipEvent_t &e : ev_)
+            MXLU_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        active_ = true;
+        return 0;
+    }
+    // p continues after everything enqueued so far on s
+    int fork() {
+        MXLU_HIP_TRY(hipEventRecord(ev_[0], s_));
+        MXLU_HIP_TRY(hipStreamWaitEvent(p_, ev_[0], 0));
+        return 0;
+    }
+    // s continues after everything enqueued so far on p
+    int join() {
+        MXLU_HIP_TRY(hipEventRecord(ev_[1], p_));
+        MXLU_HIP_TRY(hipStreamWaitEvent(s_, ev_[1], 0));
+        return 0;
+    }
+
+  private:
+    hipStream_t s_, p_;
+    hipEvent_t ev_[2] = {};
+    bool active_ = false;
+};
+
 // ------------------------------------------------------------------ factor
 int lp_factorize(const mxp_opts &o, int64_t n, const ASource &src, uint16_t *F,
                  int64_t ldf, int32_t *ipiv, int *info_host, hipStream_t s, double *t_conv,
@@ -74,7 +111,7 @@ int lp_factorize(const mxp_opts &o, int64_t n, const ASource &src, uint16_t *F,
     Scratch scratch(s);
     float *P32 = scratch.alloc_n<float>((size_t)n * nb);
     float *T32 = scratch.alloc_n<float>((size_t)nb * n);
-    int *d_info = scratch.alloc_n<int>(4);
+    int *d_info = scratch.alloc_n<int>(4);   // [0] first zero pivot, [2] the leaves' counter
     uint16_t *LTp = nullptr, *Up = nullptr;   // chunk-packed L21 and U12 (16-bit form)
     const int64_t Mp = lp_round_up(n, kLpTileM), Np = lp_round_up(n, kLpTileN);
     uint8_t *LTq = nullptr, *Uq = nullptr;
@@ -116,26 +153,71 @@ int lp_factorize(const mxp_opts &o, int64_t n, const ASource &src, uint16_t *F,
         MXLU_TRY(lp_convert_src(fmt, n, src, F, ldf, s));
     }
     tc.stop();
+
+    // Depth-1 look-ahead (no pivoting only: the pivoted panel's workgroups
+    // must all be resident at once, which a stream shared with the update
+    // cannot promise): the update of the next panel's columns runs first, then
+    // that panel is factored on the look-ahead stream while the rest of the
+    // update runs on s.  Both parts are the same tiles as the whole update
+    // (split at a multiple of the tile width and of the scale tile), so every
+    // element takes the same operations in the same order as at depth 0.
+    AheadStreams ahs;
+    std::unique_lock<std::mutex> ahead_lock;
+    const bool la = !o.pivot && n > nb && nb % 128 == 0 && (!fp8 || mx || nb % tile == 0) &&
+                    lp_ahead_streams(&ahs, &ahead_lock);
+    uint16_t *LTp_next = nullptr;   // the look-ahead panel's packed L21 (16-bit form)
+    if (la && !fp8) {
+        LTp_next = scratch.alloc_n<uint16_t>((size_t)nb * Mp);
+        if (!LTp_next) return MXLU_E_NOMEM;
+    }
+    AheadJoin aj(s, la ? ahs.panel : nullptr);
+    if (la) MXLU_TRY(aj.create());
+
+    // PFACT of the panel at k0 (width kb) on stream st; lt receives its
+    // packed L21 in the 16-bit form
+    auto pfact = [&](int64_t k0, int64_t kb, hipStream_t st, uint16_t *lt) -> int {
+        const int64_t m = n - k0, c1 = k0 + kb;
+        uint16_t *Fk = F + (size_t)k0 + (size_t)k0 * ldf;
+        // work: the panel's bytes in storage precision
+        PhaseScope ph(kPhasePfact, st, 2.0 * (double)m * kb);
+        MXLU_TRY(lp_load_f32(fmt, m, kb, Fk, ldf, P32, m, st));
+        if (o.pivot)   // partial pivoting on the FP32 values of the panel
+            MXLU_TRY(panel_factor<float>(P32, m, m, kb, k0, ipiv, ex, moves, st));
+        else
+            MXLU_TRY(lp_panel_factor_nopiv(m, (int)kb, P32, m, d_info, d_info + 2, k0, st));
+        const bool need_lt = !fp8 && c1 < n;
+        return lp_panel_store(fmt, m, (int)kb, P32, m, Fk, ldf, need_lt ? lt : nullptr, Mp, st);
+    };
+    // columns [j0, j0 + w) of the trailing update A22 -= L21 U12 of the step
+    // at k0 (the operands already quantised or packed), on stream st
+    auto update = [&](int64_t k0, int64_t kb, int64_t j0, int64_t w, hipStream_t st,
+                      const uint16_t *lt) -> int {
+        const int64_t c1 = k0 + kb, nt = n - c1;
+        uint16_t *C = F + (size_t)c1 + (size_t)(c1 + j0) * ldf;
+        // algorithmic bytes: the block of A22 read and written in 16 bits,
+        // L21 and the block's U12 columns read once
+        const double ob = fp8 ? 1.0 : 2.0;
+        PhaseScope ph(kPhaseLpSchur, st, 4.0 * (double)nt * (double)w + ob * (double)(nt + w) * kb);
+        if (mx)
+            return lp_schur_update_mx(fmt, nt, w, (int)kb, LTq, Mp8, sLx, Uq, Np8, sUx, j0, C, ldf,
+                                      st);
+        if (fp8)
+            return lp_schur_update_fp8(fmt, nt, w, (int)kb, LTq, Mp8, sL, Uq, Np8, sU, tile, j0, C,
+                                       ldf, st);
+        return lp_schur_update(fmt, nt, w, (int)kb, lt, Mp, Up, Np, j0, C, ldf, st);
+    };
+
     tf.start();
     {
         PhaseScope ph(kPhaseLpFactor, s, (2.0 / 3.0) * (double)n * n * n);
         int64_t step = 0;
+        bool ahead = false;   // the current panel was factored during the previous update
         for (int64_t k0 = 0; k0 < n; k0 += nb, ++step) {
             if (o.factor_steps > 0 && step >= o.factor_steps) break;
             profile_set_step(step);
-            const int64_t kb = std::min(nb, n - k0), m = n - k0, c1 = k0 + kb;
-            uint16_t *Fk = F + (size_t)k0 + (size_t)k0 * ldf;
-            {   // PFACT in FP32 (work: the panel's bytes in storage precision)
-                PhaseScope ph(kPhasePfact, s, 2.0 * (double)m * kb);
-                MXLU_TRY(lp_load_f32(fmt, m, kb, Fk, ldf, P32, m, s));
-                if (o.pivot)   // partial pivoting on the FP32 values of the panel
-                    MXLU_TRY(panel_factor<float>(P32, m, m, kb, k0, ipiv, ex, moves, s));
-                else
-                    MXLU_TRY(lp_panel_factor_nopiv(m, (int)kb, P32, m, d_info, k0, s));
-                const bool need_lt = !fp8 && c1 < n;
-                MXLU_TRY(lp_panel_store(fmt, m, (int)kb, P32, m, Fk, ldf, need_lt ? LTp : nullptr,
-                                        Mp, s));
-            }
+            const int64_t kb = std::min(nb, n - k0), c1 = k0 + kb;
+            if (!ahead) MXLU_TRY(pfact(k0, kb, s, LTp));
+            ahead = false;
             if (o.pivot && n > kb) {   // the panel's interchanges on the other stored columns
                 PhaseScope ph(kPhaseSwap, s, 8.0 * kb * (double)(n - kb));
                 MXLU_TRY(swap_compose(ipiv, k0, (int)kb, n, moves, s));
@@ -147,33 +229,37 @@ int lp_factorize(const mxp_opts &o, int64_t n, const ASource &src, uint16_t *F,
             {   // U12 = L11^-1 A12 in FP32
                 PhaseScope ph(kPhaseTrsm, s, (double)kb * (kb - 1) * (double)nt);
                 MXLU_TRY(lp_load_f32(fmt, kb, nt, U12, ldf, T32, kb, s));
-                MXLU_TRY(trsm_f32_llnu(kb, nt, P32, m, T32, kb, s));
+                MXLU_TRY(trsm_f32_llnu(kb, nt, P32, n - k0, T32, kb, s));
                 MXLU_TRY(lp_store_f32(fmt, kb, nt, T32, kb, U12, ldf, s));
             }
-            uint16_t *A22 = F + (size_t)c1 + (size_t)c1 * ldf;
-            // algorithmic bytes: A22 read and written in 16 bits, L21 and U12 read once
-            const double ob = fp8 ? 1.0 : 2.0;
-            const double schur_bytes =
-                4.0 * (double)nt * (double)nt + 2.0 * ob * (double)nt * (double)kb;
             if (mx) {
                 const uint16_t *L21 = F + (size_t)c1 + (size_t)k0 * ldf;
                 MXLU_TRY(lp_quant_l21_mx(fmt, nt, (int)kb, L21, ldf, LTq, Mp8, sLx, s));
                 MXLU_TRY(lp_quant_u12_mx(fmt, nt, (int)kb, U12, ldf, Uq, Np8, sUx, s));
-                PhaseScope ph(kPhaseLpSchur, s, schur_bytes);
-                MXLU_TRY(lp_schur_update_mx(fmt, nt, nt, (int)kb, LTq, Mp8, sLx, Uq, Np8, sUx, A22,
-                                            ldf, s));
             } else if (fp8) {
                 const uint16_t *L21 = F + (size_t)c1 + (size_t)k0 * ldf;
                 MXLU_TRY(lp_quant_l21(fmt, nt, (int)kb, tile, L21, ldf, LTq, Mp8, sL, s));
                 MXLU_TRY(lp_quant_u12(fmt, nt, (int)kb, tile, U12, ldf, Uq, Np8, sU, s));
-                PhaseScope ph(kPhaseLpSchur, s, schur_bytes);
-                MXLU_TRY(lp_schur_update_fp8(fmt, nt, nt, (int)kb, LTq, Mp8, sL, Uq, Np8, sU, tile,
-                                             A22, ldf, s));
             } else {
                 MXLU_TRY(lp_pack_u12(nt, (int)kb, U12, ldf, Up, Np, s));
-                PhaseScope ph(kPhaseLpSchur, s, schur_bytes);
-                MXLU_TRY(lp_schur_update(fmt, nt, nt, (int)kb, LTp, Mp, Up, Np, A22, ldf, s));
             }
+            // a factorization stopped after this step leaves the next panel
+            // unfactored, so it is not factored ahead
+            const bool go_ahead = la && !(o.factor_steps > 0 && step + 1 >= o.factor_steps);
+            if (!go_ahead) {
+                MXLU_TRY(update(k0, kb, 0, nt, s, LTp));
+                continue;
+            }
+            const int64_t kb1 = std::min(nb, nt);
+            MXLU_TRY(update(k0, kb, 0, kb1, s, LTp));
+            MXLU_TRY(aj.fork());
+            profile_set_step(step + 1);   // the next step's panel
+            MXLU_TRY(pfact(c1, kb1, ahs.panel, LTp_next));
+            profile_set_step(step);
+            if (nt > kb1) MXLU_TRY(update(k0, kb, kb1, nt - kb1, s, LTp));
+            MXLU_TRY(aj.join());
+            std::swap(LTp, LTp_next);
+            ahead = true;
         }
     }
     profile_set_step(-1);
@@ -201,7 +287,7 @@ int lp_factorize_f32(const mxp_opts &o, int64_t n, const ASource &src, float *F,
                      double *t_fact) {
     const int64_t nb = std::min<int64_t>(o.nb, n);
     Scratch scratch(s);
-    int *d_info = scratch.alloc_n<int>(4);
+    int *d_info = scratch.alloc_n<int>(4);   // [0] first zero pivot, [2] the leaves' counter
     if (!d_info) return MXLU_E_NOMEM;
     MXLU_HIP_TRY(hipMemsetAsync(d_info, 0, 4 * sizeof(int), s));
     PanelExchange ex{};
@@ -232,7 +318,7 @@ int lp_factorize_f32(const mxp_opts &o, int64_t n, const ASource &src, float *F,
                 if (o.pivot)
                     MXLU_TRY(panel_factor<float>(Fk, ldf, m, kb, k0, ipiv, ex, moves, s));
                 else
-                    MXLU_TRY(lp_panel_factor_nopiv(m, (int)kb, Fk, ldf, d_info, k0, s));
+                    MXLU_TRY(lp_panel_factor_nopiv(m, (int)kb, Fk, ldf, d_info, d_info + 2, k0, s));
             }
             if (o.pivot && n > kb) {
                 PhaseScope ph(kPhaseSwap, s, 16.0 * kb * (double)(n - kb));

@@ -176,6 +176,42 @@ def test_lp_factors_against_oracle(api, prec, n, nb, kind, tile):
     assert err <= 4 * u
 
 
+@pytest.mark.parametrize("prec,n,nb,kind,tile,steps", [
+    ("bf16", 2216, 512, "dominant", 128, 0), ("fp16", 700, 128, "dominant", 64, 0),
+    ("bf16", 1064, 256, "scaled", 128, 2), ("fp8", 2216, 1024, "dominant", 128, 0),
+    ("fp8", 1064, 256, "scaled", 128, 0), ("fp8", 1064, 256, "scaled", 64, 3),
+    ("fp8", 500, 128, "scaled", 12, 0), ("fp8_mx", 2216, 1024, "scaled", 32, 0),
+    ("fp8_mx", 1064, 256, "scaled", 32, 2)])
+def test_lp_lookahead_equals_depth0(api, prec, n, nb, kind, tile, steps):
+    """Look-ahead depth 1 (the next panel factored on a second stream while
+    the rest of the update runs) gives the same factors as depth 0 bit for
+    bit: the update is split at a tile boundary, so every element takes the
+    same operations in the same order.  Covers a ragged last panel (n = 2216,
+    nb = 1024: the last update is narrower than a panel), factorizations
+    stopped after a few steps (the panel after the last step stays
+    unfactored) and a scale tile that does not divide nb (depth 0 is used)."""
+    note(f"look-ahead vs depth 0 prec={prec} n={n} nb={nb} input={kind} tile={tile} "
+         f"steps={steps}")
+    A = lp_input(kind, n, 91 + n, tile)
+    b = inputs.uniform_matrix(91 + n, 1, n, 1)[:, 0]
+    got = []
+    try:
+        for depth in (0, 1):
+            api.set_lookahead(depth)
+            _, rep, work, _ = run_mxp(api, A, b, prec=prec, nb=nb, max_outer=0,
+                                      scale_tile=tile, factor_steps=steps)
+            got.append(api.mxp_factors(work, n, prec).cpu().clone())
+            assert rep["info"] == 0
+    finally:
+        api.set_lookahead(1)
+    assert torch.equal(got[0].view(torch.int16), got[1].view(torch.int16))
+    if steps:   # the block after the last step is the updated, unfactored Schur complement
+        F_ref, _, _ = oracle.lp_getrf(A, nb, PREC_ID[prec], pivot=False, tile=tile,
+                                      max_steps=steps)
+        F = got[1].to(torch.float64).numpy()
+        assert np.all(np.abs(F - F_ref) <= componentwise_bound(A, F_ref, nb, prec))
+
+
 @pytest.mark.parametrize("prec,n,nb,kind,tile", [
     ("bf16", 680, 256, "dominant", 128), ("fp16", 700, 128, "dominant", 64),
     ("bf16", 2216, 512, "dominant", 128),
@@ -399,6 +435,45 @@ def test_full_size_fp8_configuration(api):
     note(f"seeded report {reps}")
     assert reps["outer_iters"] == rep["outer_iters"] and reps["inner_iters"] == rep["inner_iters"]
     assert torch.equal(Xs, X)
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+def test_full_size_fp8_lookahead_equals_depth0(api):
+    """N = 131072, NB = 1024 FP8 factorization: look-ahead depth 1 (the next
+    panel factored on a second stream) gives the depth-0 factors bit for bit
+    at full size, where the panel's leaves run hundreds of workgroups.  (A
+    leaf that let one workgroup write the factored diagonal block back while
+    others might still read it flipped a few hundred FP16 entries by one unit
+    here once the panel's workgroups were scheduled differently.)"""
+    cfg = inputs.WORKLOADS["fp8_ir"]
+    n, nb, seed = cfg["n"], cfg["nb"], inputs.config_seed(cfg["index"])
+    note(f"full size fp8 look-ahead vs depth 0 n={n} nb={nb}")
+    dA = api.fortran_empty(n, n)
+    api.fill_uniform(dA, seed, inputs.STREAM_A)
+    api.make_diag_dominant(dA)
+    db = torch.from_numpy(inputs.uniform_matrix(seed, inputs.STREAM_B, n, 1)[:, 0]).cuda()
+    opts = api.mxp_options(prec="fp8", nb=nb, scale_tile=128, max_outer=0)
+    work = torch.empty(api.mxp_workspace_bytes(n, opts, n), dtype=torch.uint8, device="cuda")
+    F0 = None
+    try:
+        for depth in (0, 1):
+            api.set_lookahead(depth)
+            _, rep, work, _ = api.mxp_solve(dA, db, work=work, opts=opts, allow_notconv=True)
+            torch.cuda.synchronize()
+            assert rep["info"] == 0
+            F = api.mxp_factors(work, n, "fp8").view(torch.int16)
+            if F0 is None:
+                F0 = F.clone()
+    finally:
+        api.set_lookahead(1)
+    del dA
+    torch.cuda.empty_cache()
+    differ = 0
+    for j0 in range(0, n, 8192):   # column slabs bound the temporaries
+        differ += int((F[:, j0:j0 + 8192] != F0[:, j0:j0 + 8192]).sum())
+    note(f"  entries differing: {differ}")
+    assert differ == 0
 
 
 def test_lp_pivoted_first_panel_matches_oracle(api):
