@@ -587,16 +587,18 @@ __global__ __launch_bounds__(256, NS <= 2 ? 2 : 1) void lp_schur8_kernel(
 namespace mxlu {
 
 int lp_schur_update(int fmt, int64_t M, int64_t N, int K, const uint16_t *Lp, int64_t Mp,
-                    const uint16_t *Up, int64_t Np, int64_t j0, uint16_t *C, int64_t ldc,
-                    hipStream_t s) {
+                    int64_t i0, const uint16_t *Up, int64_t Np, int64_t j0, uint16_t *C,
+                    int64_t ldc, hipStream_t s) {
     if (M <= 0 || N <= 0 || K <= 0) return 0;
-    if (K % BK16 || Mp % TM || Np % TN || Mp < M || j0 < 0 || j0 % TN || Np - j0 < N ||
-        ldc % 4 || ((uintptr_t)Lp | (uintptr_t)Up) % 16 || (uintptr_t)C % 8) {
-        set_error_msg("lp_schur_update: K % 32, padded packed operands, j0 % 128, ldc % 4 and "
-                      "alignment required");
+    if (K % BK16 || Mp % TM || Np % TN || i0 < 0 || i0 % TM || Mp - i0 < M || j0 < 0 ||
+        j0 % TN || Np - j0 < N || ldc % 4 || ((uintptr_t)Lp | (uintptr_t)Up) % 16 ||
+        (uintptr_t)C % 8) {
+        set_error_msg("lp_schur_update: K % 32, padded packed operands, i0 % 256, j0 % 128, "
+                      "ldc % 4 and alignment required");
         return MXLU_E_NOMEM;
     }
-    Up += (size_t)j0 * BK16;   // line j0 of every K chunk
+    Lp += (size_t)i0 * BK16;   // line i0 of every K chunk
+    Up += (size_t)j0 * BK16;
     const int64_t tiles_m = (M + TM - 1) / TM, tiles_n = (N + TN - 1) / TN;
     const dim3 grid((unsigned)(tiles_m * tiles_n));
     if (fmt == kFmtBf16)
@@ -610,17 +612,20 @@ int lp_schur_update(int fmt, int64_t M, int64_t N, int K, const uint16_t *Lp, in
 }
 
 int lp_schur_update_fp8(int fmt, int64_t M, int64_t N, int K, const uint8_t *Lq, int64_t Mp,
-                        const float *sL, const uint8_t *Uq, int64_t Np, const float *sU,
-                        int tile, int64_t j0, uint16_t *C, int64_t ldc, hipStream_t s) {
+                        const float *sL, int64_t i0, const uint8_t *Uq, int64_t Np,
+                        const float *sU, int64_t j0, int tile, uint16_t *C, int64_t ldc,
+                        hipStream_t s) {
     if (M <= 0 || N <= 0 || K <= 0) return 0;
-    if (K % BK8 || Mp % kTm8 || Np % kTn8 || Mp < M || tile % 4 || tile <= 0 || j0 < 0 ||
-        j0 % kTn8 || j0 % tile || Np - j0 < N || ldc % 4 ||
-        ((uintptr_t)Lq | (uintptr_t)Uq) % 16 || (uintptr_t)C % 8) {
-        set_error_msg("lp_schur_update_fp8: K % 128, padded packed operands, tile % 4, j0 a "
-                      "multiple of 128 and of the tile, ldc % 4 and alignment required");
+    if (K % BK8 || Mp % kTm8 || Np % kTn8 || tile % 4 || tile <= 0 || i0 < 0 || i0 % kTm8 ||
+        i0 % tile || Mp - i0 < M || j0 < 0 || j0 % kTn8 || j0 % tile || Np - j0 < N ||
+        ldc % 4 || ((uintptr_t)Lq | (uintptr_t)Uq) % 16 || (uintptr_t)C % 8) {
+        set_error_msg("lp_schur_update_fp8: K % 128, padded packed operands, tile % 4, i0 and "
+                      "j0 multiples of 128 and of the tile, ldc % 4 and alignment required");
         return MXLU_E_NOMEM;
     }
-    Uq += (size_t)j0 * BK8;   // line j0 of every K chunk
+    Lq += (size_t)i0 * BK8;   // line i0 (j0) of every K chunk
+    Uq += (size_t)j0 * BK8;
+    sL += i0 / tile;
     sU += j0 / tile;
     const int64_t tiles_m = (M + kTm8 - 1) / kTm8, tiles_n = (N + kTn8 - 1) / kTn8;
     const dim3 grid((unsigned)(tiles_m * tiles_n));
@@ -646,17 +651,20 @@ int lp_schur_update_fp8(int fmt, int64_t M, int64_t N, int K, const uint8_t *Lq,
 }
 
 int lp_schur_update_mx(int fmt, int64_t M, int64_t N, int K, const uint8_t *Lq, int64_t Mp,
-                       const uint8_t *sLx, const uint8_t *Uq, int64_t Np, const uint8_t *sUx,
-                       int64_t j0, uint16_t *C, int64_t ldc, hipStream_t s) {
+                       const uint8_t *sLx, int64_t i0, const uint8_t *Uq, int64_t Np,
+                       const uint8_t *sUx, int64_t j0, uint16_t *C, int64_t ldc, hipStream_t s) {
     if (M <= 0 || N <= 0 || K <= 0) return 0;
-    if (K % BK8 || Mp % kTm8 || Np % kTn8 || Mp < M || j0 < 0 || j0 % kTn8 || Np - j0 < N ||
-        ldc % 4 || ((uintptr_t)Lq | (uintptr_t)Uq) % 16 || (uintptr_t)C % 8 || !sLx || !sUx) {
-        set_error_msg("lp_schur_update_mx: K % 128, padded packed operands, scales, j0 % 128, "
-                      "ldc % 4 and alignment required");
+    if (K % BK8 || Mp % kTm8 || Np % kTn8 || i0 < 0 || i0 % kTm8 || Mp - i0 < M || j0 < 0 ||
+        j0 % kTn8 || Np - j0 < N || ldc % 4 || ((uintptr_t)Lq | (uintptr_t)Uq) % 16 ||
+        (uintptr_t)C % 8 || !sLx || !sUx) {
+        set_error_msg("lp_schur_update_mx: K % 128, padded packed operands, scales, i0 % 128, "
+                      "j0 % 128, ldc % 4 and alignment required");
         return MXLU_E_NOMEM;
     }
-    Uq += (size_t)j0 * BK8;   // line j0 of every K chunk
-    sUx += j0;                // sUx[b Np + c]: line j0 of every block
+    Lq += (size_t)i0 * BK8;   // line i0 (j0) of every K chunk
+    Uq += (size_t)j0 * BK8;
+    sLx += i0;                // sLx[b Mp + r], sUx[b Np + c]: line i0 (j0) of every block
+    sUx += j0;
     const int64_t tiles_m = (M + kTm8 - 1) / kTm8, tiles_n = (N + kTn8 - 1) / kTn8;
     const dim3 grid((unsigned)(tiles_m * tiles_n));
     const float *none = nullptr;

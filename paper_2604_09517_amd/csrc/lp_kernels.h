@@ -74,24 +74,28 @@ int lp_quant_l21_mx(int fmt, int64_t mt, int kb, const uint16_t *L21, int64_t ld
 int lp_quant_u12_mx(int fmt, int64_t nt, int kb, const uint16_t *U12, int64_t ldf, uint8_t *Uq,
                     int64_t Np, uint8_t *sUx, hipStream_t s);
 
-// Trailing update on the matrix cores, of the M x N block C whose columns are
-// lines j0 .. j0 + N - 1 of the packed U operand (and of its scales; j0 a
-// multiple of the tile width 128, and for FP8 of the scale tile, so that the
+// Trailing update on the matrix cores, of the M x N block C whose rows are
+// lines i0 .. i0 + M - 1 of the packed L operand and whose columns are lines
+// j0 .. j0 + N - 1 of the packed U operand (and of their scales; i0 and j0
+// multiples of the tile sizes, and for FP8 of the scale tile, so that the
 // tiles are those of the whole update):
 //   16-bit: C <- round(fp32(C) - L U) with L (M x K) and U (K x N) chunk-packed
-//           (Mp, Np lines), K % kLpKc == 0, C 8-byte aligned with ldc % 4 == 0
+//           (Mp, Np lines), K % kLpKc == 0, C 8-byte aligned with ldc % 4 == 0,
+//           i0 % 256 == 0, j0 % 128 == 0
 //   FP8:    C <- round(fp32(C) - (Lq Uq) sL sU), e4m3fn operands chunk-packed
-//           (Mp, Np lines), K % kLp8Kc == 0, tile % 4 == 0
+//           (Mp, Np lines), K % kLp8Kc == 0, tile % 4 == 0, i0 and j0
+//           multiples of 128 and of the tile
 int lp_schur_update(int fmt, int64_t M, int64_t N, int K, const uint16_t *Lp, int64_t Mp,
-                    const uint16_t *Up, int64_t Np, int64_t j0, uint16_t *C, int64_t ldc,
-                    hipStream_t s);
+                    int64_t i0, const uint16_t *Up, int64_t Np, int64_t j0, uint16_t *C,
+                    int64_t ldc, hipStream_t s);
 int lp_schur_update_fp8(int fmt, int64_t M, int64_t N, int K, const uint8_t *Lq, int64_t Mp,
-                        const float *sL, const uint8_t *Uq, int64_t Np, const float *sU,
-                        int tile, int64_t j0, uint16_t *C, int64_t ldc, hipStream_t s);
+                        const float *sL, int64_t i0, const uint8_t *Uq, int64_t Np,
+                        const float *sU, int64_t j0, int tile, uint16_t *C, int64_t ldc,
+                        hipStream_t s);
 //   MX:     C <- round(fp32(C) - sum_k (Lq sLx)(Uq sUx)), the E8M0 block scales
-//           applied by the matrix cores
+//           applied by the matrix cores; i0 and j0 multiples of 128
 int lp_schur_update_mx(int fmt, int64_t M, int64_t N, int K, const uint8_t *Lq, int64_t Mp,
-                       const uint8_t *sLx, const uint8_t *Uq, int64_t Np, const uint8_t *sUx,
-                       int64_t j0, uint16_t *C, int64_t ldc, hipStream_t s);
+                       const uint8_t *sLx, int64_t i0, const uint8_t *Uq, int64_t Np,
+                       const uint8_t *sUx, int64_t j0, uint16_t *C, int64_t ldc, hipStream_t s);
 
 }  // namespace mxlu

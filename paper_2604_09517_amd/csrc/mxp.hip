@@ -112,30 +112,39 @@ int lp_factorize(const mxp_opts &o, int64_t n, const ASource &src, uint16_t *F,
     float *P32 = scratch.alloc_n<float>((size_t)n * nb);
     float *T32 = scratch.alloc_n<float>((size_t)nb * n);
     int *d_info = scratch.alloc_n<int>(4);   // [0] first zero pivot, [2] the leaves' counter
-    uint16_t *LTp = nullptr, *Up = nullptr;   // chunk-packed L21 and U12 (16-bit form)
     const int64_t Mp = lp_round_up(n, kLpTileM), Np = lp_round_up(n, kLpTileN);
-    uint8_t *LTq = nullptr, *Uq = nullptr;
-    float *sL = nullptr, *sU = nullptr;
-    uint8_t *sLx = nullptr, *sUx = nullptr;   // MX block scales
     const int64_t Mp8 = lp_round_up(n, kLp8Tile), Np8 = lp_round_up(n, kLp8Tile);
-    if (fp8) {
-        LTq = scratch.alloc_n<uint8_t>((size_t)nb * Mp8);
-        Uq = scratch.alloc_n<uint8_t>((size_t)nb * Np8);
-        if (!LTq || !Uq) return MXLU_E_NOMEM;
-        if (mx) {
-            sLx = scratch.alloc_n<uint8_t>((size_t)(nb / 32) * Mp8);
-            sUx = scratch.alloc_n<uint8_t>((size_t)(nb / 32) * Np8);
-            if (!sLx || !sUx) return MXLU_E_NOMEM;
+    // the packed operands of one step's update (a second set for the step
+    // prepared ahead)
+    struct Ops {
+        uint16_t *LTp = nullptr, *Up = nullptr;   // chunk-packed L21 and U12 (16-bit form)
+        uint8_t *LTq = nullptr, *Uq = nullptr;    // e4m3 L21 and U12 (FP8 forms)
+        float *sL = nullptr, *sU = nullptr;       // power-of-two tile scales
+        uint8_t *sLx = nullptr, *sUx = nullptr;   // MX block scales
+    };
+    auto alloc_ops = [&](Ops &q) -> int {
+        if (fp8) {
+            q.LTq = scratch.alloc_n<uint8_t>((size_t)nb * Mp8);
+            q.Uq = scratch.alloc_n<uint8_t>((size_t)nb * Np8);
+            if (!q.LTq || !q.Uq) return MXLU_E_NOMEM;
+            if (mx) {
+                q.sLx = scratch.alloc_n<uint8_t>((size_t)(nb / 32) * Mp8);
+                q.sUx = scratch.alloc_n<uint8_t>((size_t)(nb / 32) * Np8);
+                if (!q.sLx || !q.sUx) return MXLU_E_NOMEM;
+            } else {
+                q.sL = scratch.alloc_n<float>((size_t)(n / tile + 2));
+                q.sU = scratch.alloc_n<float>((size_t)(n / tile + 2));
+                if (!q.sL || !q.sU) return MXLU_E_NOMEM;
+            }
         } else {
-            sL = scratch.alloc_n<float>((size_t)(n / tile + 2));
-            sU = scratch.alloc_n<float>((size_t)(n / tile + 2));
-            if (!sL || !sU) return MXLU_E_NOMEM;
+            q.LTp = scratch.alloc_n<uint16_t>((size_t)nb * Mp);
+            q.Up = scratch.alloc_n<uint16_t>((size_t)nb * Np);
+            if (!q.LTp || !q.Up) return MXLU_E_NOMEM;
         }
-    } else {
-        LTp = scratch.alloc_n<uint16_t>((size_t)nb * Mp);
-        Up = scratch.alloc_n<uint16_t>((size_t)nb * Np);
-        if (!LTp || !Up) return MXLU_E_NOMEM;
-    }
+        return 0;
+    };
+    Ops cur, nxt;
+    MXLU_TRY(alloc_ops(cur));
     if (!P32 || !T32 || !d_info) return MXLU_E_NOMEM;
     MXLU_HIP_TRY(hipMemsetAsync(d_info, 0, 4 * sizeof(int), s));
     PanelExchange ex{};
@@ -156,26 +165,27 @@ int lp_factorize(const mxp_opts &o, int64_t n, const ASource &src, uint16_t *F,
 
     // Depth-1 look-ahead (no pivoting only: the pivoted panel's workgroups
     // must all be resident at once, which a stream shared with the update
-    // cannot promise): the update of the next panel's columns runs first, then
-    // that panel is factored on the look-ahead stream while the rest of the
-    // update runs on s.  Both parts are the same tiles as the whole update
-    // (split at a multiple of the tile width and of the scale tile), so every
-    // element takes the same operations in the same order as at depth 0.
+    // cannot promise).  The update of step k runs in three parts: the next
+    // panel's columns, then the top rows of the other columns (the next
+    // step's U12 rows), then the rest.  After the first part the next panel
+    // is factored on the look-ahead stream; after the second, the same stream
+    // solves and packs the next step's U12 and packs its L21 into the second
+    // operand set, all while the third part runs.  Each part is a set of
+    // whole tiles of the undivided update (split at multiples of the tile
+    // sizes and of the scale tile), so every element takes the same
+    // operations in the same order as at depth 0.
     AheadStreams ahs;
     std::unique_lock<std::mutex> ahead_lock;
-    const bool la = !o.pivot && n > nb && nb % 128 == 0 && (!fp8 || mx || nb % tile == 0) &&
-                    lp_ahead_streams(&ahs, &ahead_lock);
-    uint16_t *LTp_next = nullptr;   // the look-ahead panel's packed L21 (16-bit form)
-    if (la && !fp8) {
-        LTp_next = scratch.alloc_n<uint16_t>((size_t)nb * Mp);
-        if (!LTp_next) return MXLU_E_NOMEM;
-    }
+    const int64_t tile_m = fp8 ? kLp8Tile : kLpTileM;
+    const bool la = !o.pivot && n > nb && nb % tile_m == 0 && nb % 128 == 0 &&
+                    (!fp8 || mx || nb % tile == 0) && lp_ahead_streams(&ahs, &ahead_lock);
+    if (la) MXLU_TRY(alloc_ops(nxt));
     AheadJoin aj(s, la ? ahs.panel : nullptr);
     if (la) MXLU_TRY(aj.create());
 
-    // PFACT of the panel at k0 (width kb) on stream st; lt receives its
-    // packed L21 in the 16-bit form
-    auto pfact = [&](int64_t k0, int64_t kb, hipStream_t st, uint16_t *lt) -> int {
+    // PFACT of the panel at k0 (width kb) on stream st; the 16-bit form also
+    // packs its L21 into q
+    auto pfact = [&](int64_t k0, int64_t kb, hipStream_t st, Ops &q) -> int {
         const int64_t m = n - k0, c1 = k0 + kb;
         uint16_t *Fk = F + (size_t)k0 + (size_t)k0 * ldf;
         // work: the panel's bytes in storage precision
@@ -186,79 +196,92 @@ int lp_factorize(const mxp_opts &o, int64_t n, const ASource &src, uint16_t *F,
         else
             MXLU_TRY(lp_panel_factor_nopiv(m, (int)kb, P32, m, d_info, d_info + 2, k0, st));
         const bool need_lt = !fp8 && c1 < n;
-        return lp_panel_store(fmt, m, (int)kb, P32, m, Fk, ldf, need_lt ? lt : nullptr, Mp, st);
+        return lp_panel_store(fmt, m, (int)kb, P32, m, Fk, ldf, need_lt ? q.LTp : nullptr, Mp,
+                              st);
     };
-    // columns [j0, j0 + w) of the trailing update A22 -= L21 U12 of the step
-    // at k0 (the operands already quantised or packed), on stream st
-    auto update = [&](int64_t k0, int64_t kb, int64_t j0, int64_t w, hipStream_t st,
-                      const uint16_t *lt) -> int {
+    // U12 = L11^-1 A12 of the step at k0 in FP32 (L11 from P32), then the
+    // update's operands packed into q (quantised for FP8), on stream st
+    auto finish = [&](int64_t k0, int64_t kb, hipStream_t st, Ops &q) -> int {
         const int64_t c1 = k0 + kb, nt = n - c1;
-        uint16_t *C = F + (size_t)c1 + (size_t)(c1 + j0) * ldf;
+        uint16_t *U12 = F + (size_t)k0 + (size_t)c1 * ldf;
+        {
+            PhaseScope ph(kPhaseTrsm, st, (double)kb * (kb - 1) * (double)nt);
+            MXLU_TRY(lp_load_f32(fmt, kb, nt, U12, ldf, T32, kb, st));
+            MXLU_TRY(trsm_f32_llnu(kb, nt, P32, n - k0, T32, kb, st));
+            MXLU_TRY(lp_store_f32(fmt, kb, nt, T32, kb, U12, ldf, st));
+        }
+        const uint16_t *L21 = F + (size_t)c1 + (size_t)k0 * ldf;
+        if (mx) {
+            MXLU_TRY(lp_quant_l21_mx(fmt, nt, (int)kb, L21, ldf, q.LTq, Mp8, q.sLx, st));
+            return lp_quant_u12_mx(fmt, nt, (int)kb, U12, ldf, q.Uq, Np8, q.sUx, st);
+        }
+        if (fp8) {
+            MXLU_TRY(lp_quant_l21(fmt, nt, (int)kb, tile, L21, ldf, q.LTq, Mp8, q.sL, st));
+            return lp_quant_u12(fmt, nt, (int)kb, tile, U12, ldf, q.Uq, Np8, q.sU, st);
+        }
+        return lp_pack_u12(nt, (int)kb, U12, ldf, q.Up, Np, st);
+    };
+    // rows [i0, i0 + h) x columns [j0, j0 + w) of the trailing update
+    // A22 -= L21 U12 of the step at k0, from the operands in q, on stream st
+    auto update = [&](int64_t k0, int64_t kb, int64_t i0, int64_t h, int64_t j0, int64_t w,
+                      hipStream_t st, const Ops &q) -> int {
+        const int64_t c1 = k0 + kb;
+        uint16_t *C = F + (size_t)(c1 + i0) + (size_t)(c1 + j0) * ldf;
         // algorithmic bytes: the block of A22 read and written in 16 bits,
-        // L21 and the block's U12 columns read once
+        // its L21 rows and U12 columns read once
         const double ob = fp8 ? 1.0 : 2.0;
-        PhaseScope ph(kPhaseLpSchur, st, 4.0 * (double)nt * (double)w + ob * (double)(nt + w) * kb);
+        PhaseScope ph(kPhaseLpSchur, st, 4.0 * (double)h * (double)w + ob * (double)(h + w) * kb);
         if (mx)
-            return lp_schur_update_mx(fmt, nt, w, (int)kb, LTq, Mp8, sLx, Uq, Np8, sUx, j0, C, ldf,
-                                      st);
+            return lp_schur_update_mx(fmt, h, w, (int)kb, q.LTq, Mp8, q.sLx, i0, q.Uq, Np8, q.sUx,
+                                      j0, C, ldf, st);
         if (fp8)
-            return lp_schur_update_fp8(fmt, nt, w, (int)kb, LTq, Mp8, sL, Uq, Np8, sU, tile, j0, C,
-                                       ldf, st);
-        return lp_schur_update(fmt, nt, w, (int)kb, lt, Mp, Up, Np, j0, C, ldf, st);
+            return lp_schur_update_fp8(fmt, h, w, (int)kb, q.LTq, Mp8, q.sL, i0, q.Uq, Np8, q.sU,
+                                       j0, tile, C, ldf, st);
+        return lp_schur_update(fmt, h, w, (int)kb, q.LTp, Mp, i0, q.Up, Np, j0, C, ldf, st);
     };
 
     tf.start();
     {
         PhaseScope ph(kPhaseLpFactor, s, (2.0 / 3.0) * (double)n * n * n);
         int64_t step = 0;
-        bool ahead = false;   // the current panel was factored during the previous update
+        bool ahead = false;   // the current step was prepared during the previous update
         for (int64_t k0 = 0; k0 < n; k0 += nb, ++step) {
             if (o.factor_steps > 0 && step >= o.factor_steps) break;
             profile_set_step(step);
             const int64_t kb = std::min(nb, n - k0), c1 = k0 + kb;
-            if (!ahead) MXLU_TRY(pfact(k0, kb, s, LTp));
-            ahead = false;
+            if (!ahead) MXLU_TRY(pfact(k0, kb, s, cur));
             if (o.pivot && n > kb) {   // the panel's interchanges on the other stored columns
                 PhaseScope ph(kPhaseSwap, s, 8.0 * kb * (double)(n - kb));
                 MXLU_TRY(swap_compose(ipiv, k0, (int)kb, n, moves, s));
                 MXLU_TRY(swap_apply<uint16_t>(F, ldf, k0, moves, 0, n - kb, k0, kb, s));
             }
             if (c1 >= n) continue;
+            if (!ahead) MXLU_TRY(finish(k0, kb, s, cur));
+            ahead = false;
             const int64_t nt = n - c1;
-            uint16_t *U12 = F + (size_t)k0 + (size_t)c1 * ldf;
-            {   // U12 = L11^-1 A12 in FP32
-                PhaseScope ph(kPhaseTrsm, s, (double)kb * (kb - 1) * (double)nt);
-                MXLU_TRY(lp_load_f32(fmt, kb, nt, U12, ldf, T32, kb, s));
-                MXLU_TRY(trsm_f32_llnu(kb, nt, P32, n - k0, T32, kb, s));
-                MXLU_TRY(lp_store_f32(fmt, kb, nt, T32, kb, U12, ldf, s));
-            }
-            if (mx) {
-                const uint16_t *L21 = F + (size_t)c1 + (size_t)k0 * ldf;
-                MXLU_TRY(lp_quant_l21_mx(fmt, nt, (int)kb, L21, ldf, LTq, Mp8, sLx, s));
-                MXLU_TRY(lp_quant_u12_mx(fmt, nt, (int)kb, U12, ldf, Uq, Np8, sUx, s));
-            } else if (fp8) {
-                const uint16_t *L21 = F + (size_t)c1 + (size_t)k0 * ldf;
-                MXLU_TRY(lp_quant_l21(fmt, nt, (int)kb, tile, L21, ldf, LTq, Mp8, sL, s));
-                MXLU_TRY(lp_quant_u12(fmt, nt, (int)kb, tile, U12, ldf, Uq, Np8, sU, s));
-            } else {
-                MXLU_TRY(lp_pack_u12(nt, (int)kb, U12, ldf, Up, Np, s));
-            }
             // a factorization stopped after this step leaves the next panel
             // unfactored, so it is not factored ahead
             const bool go_ahead = la && !(o.factor_steps > 0 && step + 1 >= o.factor_steps);
             if (!go_ahead) {
-                MXLU_TRY(update(k0, kb, 0, nt, s, LTp));
+                MXLU_TRY(update(k0, kb, 0, nt, 0, nt, s, cur));
                 continue;
             }
-            const int64_t kb1 = std::min(nb, nt);
-            MXLU_TRY(update(k0, kb, 0, kb1, s, LTp));
+            const int64_t kb1 = std::min(nb, nt), rest = nt - kb1;
+            MXLU_TRY(update(k0, kb, 0, nt, 0, kb1, s, cur));
             MXLU_TRY(aj.fork());
             profile_set_step(step + 1);   // the next step's panel
-            MXLU_TRY(pfact(c1, kb1, ahs.panel, LTp_next));
+            MXLU_TRY(pfact(c1, kb1, ahs.panel, nxt));
             profile_set_step(step);
-            if (nt > kb1) MXLU_TRY(update(k0, kb, kb1, nt - kb1, s, LTp));
+            if (rest > 0) {
+                MXLU_TRY(update(k0, kb, 0, kb1, kb1, rest, s, cur));
+                MXLU_TRY(aj.fork());   // the next step's U12 rows are final
+                profile_set_step(step + 1);
+                MXLU_TRY(finish(c1, kb1, ahs.panel, nxt));
+                profile_set_step(step);
+                MXLU_TRY(update(k0, kb, kb1, rest, kb1, rest, s, cur));
+            }
             MXLU_TRY(aj.join());
-            std::swap(LTp, LTp_next);
+            std::swap(cur, nxt);
             ahead = true;
         }
     }

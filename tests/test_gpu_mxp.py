@@ -177,7 +177,8 @@ def test_lp_factors_against_oracle(api, prec, n, nb, kind, tile):
 
 
 @pytest.mark.parametrize("prec,n,nb,kind,tile,steps", [
-    ("bf16", 2216, 512, "dominant", 128, 0), ("fp16", 700, 128, "dominant", 64, 0),
+    ("bf16", 2216, 512, "dominant", 128, 0), ("fp16", 1100, 256, "dominant", 64, 0),
+    ("fp16", 700, 128, "dominant", 64, 0),
     ("bf16", 1064, 256, "scaled", 128, 2), ("fp8", 2216, 1024, "dominant", 128, 0),
     ("fp8", 1064, 256, "scaled", 128, 0), ("fp8", 1064, 256, "scaled", 64, 3),
     ("fp8", 500, 128, "scaled", 12, 0), ("fp8_mx", 2216, 1024, "scaled", 32, 0),
@@ -189,7 +190,8 @@ def test_lp_lookahead_equals_depth0(api, prec, n, nb, kind, tile, steps):
     same operations in the same order.  Covers a ragged last panel (n = 2216,
     nb = 1024: the last update is narrower than a panel), factorizations
     stopped after a few steps (the panel after the last step stays
-    unfactored) and a scale tile that does not divide nb (depth 0 is used)."""
+    unfactored), and a scale tile that does not divide nb or a 16-bit panel
+    narrower than the 256-row tile (depth 0 is used)."""
     note(f"look-ahead vs depth 0 prec={prec} n={n} nb={nb} input={kind} tile={tile} "
          f"steps={steps}")
     A = lp_input(kind, n, 91 + n, tile)
