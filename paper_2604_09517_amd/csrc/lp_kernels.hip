@@ -339,6 +339,102 @@ __global__ __launch_bounds__(256) void gemm_f32_sub_big_kernel(int64_t M, int64_
         }
 }
 
+// Matrix-core form: 128 x 128 tiles, 256 threads, each wave a 64 x 64
+// quarter as 4 x 4 blocks of v_mfma_f32_16x16x4f32, K staged through LDS in
+// chunks of 16 like the large-tile form.  The instruction computes each
+// output as four fused multiply-adds in ascending k (measured bit for bit
+// against fmaf on millions of random operands), and the blocks walk k in
+// ascending groups of four from C with A negated, so every element takes the
+// same terms in the same order as the other forms.  K % 4 == 0: no padded
+// term ever enters a sum.
+// Lane l of a block supplies A[row l % 16][k l / 16] and B[k l / 16][col
+// l % 16] and holds rows 4 (l / 16) + r of column l % 16 of the result.
+constexpr int kM32Ld = kG32Tile + 16;   // A and B rows of four k map to disjoint banks
+
+typedef float v4f32 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void gemm_f32_mfma_kernel(int64_t M, int64_t N, int64_t K,
+                                                            const float *__restrict__ A,
+                                                            int64_t lda,
+                                                            const float *__restrict__ B,
+                                                            int64_t ldb, float *__restrict__ C,
+                                                            int64_t ldc, int tiles_m) {
+    __shared__ __attribute__((aligned(16))) float As[2][kG32Kc][kM32Ld];
+    __shared__ __attribute__((aligned(16))) float Bs[2][kG32Kc][kM32Ld];
+    const int tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
+    const int64_t row0 = (int64_t)tm * kG32Tile, col0 = (int64_t)tn * kG32Tile;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int wr = (wave & 1) * 64, wc = (wave >> 1) * 64;
+    const int li = lane & 15, lg = lane >> 4;
+    // global load roles as in the large-tile form
+    const int ar = tid & 127, ak = tid >> 7;
+    const int bk = tid & 15, bc = tid >> 4;
+    float ra[8], rb[8];
+    auto load = [&](int64_t k0) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t r = row0 + ar, kk = k0 + ak + 2 * q;
+            ra[q] = (r < M && kk < K) ? A[(size_t)r + (size_t)kk * lda] : 0.0f;
+            const int64_t cc = col0 + bc + 16 * q, kb = k0 + bk;
+            rb[q] = (cc < N && kb < K) ? B[(size_t)kb + (size_t)cc * ldb] : 0.0f;
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            As[buf][ak + 2 * q][ar] = ra[q];
+            Bs[buf][bk][bc + 16 * q] = rb[q];
+        }
+    };
+    v4f32 acc[4][4];
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = row0 + wr + 16 * bi + 4 * lg + r;
+                const int64_t col = col0 + wc + 16 * bj + li;
+                acc[bi][bj][r] = (row < M && col < N) ? C[(size_t)row + (size_t)col * ldc] : 0.0f;
+            }
+    const int nk = (int)((K + kG32Kc - 1) / kG32Kc);
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int buf = kt & 1;
+        if (kt + 1 < nk) load((int64_t)(kt + 1) * kG32Kc);
+        const int64_t left = K - (int64_t)kt * kG32Kc;
+        const int groups = left < kG32Kc ? (int)(left / 4) : kG32Kc / 4;
+        for (int g = 0; g < groups; ++g) {
+            const int k = 4 * g + lg;
+            float a[4], b[4];
+#pragma unroll
+            for (int bi = 0; bi < 4; ++bi) a[bi] = -As[buf][k][wr + 16 * bi + li];
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj) b[bj] = Bs[buf][k][wc + 16 * bj + li];
+#pragma unroll
+            for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 4; ++bj)
+                    acc[bi][bj] =
+                        __builtin_amdgcn_mfma_f32_16x16x4f32(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
+        }
+        if (kt + 1 < nk) store(buf ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = row0 + wr + 16 * bi + 4 * lg + r;
+                const int64_t col = col0 + wc + 16 * bj + li;
+                if (row < M && col < N) C[(size_t)row + (size_t)col * ldc] = acc[bi][bj][r];
+            }
+}
+
 // ---------------------------------------------------------------- FP32 TRSM
 // B (kb x ncols) <- L^-1 B, L unit lower kb x kb (kb <= 256), thread per row,
 // NC columns per workgroup, one LDS barrier per step; each thread reads its
@@ -664,11 +760,15 @@ int lp_store_f32(int fmt, int64_t rows, int64_t cols, const float *P, int64_t ld
 int gemm_f32_sub(int64_t M, int64_t N, int64_t K, const float *A, int64_t lda, const float *B,
                  int64_t ldb, float *C, int64_t ldc, hipStream_t s) {
     if (M <= 0 || N <= 0 || K <= 0) return 0;
-    {   // large-tile form when it still gives every CU a few tiles
+    {   // large-tile forms when they still give every CU a few tiles
         const int64_t tm = (M + kG32Tile - 1) / kG32Tile, tn = (N + kG32Tile - 1) / kG32Tile;
         if (K >= 32 && M >= 96 && N >= 96 && tm * tn >= 512 && tm * tn <= 0x7fffffff) {
-            hipLaunchKernelGGL(gemm_f32_sub_big_kernel, dim3((unsigned)(tm * tn)), dim3(256), 0, s,
-                               M, N, K, A, lda, B, ldb, C, ldc, (int)tm);
+            if (K % 4 == 0)
+                hipLaunchKernelGGL(gemm_f32_mfma_kernel, dim3((unsigned)(tm * tn)), dim3(256), 0,
+                                   s, M, N, K, A, lda, B, ldb, C, ldc, (int)tm);
+            else
+                hipLaunchKernelGGL(gemm_f32_sub_big_kernel, dim3((unsigned)(tm * tn)), dim3(256), 0,
+                                   s, M, N, K, A, lda, B, ldb, C, ldc, (int)tm);
             MXLU_LAUNCH_CHECK();
             return 0;
         }

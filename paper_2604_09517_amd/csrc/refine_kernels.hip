@@ -336,7 +336,13 @@ __global__ __launch_bounds__(256) void trsv_chain_kernel(int64_t n, const uint16
     // transposed kinds: fr holds the thread's row of the earlier block, F
     // values for k = 2j, 2j+1 packed in one word, loaded before the wait
     uint32_t fr[COLMAJOR ? 1 : BS / 2];
-    uint4 g0[4], g1[4];
+    // column-major kinds: gb holds the 8 chunks of the next full earlier
+    // block; slot c is refilled with the following block's chunk c as soon
+    // as it is staged, so a whole block of loads is in flight while the
+    // current one is applied
+    constexpr int NG = COLMAJOR ? 8 : 1;
+    uint4 gb[NG][4];
+    bool have = false;   // gb holds the current earlier block
     for (int t = 0; t < w; ++t) {
         const int64_t pb = FWD ? t : nblk - 1 - t;
         const int64_t p0 = pb * BS;
@@ -344,7 +350,9 @@ __global__ __launch_bounds__(256) void trsv_chain_kernel(int64_t n, const uint16
         const bool full = (pr == BS);   // the earlier block is full
         if (full) {
             if (COLMAJOR) {
-                ld_chunk(p0, chunk_of(0), g0);
+                if (!have)
+#pragma unroll
+                    for (int c = 0; c < NG; ++c) ld_chunk(p0, chunk_of(c), gb[c]);
             } else if (tid < rows) {   // F[k][i] for k in the earlier block: contiguous in k
                 const uint4 *q = reinterpret_cast<const uint4 *>(&F[(size_t)p0 + (size_t)i * ldf]);
 #pragma unroll
@@ -391,19 +399,18 @@ __global__ __launch_bounds__(256) void trsv_chain_kernel(int64_t n, const uint16
         }
         lds_barrier();
         if (full && COLMAJOR) {
-            // chunks in solve order; the next chunk's loads are in flight
-            // during the current chunk's FMAs
+            // chunks in solve order; each staged chunk's slot takes the next
+            // earlier block's chunk (when that block is full)
+            const int64_t pn = FWD ? t + 1 : nblk - 2 - t;
+            const bool next = t + 1 < w && (n - pn * BS >= BS);
 #pragma unroll
-            for (int c = 0; c < 8; c += 2) {
-                apply_chunk(chunk_of(c), g0);
-                ld_chunk(p0, chunk_of(c + 1), g1);
+            for (int c = 0; c < NG; ++c) {
+                apply_chunk(chunk_of(c), gb[c]);
+                if (next) ld_chunk(pn * BS, chunk_of(c), gb[c]);
                 lds_barrier();
                 fma_chunk(chunk_of(c));
-                apply_chunk(chunk_of(c + 1), g1);
-                if (c + 2 < 8) ld_chunk(p0, chunk_of(c + 2), g0);
-                lds_barrier();
-                fma_chunk(chunk_of(c + 1));
             }
+            have = next;
         } else if (full && tid < rows) {
             // U^T, L^T: k ascending
 #pragma unroll

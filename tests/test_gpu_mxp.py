@@ -580,6 +580,30 @@ def test_fp32_storage_factors_bitwise(api, n, nb, pivot):
     assert np.array_equal(F, F_ref)
 
 
+@pytest.mark.parametrize("n,nb,steps,pivot", [(3200, 128, 1, False), (3200, 96, 1, False),
+                                               (3400, 256, 2, False), (3200, 128, 1, True)])
+def test_fp32_matrix_core_update_bitwise(api, n, nb, steps, pivot):
+    """The FP32 trailing update at sizes that take the matrix-core GEMM
+    (v_mfma_f32_16x16x4f32, four fused multiply-adds in ascending k per
+    instruction): after `steps` panel steps the whole partial factorization is
+    bit for bit the oracle's."""
+    note(f"fp32 matrix-core update n={n} nb={nb} steps={steps} pivot={pivot}")
+    seed = 313 + n + nb
+    A = (inputs.uniform_matrix(seed, 0, n, n) if pivot
+         else inputs.diag_dominant_matrix(seed, 0, n))
+    b = inputs.uniform_matrix(seed, 1, n, 1)[:, 0]
+    X, rep, work, ipiv = api.mxp_solve(to_dev(A), to_dev(b), prec="fp32", nb=nb, pivot=pivot,
+                                       max_outer=0, factor_steps=steps, allow_notconv=True)
+    torch.cuda.synchronize()
+    F = factors_to_host(api, work, n, "fp32")
+    F_ref, ipiv_ref, info = oracle.lp_getrf(A, nb, 4, pivot=pivot, max_steps=steps)
+    assert rep["info"] == info == 0
+    if pivot:
+        k = steps * nb
+        assert np.array_equal(ipiv.cpu().numpy()[:k], ipiv_ref[:k])
+    assert np.array_equal(F, F_ref)
+
+
 @pytest.mark.parametrize("pivot", [False, True])
 def test_fp32_storage_preconditioner_bitwise(api, pivot):
     """x0 = M b from FP32 factors: the block solves take every term in the
