@@ -307,6 +307,9 @@ def run_mxp(args, cfg, name, steps, warmup):
                      "kernel": f"lp_schur{'16' if prec == 'bf16' else '8'}_kernel "
                                f"(trailing update)",
                      "launches": scnt, "avg_launch_ms": round(sms / max(1, scnt), 4),
+                     "concurrent_with": "the look-ahead's next panel, U12 solve and operand "
+                                        "packing on a second stream (three update launches per "
+                                        "step; the third overlaps that work)",
                      "mfma_tflops": round(schur_flops * steps / (sms * 1e-3) / 1e12, 1)
                      if sms > 0 else None,
                      "mfma_peak_tflops": mma_peak},
