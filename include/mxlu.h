@@ -2,8 +2,9 @@
  * mxlu.h -- C ABI of the MI355X (gfx950) dense LU solver.
  *
  * The operations are those of the paper's benchmarks (Sec. III-A.1: solve
- * A x = b, A an N x N FP64 matrix, by LU factorization with partial pivoting
- * followed by triangular solves, computed by the right-looking blocked
+ * A x = b, A an N x N FP64 matrix: factor P A = L U with row interchanges
+ * chosen by the largest magnitude in each column, then solve with the two
+ * triangular factors; the factorization is the right-looking blocked
  * algorithm of panel width NB with the phases PFACT, SWAP, DTRSM, DGEMM;
  * Sec. III-A.2: the mixed-precision variant, low-precision factorization and
  * trailing updates without pivoting, accuracy restored by FP64 iterative
