@@ -342,17 +342,33 @@ __global__ __launch_bounds__(256) void trsv_chain_kernel(int64_t n, const uint16
     // current one is applied
     constexpr int NG = COLMAJOR ? 8 : 1;
     uint4 gb[NG][4];
+    uint32_t cr[NG][16];
     bool have = false;   // gb holds the current earlier block
     for (int t = 0; t < w; ++t) {
         const int64_t pb = FWD ? t : nblk - 1 - t;
         const int64_t p0 = pb * BS;
         const int pr = (int)((n - p0 < BS) ? n - p0 : BS);
         const bool full = (pr == BS);   // the earlier block is full
+        // the last earlier block is on the chain's critical path: its values
+        // move into registers (the thread's row, two values per word) while
+        // its solution is still awaited, so that only its multiply-adds follow
+        // the arrival
+        const bool last = COLMAJOR && full && t == w - 1;
         if (full) {
             if (COLMAJOR) {
                 if (!have)
 #pragma unroll
                     for (int c = 0; c < NG; ++c) ld_chunk(p0, chunk_of(c), gb[c]);
+                if (last) {
+#pragma unroll
+                    for (int c = 0; c < NG; ++c) {
+                        apply_chunk(chunk_of(c), gb[c]);
+                        lds_barrier();
+#pragma unroll
+                        for (int q = 0; q < 16; ++q)
+                            cr[c][q] = (uint32_t)stg[2 * q][tid] | ((uint32_t)stg[2 * q + 1][tid] << 16);
+                    }
+                }
             } else if (tid < rows) {   // F[k][i] for k in the earlier block: contiguous in k
                 const uint4 *q = reinterpret_cast<const uint4 *>(&F[(size_t)p0 + (size_t)i * ldf]);
 #pragma unroll
@@ -398,7 +414,25 @@ __global__ __launch_bounds__(256) void trsv_chain_kernel(int64_t n, const uint16
             xprev[tid] = __uint_as_float((uint32_t)x);
         }
         lds_barrier();
-        if (full && COLMAJOR) {
+        if (last) {
+            // the same terms in the same order as fma_chunk over the chunks
+#pragma unroll
+            for (int c = 0; c < NG; ++c) {
+                const int cc = chunk_of(c);
+                if (KIND == 0) {
+#pragma unroll
+                    for (int kk = 0; kk < 32; ++kk)
+                        acc = fmaf(-lp_to_f32<FMT>((uint16_t)(cr[c][kk >> 1] >> (16 * (kk & 1)))),
+                                   xprev[32 * cc + kk], acc);
+                } else {
+#pragma unroll
+                    for (int kk = 31; kk >= 0; --kk)
+                        acc = fmaf(-lp_to_f32<FMT>((uint16_t)(cr[c][kk >> 1] >> (16 * (kk & 1)))),
+                                   xprev[32 * cc + kk], acc);
+                }
+            }
+            have = false;
+        } else if (full && COLMAJOR) {
             // chunks in solve order; each staged chunk's slot takes the next
             // earlier block's chunk (when that block is full)
             const int64_t pn = FWD ? t + 1 : nblk - 2 - t;
@@ -455,6 +489,10 @@ __global__ __launch_bounds__(256) void trsv_chain_kernel(int64_t n, const uint16
 #pragma unroll
             for (int p = 0; p < 32; ++p)
                 rr[p] = *reinterpret_cast<const uint32_t *>(&Ld[tid][base + 2 * p]);
+            // every lane applies every step (the update of a lane already
+            // solved is never read again); each lane's finished value is kept
+            // aside at its own step, off the dependency chain
+            float xfin = x;
 #pragma unroll
             for (int j = 0; j < 64; ++j) {
                 const int kl = FWD ? j : 63 - j;
@@ -463,10 +501,10 @@ __global__ __launch_bounds__(256) void trsv_chain_kernel(int64_t n, const uint16
                 // on the owner lane lv is the diagonal entry
                 const float own = UNIT ? x : x / lv;
                 const float xk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(own), kl));
-                const float upd = fmaf(-lv, xk, x);
-                const bool later = FWD ? lane > kl : lane < kl;
-                x = (lane == kl) ? xk : (later ? upd : x);
+                xfin = (lane == kl) ? xk : xfin;
+                x = fmaf(-lv, xk, x);
             }
+            x = xfin;
             xprev[tid] = x;
         } else if (wave == sb && len > 0) {
             auto kat = [&](int j) { return FWD ? base + j : base + len - 1 - j; };
