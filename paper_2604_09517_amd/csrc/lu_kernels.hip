@@ -392,31 +392,45 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
 }
 
 // One right-hand side through a triangular diagonal block of order bb <= 256
-// (one workgroup): the block is solved 64 rows at a time; wave 0 holds the
-// 64 x 64 diagonal sub-block, one row per lane, in registers and solves it
-// with each finished value broadcast by readlane; then all threads apply the
-// sub-block's values to the rows still to be solved (one row per thread,
-// coalesced column loads).  LOWER: unit lower, forward; else upper with its
-// diagonal, backward.  y (bb values) is read once and written once.
+// (one workgroup of five waves): the block is solved 64 rows at a time; wave
+// 0 holds the 64 x 64 diagonal sub-block, one row per lane, in registers and
+// solves it with each finished value broadcast by readlane; waves 1-4 (one
+// thread per row) then apply the sub-block's values to the rows still to be
+// solved, their operands (coalesced column loads) having been loaded before
+// the sub-block was solved, so that they arrive meanwhile.  LOWER: unit
+// lower, forward; else upper with its diagonal, backward.  y (bb values) is
+// read once and written once.
+constexpr int kTrsvF64Threads = 320;
+
 template <bool LOWER>
-__global__ __launch_bounds__(256) void trsv_block_f64_kernel(int bb, const double *__restrict__ T,
-                                                             int64_t ldt, double *__restrict__ y) {
+__global__ __launch_bounds__(kTrsvF64Threads) void trsv_block_f64_kernel(
+    int bb, const double *__restrict__ T, int64_t ldt, double *__restrict__ y) {
     __shared__ double ys[256];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int u = tid - 64;   // the applying thread's index (waves 1-4)
     if (tid < bb) ys[tid] = y[tid];
     const int nsb = (bb + 63) / 64;
     for (int k = 0; k < nsb; ++k) {
-        const int sb = LOWER ? k : nsb - 1 - k;
-        const int c0 = 64 * sb;
+        const int c0 = 64 * (LOWER ? k : nsb - 1 - k);
+        const int jn = (bb - c0 < 64) ? bb - c0 : 64;
+        // rows still to solve: below the sub-block (LOWER) or above it
+        const int r = LOWER ? c0 + 64 + u : u;
+        const bool todo = wave > 0 && (LOWER ? (r < bb) : (r < c0));
+        // t: wave 0's row of the diagonal sub-block, or an applying thread's
+        // row in the sub-block's columns (both independent of the solution,
+        // so loaded before waiting for it)
+        const int rr = c0 + lane;
+        const bool ok = rr < bb;
+        const int lr = wave == 0 ? rr : r;
+        const bool lok = wave == 0 ? ok : todo;
+        double t[64];
+#pragma unroll
+        for (int j = 0; j < 64; ++j)
+            t[j] = (lok && j < jn) ? T[(size_t)lr + (size_t)(c0 + j) * ldt] : 0.0;
         __syncthreads();
         if (wave == 0) {
-            const int r = c0 + lane;
-            const bool ok = r < bb;
-            double a[64];
-#pragma unroll
-            for (int j = 0; j < 64; ++j)
-                a[j] = (ok && c0 + j < bb) ? T[(size_t)r + (size_t)(c0 + j) * ldt] : 0.0;
-            double x = ok ? ys[r] : 0.0;
+            const double *a = t;
+            double x = ok ? ys[rr] : 0.0;
             if (LOWER) {
 #pragma unroll
                 for (int j = 0; j < 64; ++j) {
@@ -431,19 +445,10 @@ __global__ __launch_bounds__(256) void trsv_block_f64_kernel(int bb, const doubl
                     if (lane < j) x = fma(-a[j], xj, x);
                 }
             }
-            if (ok) ys[r] = x;
+            if (ok) ys[rr] = x;
         }
         __syncthreads();
-        // rows still to solve: below the sub-block (LOWER) or above it
-        const int r = LOWER ? c0 + 64 + tid : tid;
-        const bool todo = LOWER ? (r < bb) : (r < c0);
         if (todo) {
-            // all 64 loads issued before the first use
-            const int jn = (bb - c0 < 64) ? bb - c0 : 64;
-            double t[64];
-#pragma unroll
-            for (int j = 0; j < 64; ++j)
-                t[j] = (j < jn) ? T[(size_t)r + (size_t)(c0 + j) * ldt] : 0.0;
             double acc = ys[r];
 #pragma unroll
             for (int j = 0; j < 64; ++j)
@@ -608,9 +613,11 @@ int trsv_block_f64(int bb, bool lower, const double *T, int64_t ldt, double *y, 
         return MXLU_E_NOMEM;
     }
     if (lower)
-        hipLaunchKernelGGL(trsv_block_f64_kernel<true>, dim3(1), dim3(256), 0, s, bb, T, ldt, y);
+        hipLaunchKernelGGL(trsv_block_f64_kernel<true>, dim3(1), dim3(kTrsvF64Threads), 0, s, bb,
+                           T, ldt, y);
     else
-        hipLaunchKernelGGL(trsv_block_f64_kernel<false>, dim3(1), dim3(256), 0, s, bb, T, ldt, y);
+        hipLaunchKernelGGL(trsv_block_f64_kernel<false>, dim3(1), dim3(kTrsvF64Threads), 0, s, bb,
+                           T, ldt, y);
     MXLU_LAUNCH_CHECK();
     return 0;
 }
