@@ -71,6 +71,89 @@ __global__ __launch_bounds__(256) void gemv_n_partial_kernel(int64_t n, ASource 
     if (asum_part) asum_part[(size_t)blockIdx.y * n + i] = as;
 }
 
+// The same for a stored A with even lda and 16-byte alignment: two adjacent
+// rows per thread (one 16-byte load per column covers both), each row's
+// terms still in ascending j, eight columns per iteration in flight.
+__global__ __launch_bounds__(256) void gemv_n_partial2_kernel(int64_t n, const double *__restrict__ A,
+                                                              int64_t lda,
+                                                              const double *__restrict__ x,
+                                                              int64_t cps, double *__restrict__ part,
+                                                              double *__restrict__ asum_part) {
+    const int64_t i = 2 * ((int64_t)blockIdx.x * 256 + threadIdx.x);
+    const int64_t j0 = (int64_t)blockIdx.y * cps;
+    const int64_t j1 = (j0 + cps < n) ? j0 + cps : n;
+    if (i >= n) return;
+    double acc0 = 0.0, acc1 = 0.0, as0 = 0.0, as1 = 0.0;
+    if (i + 1 < n) {
+        int64_t j = j0;
+        for (; j + 8 <= j1; j += 8) {
+            double2 a[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                a[q] = *reinterpret_cast<const double2 *>(&A[(size_t)i + (size_t)(j + q) * lda]);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const double xq = x[j + q];
+                acc0 = fma(a[q].x, xq, acc0);
+                acc1 = fma(a[q].y, xq, acc1);
+            }
+            if (asum_part) {
+                // the same grouping as the one-row form: four terms, then added
+#pragma unroll
+                for (int h = 0; h < 8; h += 4) {
+                    as0 += fabs(a[h].x) + fabs(a[h + 1].x) + fabs(a[h + 2].x) + fabs(a[h + 3].x);
+                    as1 += fabs(a[h].y) + fabs(a[h + 1].y) + fabs(a[h + 2].y) + fabs(a[h + 3].y);
+                }
+            }
+        }
+        for (; j + 4 <= j1; j += 4) {
+            double2 a[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                a[q] = *reinterpret_cast<const double2 *>(&A[(size_t)i + (size_t)(j + q) * lda]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double xq = x[j + q];
+                acc0 = fma(a[q].x, xq, acc0);
+                acc1 = fma(a[q].y, xq, acc1);
+            }
+            if (asum_part) {
+                as0 += fabs(a[0].x) + fabs(a[1].x) + fabs(a[2].x) + fabs(a[3].x);
+                as1 += fabs(a[0].y) + fabs(a[1].y) + fabs(a[2].y) + fabs(a[3].y);
+            }
+        }
+        for (; j < j1; ++j) {
+            const double2 a = *reinterpret_cast<const double2 *>(&A[(size_t)i + (size_t)j * lda]);
+            acc0 = fma(a.x, x[j], acc0);
+            acc1 = fma(a.y, x[j], acc1);
+            if (asum_part) {
+                as0 += fabs(a.x);
+                as1 += fabs(a.y);
+            }
+        }
+        part[(size_t)blockIdx.y * n + i + 1] = acc1;
+        if (asum_part) asum_part[(size_t)blockIdx.y * n + i + 1] = as1;
+    } else {   // the last row of an odd n
+        int64_t j = j0;
+        for (; j + 4 <= j1; j += 4) {
+            const double a0 = MXLU_AT(A, i, j, lda), a1 = MXLU_AT(A, i, j + 1, lda);
+            const double a2 = MXLU_AT(A, i, j + 2, lda), a3 = MXLU_AT(A, i, j + 3, lda);
+            acc0 = fma(a0, x[j], acc0);
+            acc0 = fma(a1, x[j + 1], acc0);
+            acc0 = fma(a2, x[j + 2], acc0);
+            acc0 = fma(a3, x[j + 3], acc0);
+            if (asum_part) as0 += fabs(a0) + fabs(a1) + fabs(a2) + fabs(a3);
+        }
+        for (; j < j1; ++j) {
+            const double a = MXLU_AT(A, i, j, lda);
+            acc0 = fma(a, x[j], acc0);
+            if (asum_part) as0 += fabs(a);
+        }
+    }
+    part[(size_t)blockIdx.y * n + i] = acc0;
+    if (asum_part) asum_part[(size_t)blockIdx.y * n + i] = as0;
+}
+
 // Transposed: part[s][i] = sum over rows j of split s of A[j, i] x[j]; one
 // wave per i (column i of A is contiguous).
 template <bool SEEDED>
@@ -623,7 +706,10 @@ int gemv_f64(int trans, int64_t n, const ASource &src, const double *x,
     if (n <= 0) return 0;
     const int64_t cps = (n + nsplit - 1) / nsplit;
     const dim3 gn(g1(n), (unsigned)nsplit), gt((unsigned)((n + 3) / 4), (unsigned)nsplit);
-    if (trans == 0 && !src.seeded())
+    if (trans == 0 && !src.seeded() && src.lda % 2 == 0 && (uintptr_t)src.A % 16 == 0)
+        hipLaunchKernelGGL(gemv_n_partial2_kernel, dim3((unsigned)((n + 511) / 512), (unsigned)nsplit),
+                           dim3(256), 0, s, n, src.A, src.lda, x, cps, part, asum_part);
+    else if (trans == 0 && !src.seeded())
         hipLaunchKernelGGL(gemv_n_partial_kernel<false>, gn, dim3(256), 0, s, n, src, x, cps, part,
                            asum_part);
     else if (trans == 0)
