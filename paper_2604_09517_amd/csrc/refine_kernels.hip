@@ -575,19 +575,61 @@ __global__ __launch_bounds__(256) void trsv_chain_kernel(int64_t n, const uint16
             // every lane applies every step (the update of a lane already
             // solved is never read again); each lane's finished value is kept
             // aside at its own step, off the dependency chain
-            float xfin = x;
+            //
+            // U (non-unit): the quotient x / d of a step comes from r = RN(1/d),
+            // the reciprocal of the lane's own diagonal entry computed ahead of
+            // the chain: q0 = RN(x r), q = RN(q0 + (x - q0 d) r) with both
+            // corrections fused multiply-adds.  While every value stays in the
+            // normal range that is the correctly rounded quotient (Markstein's
+            // theorem for a reciprocal rounded to nearest; also checked against
+            // the division on 4e8 operand pairs, quotients at rounding
+            // midpoints and divisors with all-ones significands included, and
+            // scale-invariant away from underflow and overflow).  Each lane
+            // keeps the value it divided; after the 64 steps one vote checks
+            // |x| >= 2^-100 (or x == 0), |q| within [2^-99, 2^99] and |d| within
+            // [2^-100, 2^100], and if any lane is outside, the sub-block is
+            // solved again with the division: the result is the division's bit
+            // for bit either way.
+            const float x_in = x;
+            const float dl = lp_to_f32<FMT>(Ld[tid][tid]);
+            const float rdiag = UNIT ? 1.0f : 1.0f / dl;
+            float xfin = x, xo = x;
 #pragma unroll
             for (int j = 0; j < 64; ++j) {
                 const int kl = FWD ? j : 63 - j;
                 const uint32_t w2 = rr[kl >> 1];
                 const float lv = lp_to_f32<FMT>((uint16_t)((kl & 1) ? (w2 >> 16) : w2));
                 // on the owner lane lv is the diagonal entry
-                const float own = UNIT ? x : x / lv;
+                float own = x;
+                if (!UNIT) {
+                    const float q0 = x * rdiag;
+                    own = fmaf(fmaf(-q0, lv, x), rdiag, q0);
+                    xo = (lane == kl) ? x : xo;
+                }
                 const float xk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(own), kl));
                 xfin = (lane == kl) ? xk : xfin;
                 x = fmaf(-lv, xk, x);
             }
             x = xfin;
+            if (!UNIT) {
+                const float ax = fabsf(xo), aq = fabsf(xfin), ad = fabsf(dl);
+                const bool in = (xo == 0.0f || (ax >= 0x1p-100f && aq >= 0x1p-99f && aq <= 0x1p99f)) &&
+                                ad >= 0x1p-100f && ad <= 0x1p100f;
+                if (!__all(in)) {   // wave-uniform; never taken on scaled inputs
+                    x = x_in;
+                    xfin = x;
+                    for (int j = 0; j < 64; ++j) {
+                        const int kl = FWD ? j : 63 - j;
+                        const float lv = lp_to_f32<FMT>(Ld[tid][base + kl]);
+                        const float own = x / lv;
+                        const float xk =
+                            __int_as_float(__builtin_amdgcn_readlane(__float_as_int(own), kl));
+                        xfin = (lane == kl) ? xk : xfin;
+                        x = fmaf(-lv, xk, x);
+                    }
+                    x = xfin;
+                }
+            }
             xprev[tid] = x;
         } else if (wave == sb && len > 0) {
             auto kat = [&](int j) { return FWD ? base + j : base + len - 1 - j; };

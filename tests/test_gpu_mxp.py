@@ -282,6 +282,31 @@ def test_preconditioner_bitwise_on_oracle_factors(api, prec, trans):
         assert np.abs(x0 - ref).max() <= 1e-5 * np.abs(ref).max()
 
 
+def test_preconditioner_bitwise_outside_the_reciprocal_range(api):
+    """The U solve's diagonal steps divide through a reciprocal only while
+    every value is in the normal range; with some diagonal entries of U scaled
+    by 2^110 (exact in BF16) the quotients of those rows fall below 2^-99, so
+    their 64-row sub-blocks are solved again with the division -- and the
+    preconditioner is still the oracle's bit for bit."""
+    n, nb = 600, 64
+    A = inputs.diag_dominant_matrix(78, 0, n)
+    b = inputs.uniform_matrix(78, 1, n, 1)[:, 0]
+    F_ref, _, _ = oracle.lp_getrf(A, nb, PREC_ID["bf16"], pivot=False)
+    F = F_ref.copy()
+    for k in (3, 64, 130, 200, 300, 450, 599):
+        F[k, k] *= 2.0 ** 110
+    dA, db = to_dev(A), to_dev(b)
+    opts = api.mxp_options(prec="bf16", nb=nb, max_outer=0, reuse_factors=True)
+    work = torch.zeros(api.mxp_workspace_bytes(n, opts, n), dtype=torch.uint8, device="cuda")
+    api.mxp_factors(work, n, "bf16").copy_(torch.from_numpy(F).to(torch.bfloat16))
+    X, rep, _, _ = api.mxp_solve(dA, db, work=work, opts=opts, allow_notconv=True)
+    torch.cuda.synchronize()
+    x0 = X.cpu().numpy()
+    ref = oracle.lp_precond(F, None, b)
+    assert np.all(np.isfinite(ref)) and np.abs(ref[[3, 130, 450]]).max() < 2.0 ** -99
+    assert np.array_equal(x0, ref)
+
+
 @pytest.mark.parametrize("prec,method,n,nb", [
     ("bf16", "gmres", 512, 128), ("bf16", "classical", 512, 128), ("fp16", "gmres", 777, 64),
     ("fp8", "gmres", 1024, 128), ("bf16", "gmres", 2048, 256), ("fp8", "classical", 640, 128),
