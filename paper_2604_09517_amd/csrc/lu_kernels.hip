@@ -339,41 +339,54 @@ __global__ __launch_bounds__(256) void perm_from_ipiv_kernel(int64_t n,
                                                              int32_t *__restrict__ perm,
                                                              int in_lds) {
     extern __shared__ int sperm[];
-    __shared__ int s_piv[256];
+    __shared__ __attribute__((aligned(16))) int s_piv[256];
     int *p = in_lds ? sperm : perm;
     const int tid = threadIdx.x;
     for (int64_t t = tid; t < n; t += 256) p[t] = (int)t;
     __syncthreads();
     for (int64_t j0 = 0; j0 < n; j0 += 256) {
         const int cnt = (int)((n - j0 < 256) ? n - j0 : 256);
-        if (tid < cnt) {
-            const int64_t q = (int64_t)ipiv[j0 + tid] - j0;
+        // entries past cnt are identity interchanges (no effect), so every
+        // loop below runs over all 256 entries, four per broadcast LDS read
+        {
+            const int64_t q = tid < cnt ? (int64_t)ipiv[j0 + tid] - j0 : (int64_t)tid;
             s_piv[tid] = (q >= tid && q < n - j0) ? (int)q : tid;
         }
         __syncthreads();
-        int d[2] = {-1, -1}, v[2] = {0, 0};
+        const int4 *piv4 = reinterpret_cast<const int4 *>(s_piv);
+        int d0 = -1, d1 = -1;
         if (tid < cnt) {
-            d[0] = tid;
+            d0 = tid;
             const int q = s_piv[tid];
-            if (q >= cnt) {
-                d[1] = q;
-                for (int u = 0; u < tid; ++u)
-                    if (s_piv[u] == q) {
-                        d[1] = -1;
-                        break;
-                    }
+            if (q >= cnt) {   // a pivot row below the block, followed where it first appears
+                bool first = true;
+                for (int u4 = 0; u4 < (tid + 3) / 4; ++u4) {
+                    const int4 w = piv4[u4];
+                    const int u = 4 * u4;
+                    first = first && !(u < tid && w.x == q) && !(u + 1 < tid && w.y == q) &&
+                            !(u + 2 < tid && w.z == q) && !(u + 3 < tid && w.w == q);
+                }
+                if (first) d1 = q;
             }
         }
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            if (d[e] < 0) continue;
-            int src = d[e];
-            for (int u = cnt - 1; u >= 0; --u) {
-                const int q = s_piv[u];
-                src = (src == u) ? q : ((src == q) ? u : src);
-            }
-            v[e] = p[j0 + src];
+        // both candidate rows traced back through the block's interchanges,
+        // last to first, side by side
+        int src0 = d0 < 0 ? 0 : d0, src1 = d1 < 0 ? 0 : d1;
+        for (int u4 = 63; u4 >= 0; --u4) {
+            const int4 w = piv4[u4];
+            const int u = 4 * u4;
+            src0 = (src0 == u + 3) ? w.w : ((src0 == w.w) ? u + 3 : src0);
+            src1 = (src1 == u + 3) ? w.w : ((src1 == w.w) ? u + 3 : src1);
+            src0 = (src0 == u + 2) ? w.z : ((src0 == w.z) ? u + 2 : src0);
+            src1 = (src1 == u + 2) ? w.z : ((src1 == w.z) ? u + 2 : src1);
+            src0 = (src0 == u + 1) ? w.y : ((src0 == w.y) ? u + 1 : src0);
+            src1 = (src1 == u + 1) ? w.y : ((src1 == w.y) ? u + 1 : src1);
+            src0 = (src0 == u) ? w.x : ((src0 == w.x) ? u : src0);
+            src1 = (src1 == u) ? w.x : ((src1 == w.x) ? u : src1);
         }
+        int d[2] = {d0, d1}, v[2] = {0, 0};
+        if (d0 >= 0) v[0] = p[j0 + src0];
+        if (d1 >= 0) v[1] = p[j0 + src1];
         __syncthreads();   // every source read before any move is written
 #pragma unroll
         for (int e = 0; e < 2; ++e)
