@@ -372,6 +372,7 @@ __global__ __launch_bounds__(256) void perm_from_ipiv_kernel(int64_t n,
         // both candidate rows traced back through the block's interchanges,
         // last to first, side by side
         int src0 = d0 < 0 ? 0 : d0, src1 = d1 < 0 ? 0 : d1;
+#pragma unroll 8
         for (int u4 = 63; u4 >= 0; --u4) {
             const int4 w = piv4[u4];
             const int u = 4 * u4;
