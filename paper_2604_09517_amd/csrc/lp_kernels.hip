@@ -45,6 +45,30 @@ __global__ void convert_kernel(int64_t rows, int64_t cols, const double *__restr
         F[(size_t)i + (size_t)j * (size_t)ldf] = f64_to_lp<FMT>(MXLU_AT(A, i, j, lda));
 }
 
+// The same with four adjacent rows per thread (two 16-byte loads of A, one
+// 8-byte store of F) when lda is even, A 16-byte aligned, ldf a multiple of
+// four and F 8-byte aligned; each element is rounded exactly as above.
+template <int FMT>
+__global__ void convert4_kernel(int64_t rows, int64_t cols, const double *__restrict__ A,
+                                int64_t lda, uint16_t *__restrict__ F, int64_t ldf) {
+    const int64_t i = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= rows) return;
+    for (int64_t j = blockIdx.y; j < cols; j += gridDim.y) {
+        const double *a = &A[(size_t)i + (size_t)j * (size_t)lda];
+        uint16_t *f = &F[(size_t)i + (size_t)j * (size_t)ldf];
+        if (i + 4 <= rows) {
+            const double2 a01 = *reinterpret_cast<const double2 *>(a);
+            const double2 a23 = *reinterpret_cast<const double2 *>(a + 2);
+            uint2 w;
+            w.x = (uint32_t)f64_to_lp<FMT>(a01.x) | ((uint32_t)f64_to_lp<FMT>(a01.y) << 16);
+            w.y = (uint32_t)f64_to_lp<FMT>(a23.x) | ((uint32_t)f64_to_lp<FMT>(a23.y) << 16);
+            *reinterpret_cast<uint2 *>(f) = w;
+        } else {
+            for (int64_t r = 0; i + r < rows; ++r) f[r] = f64_to_lp<FMT>(a[r]);
+        }
+    }
+}
+
 // The same rounding from the seeded generator's values (the FP64 matrix is
 // never stored): F[i, j] <- round(a_ij).
 template <int FMT>
@@ -700,12 +724,21 @@ namespace mxlu {
 int lp_convert(int fmt, int64_t rows, int64_t cols, const double *A, int64_t lda, uint16_t *F,
                int64_t ldf, hipStream_t s) {
     if (rows <= 0 || cols <= 0) return 0;
-    if (fmt == kFmtBf16)
+    if (lda % 2 == 0 && (uintptr_t)A % 16 == 0 && ldf % 4 == 0 && (uintptr_t)F % 8 == 0) {
+        const dim3 g((unsigned)((rows + 1023) / 1024), grid2(rows, cols).y);
+        if (fmt == kFmtBf16)
+            hipLaunchKernelGGL(convert4_kernel<kFmtBf16>, g, dim3(256), 0, s, rows, cols, A, lda, F,
+                               ldf);
+        else
+            hipLaunchKernelGGL(convert4_kernel<kFmtFp16>, g, dim3(256), 0, s, rows, cols, A, lda, F,
+                               ldf);
+    } else if (fmt == kFmtBf16) {
         hipLaunchKernelGGL(convert_kernel<kFmtBf16>, grid2(rows, cols), dim3(256), 0, s, rows, cols,
                            A, lda, F, ldf);
-    else
+    } else {
         hipLaunchKernelGGL(convert_kernel<kFmtFp16>, grid2(rows, cols), dim3(256), 0, s, rows, cols,
                            A, lda, F, ldf);
+    }
     MXLU_LAUNCH_CHECK();
     return 0;
 }
