@@ -578,14 +578,37 @@ __global__ __launch_bounds__(256) void quant_l21_kernel(int64_t mt, int kb, int 
                                                         int64_t ldf, uint8_t *__restrict__ LTq,
                                                         int64_t Mp, float *__restrict__ sL) {
     __shared__ float red[256];
-    __shared__ uint8_t T[64][256 + 4];
+    __shared__ __attribute__((aligned(16))) uint8_t T[64][256 + 8];
     const int64_t r0 = (int64_t)blockIdx.x * tile;
     const int rows = (int)((mt - r0 < tile) ? mt - r0 : tile);
     const int tid = threadIdx.x;
+    // 16-byte form: rows in groups of 8 (one 16-byte load each), all 256
+    // threads busy (groups x columns in parallel), four bytes per store of
+    // the packed copy; the general form otherwise.  Both round every element
+    // the same way, and the maximum does not depend on the order.
+    const bool wide = rows % 8 == 0 && ldf % 8 == 0 &&
+                      ((uintptr_t)(L21 + r0) & 15) == 0;
+    const int rows8 = rows / 8;
+    const int cpar = wide ? 256 / rows8 : 0;
+    const int g8 = wide ? tid % rows8 : 0, cl = wide ? tid / rows8 : 0;
     float amax = 0.0f;
-    for (int c = 0; c < kb; ++c)
-        for (int i = tid; i < rows; i += 256)
-            amax = fmaxf(amax, fabsf(lp_to_f32<FMT>(L21[(size_t)(r0 + i) + (size_t)c * ldf])));
+    if (wide) {
+        if (cl < cpar)
+            for (int c = cl; c < kb; c += cpar) {
+                const uint4 v = *reinterpret_cast<const uint4 *>(
+                    L21 + (size_t)(r0 + 8 * g8) + (size_t)c * ldf);
+                const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    amax = fmaxf(amax, fabsf(lp_to_f32<FMT>((uint16_t)(w[q] & 0xffffu))));
+                    amax = fmaxf(amax, fabsf(lp_to_f32<FMT>((uint16_t)(w[q] >> 16))));
+                }
+            }
+    } else {
+        for (int c = 0; c < kb; ++c)
+            for (int i = tid; i < rows; i += 256)
+                amax = fmaxf(amax, fabsf(lp_to_f32<FMT>(L21[(size_t)(r0 + i) + (size_t)c * ldf])));
+    }
     red[tid] = amax;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
@@ -598,15 +621,47 @@ __global__ __launch_bounds__(256) void quant_l21_kernel(int64_t mt, int kb, int 
     for (int c0 = 0; c0 < kb; c0 += 64) {
         const int cw = (kb - c0 < 64) ? kb - c0 : 64;
         __syncthreads();
-        for (int t = tid; t < cw * rows; t += 256) {
-            const int i = t % rows, j = t / rows;
-            T[j][i] = f32_to_e4m3(lp_to_f32<FMT>(L21[(size_t)(r0 + i) + (size_t)(c0 + j) * ldf]) * inv);
+        if (wide) {
+            for (int j = cl; j < cw; j += cpar) {
+                if (cl >= cpar) break;
+                const uint4 v = *reinterpret_cast<const uint4 *>(
+                    L21 + (size_t)(r0 + 8 * g8) + (size_t)(c0 + j) * ldf);
+                const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+                uint32_t lo = 0, hi = 0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t b0 = f32_to_e4m3(lp_to_f32<FMT>((uint16_t)(w[q] & 0xffffu)) * inv);
+                    const uint32_t b1 = f32_to_e4m3(lp_to_f32<FMT>((uint16_t)(w[q] >> 16)) * inv);
+                    const uint32_t pair = b0 | (b1 << 8);
+                    if (q < 2) lo |= pair << (16 * q);
+                    else hi |= pair << (16 * (q - 2));
+                }
+                *reinterpret_cast<uint2 *>(&T[j][8 * g8]) = make_uint2(lo, hi);
+            }
+        } else {
+            for (int t = tid; t < cw * rows; t += 256) {
+                const int i = t % rows, j = t / rows;
+                T[j][i] = f32_to_e4m3(lp_to_f32<FMT>(L21[(size_t)(r0 + i) + (size_t)(c0 + j) * ldf]) * inv);
+            }
         }
         __syncthreads();
-        for (int t = tid; t < cw * rows; t += 256) {
-            const int j = t % cw, i = t / cw;
-            const int k = c0 + j;
-            LTq[((size_t)(k / kLp8Kc) * Mp + (size_t)(r0 + i)) * kLp8Kc + (k % kLp8Kc)] = T[j][i];
+        if (wide && cw % 4 == 0) {
+            const int cw4 = cw / 4;
+            for (int t = tid; t < cw4 * rows; t += 256) {
+                const int jq = t % cw4, i = t / cw4;
+                const int k = c0 + 4 * jq;
+                const uint32_t w = (uint32_t)T[4 * jq][i] | ((uint32_t)T[4 * jq + 1][i] << 8) |
+                                   ((uint32_t)T[4 * jq + 2][i] << 16) |
+                                   ((uint32_t)T[4 * jq + 3][i] << 24);
+                *reinterpret_cast<uint32_t *>(
+                    &LTq[((size_t)(k / kLp8Kc) * Mp + (size_t)(r0 + i)) * kLp8Kc + (k % kLp8Kc)]) = w;
+            }
+        } else {
+            for (int t = tid; t < cw * rows; t += 256) {
+                const int j = t % cw, i = t / cw;
+                const int k = c0 + j;
+                LTq[((size_t)(k / kLp8Kc) * Mp + (size_t)(r0 + i)) * kLp8Kc + (k % kLp8Kc)] = T[j][i];
+            }
         }
     }
 }
