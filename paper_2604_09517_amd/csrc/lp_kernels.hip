@@ -677,10 +677,29 @@ __global__ __launch_bounds__(256) void quant_u12_kernel(int64_t nt, int kb, int 
     const int64_t q0 = (int64_t)blockIdx.x * tile;
     const int cols = (int)((nt - q0 < tile) ? nt - q0 : tile);
     const int tid = threadIdx.x;
+    // 16-byte form (eight consecutive k per load, eight bytes per store) when
+    // the columns are 16-byte aligned; each element is quantised as in the
+    // general form, and the maximum does not depend on the order
+    const bool wide = kb % 8 == 0 && ldf % 8 == 0 && ((uintptr_t)U12 & 15) == 0;
+    const int kb8 = kb / 8;
     float amax = 0.0f;
-    for (int j = 0; j < cols; ++j)
-        for (int k = tid; k < kb; k += 256)
-            amax = fmaxf(amax, fabsf(lp_to_f32<FMT>(U12[(size_t)k + (size_t)(q0 + j) * ldf])));
+    if (wide) {
+        for (int t = tid; t < cols * kb8; t += 256) {
+            const int j = t / kb8, k = 8 * (t % kb8);
+            const uint4 v =
+                *reinterpret_cast<const uint4 *>(U12 + (size_t)k + (size_t)(q0 + j) * ldf);
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                amax = fmaxf(amax, fabsf(lp_to_f32<FMT>((uint16_t)(w[q] & 0xffffu))));
+                amax = fmaxf(amax, fabsf(lp_to_f32<FMT>((uint16_t)(w[q] >> 16))));
+            }
+        }
+    } else {
+        for (int j = 0; j < cols; ++j)
+            for (int k = tid; k < kb; k += 256)
+                amax = fmaxf(amax, fabsf(lp_to_f32<FMT>(U12[(size_t)k + (size_t)(q0 + j) * ldf])));
+    }
     red[tid] = amax;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
@@ -690,10 +709,31 @@ __global__ __launch_bounds__(256) void quant_u12_kernel(int64_t nt, int kb, int 
     const float sc = fp8_tile_scale(red[0]);
     if (tid == 0) sU[blockIdx.x] = sc;
     const float inv = 1.0f / sc;
-    for (int j = 0; j < cols; ++j)
-        for (int k = tid; k < kb; k += 256)
-            Uq[((size_t)(k / kLp8Kc) * Np + (size_t)(q0 + j)) * kLp8Kc + (k % kLp8Kc)] =
-                f32_to_e4m3(lp_to_f32<FMT>(U12[(size_t)k + (size_t)(q0 + j) * ldf]) * inv);
+    if (wide) {
+        for (int t = tid; t < cols * kb8; t += 256) {
+            const int j = t / kb8, k = 8 * (t % kb8);
+            const uint4 v =
+                *reinterpret_cast<const uint4 *>(U12 + (size_t)k + (size_t)(q0 + j) * ldf);
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+            uint32_t lo = 0, hi = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t b0 = f32_to_e4m3(lp_to_f32<FMT>((uint16_t)(w[q] & 0xffffu)) * inv);
+                const uint32_t b1 = f32_to_e4m3(lp_to_f32<FMT>((uint16_t)(w[q] >> 16)) * inv);
+                const uint32_t pair = b0 | (b1 << 8);
+                if (q < 2) lo |= pair << (16 * q);
+                else hi |= pair << (16 * (q - 2));
+            }
+            *reinterpret_cast<uint2 *>(
+                &Uq[((size_t)(k / kLp8Kc) * Np + (size_t)(q0 + j)) * kLp8Kc + (k % kLp8Kc)]) =
+                make_uint2(lo, hi);
+        }
+    } else {
+        for (int j = 0; j < cols; ++j)
+            for (int k = tid; k < kb; k += 256)
+                Uq[((size_t)(k / kLp8Kc) * Np + (size_t)(q0 + j)) * kLp8Kc + (k % kLp8Kc)] =
+                    f32_to_e4m3(lp_to_f32<FMT>(U12[(size_t)k + (size_t)(q0 + j) * ldf]) * inv);
+    }
 }
 
 // MX form: L21 row i, block b of 32 consecutive k -> 32 e4m3 bytes at their
